@@ -1,0 +1,165 @@
+/*
+ * fcsph.h - C ABI of the MI355X (gfx950) FC(Gram)-based spectral ISPH step.
+ *
+ * The library implements the data-parallel hot path of the FC-based spectral
+ * incompressible SPH scheme (Lin, Fourtakas & Rogers): Fourier continuation of
+ * non-periodic fields across walls, kernel-weighted SPH gradient / divergence /
+ * Laplacian evaluated in frequency space through the convolution theorem, a
+ * spectral pressure-Poisson solve, and the first-order projection update.
+ * Every stage runs in hand-written HIP kernels on the device.
+ *
+ * Conventions for every call
+ *  - Field arrays are DEVICE pointers, contiguous, row-major with x fastest:
+ *    2D [ny][nx], 3D [nz][ny][nx].  Physical arrays have exactly the physical
+ *    shape; the output of fcsph_fc_extend has n+C points on each walled axis.
+ *  - State arrays (velocity, pressure, forcing, wall data) are FP64.
+ *    Derivative outputs and the PPE right-hand side are double in FCSPH_FP64
+ *    plans and float in FCSPH_FP32_MIXED plans.
+ *  - The caller owns every buffer, including the plan workspace; the library
+ *    never allocates device memory.  A plan keeps pointers into its
+ *    workspace, which must outlive the plan.
+ *  - Calls are asynchronous on the context's HIP stream.  Argument errors are
+ *    detected synchronously and returned as status codes; device faults
+ *    surface as FCSPH_E_HIP at the next call or at fcsph_ctx_sync.  No call
+ *    aborts or throws across the ABI.
+ *  - A plan is immutable after creation.  Calls on one context must not run
+ *    concurrently from several host threads.
+ */
+#ifndef FCSPH_H
+#define FCSPH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FCSPH_OK = 0,
+  FCSPH_E_INVALID = -1,      /* bad argument (null pointer, shape, value)          */
+  FCSPH_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. a BC combination) */
+  FCSPH_E_WORKSPACE = -3,    /* workspace too small or misaligned                  */
+  FCSPH_E_HIP = -4,          /* HIP runtime error (launch failure, device fault)   */
+  FCSPH_E_NONFINITE = -5     /* reserved: non-finite values detected               */
+} fcsph_status;
+
+typedef enum { FCSPH_AXIS_PERIODIC = 0, FCSPH_AXIS_WALLED = 1 } fcsph_axis_kind;
+typedef enum { FCSPH_BC_DIRICHLET = 0, FCSPH_BC_NEUMANN = 1 } fcsph_bc;
+typedef enum { FCSPH_FIELD_VELOCITY = 0, FCSPH_FIELD_PRESSURE = 1 } fcsph_field_class;
+typedef enum { FCSPH_FP64 = 0, FCSPH_FP32_MIXED = 1 } fcsph_precision;
+typedef enum { FCSPH_PPE_PHYSICAL = 0, FCSPH_PPE_EXTENDED = 1 } fcsph_ppe_domain;
+typedef enum { FCSPH_EIG_SPECTRAL = 0, FCSPH_EIG_FD2 = 1, FCSPH_EIG_SPH = 2 } fcsph_eig;
+typedef enum { FCSPH_KERNEL_WENDLAND_C2 = 0 } fcsph_kernel;
+
+/*
+ * Problem descriptor.  Axes are indexed 0 = x, 1 = y, 2 = z.
+ *  n[a]        physical points on axis a (n[2] ignored in 2D)
+ *  dx          isotropic lattice spacing; a walled axis spans [0, (n-1) dx]
+ *              with both walls on lattice points, a periodic axis has period
+ *              n dx
+ *  axis[a]     fcsph_axis_kind
+ *  vel_bc, prs_bc [a][0|1]  wall types (fcsph_bc) of the low / high wall of a
+ *              walled axis, for the velocity and the pressure field classes
+ *              (wall conditions: eqs. BC_velocity and BC_pressure)
+ *  fc_d, fc_C  FC(Gram) matching / continuation points (5 and 25)
+ *  fc_M_dir, fc_M_neu  HOST pointers to the C x d row-major FP64 continuation
+ *              maps of a Dirichlet / Neumann wall; copied at plan creation
+ *  kernel, h_over_dx   SPH kernel and smoothing length h / dx
+ *  prec        fcsph_precision;  ppe_domain  fcsph_ppe_domain;  eig  fcsph_eig
+ *  rho         fluid density
+ */
+typedef struct {
+  int ndim;
+  int n[3];
+  double dx;
+  int axis[3];
+  int vel_bc[3][2];
+  int prs_bc[3][2];
+  int fc_d, fc_C;
+  const double *fc_M_dir;
+  const double *fc_M_neu;
+  int kernel;
+  double h_over_dx;
+  int prec;
+  int ppe_domain;
+  int eig;
+  double rho;
+} fcsph_desc;
+
+typedef struct fcsph_ctx fcsph_ctx;
+typedef struct fcsph_plan fcsph_plan;
+
+/* Context: binds a device and a HIP stream (NULL = the default stream).
+ * Returns FCSPH_E_INVALID for a bad device index. */
+fcsph_status fcsph_ctx_create(int device, void *hip_stream, fcsph_ctx **out);
+fcsph_status fcsph_ctx_destroy(fcsph_ctx *c);
+/* Waits for all work on the context stream; reports device faults as FCSPH_E_HIP. */
+fcsph_status fcsph_ctx_sync(fcsph_ctx *c);
+const char *fcsph_status_string(fcsph_status s);
+/* Text of the last error on this context (never NULL). */
+const char *fcsph_ctx_last_error(fcsph_ctx *c);
+
+/* Bytes of device workspace a plan for *d needs (tables + scratch); the
+ * workspace must be 256-byte aligned. */
+fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes);
+/* Builds a plan: validates *d, computes every table on the host and copies
+ * it into the workspace on the context stream.  Validation: ndim 2 or 3;
+ * walled axes need n >= 2 fc_d; the kernel support 2h must be below half of
+ * every extended period; FCSPH_E_UNSUPPORTED for combinations not built. */
+fcsph_status fcsph_plan_create(fcsph_ctx *c, const fcsph_desc *d, void *workspace,
+                               size_t bytes, fcsph_plan **out);
+fcsph_status fcsph_plan_destroy(fcsph_plan *p);
+
+/*
+ * FC(Gram) extension (FC section, eq. eq:fc_extended and its 2D form
+ * eq. eq:fc_2d; FC(Gram) paragraph).  On every walled axis each line
+ * f_0..f_{n-1} is extended by C values
+ *     e[n-1+i] = (M_hi f_hi)[i] + (M_lo f_lo_rev)[C+1-i],   i = 1..C,
+ * with f_hi = (f_{n-d}..f_{n-1}), f_lo_rev = (f_{d-1}..f_0) and the map of each
+ * wall's type for field class fc; axes are applied in order x, y, z to every
+ * line of the current array.  f: physical FP64 array; f_ext: FP64 array of
+ * the extended shape.  Physical values are copied bitwise.
+ */
+fcsph_status fcsph_fc_extend(fcsph_plan *p, int fc, const double *f, double *f_ext);
+
+/*
+ * Spectral SPH gradient (eq. final_dft_gradient evaluated as the circular
+ * convolution of eq. circularConv on the FC-extended periodic lattice):
+ *     g_a = restrict( IDFT( DFT(FC(f)) * DFT(dV d_a W sampled, corner-wrapped) ) )
+ * f: physical FP64 array; g[a] (a < ndim): physical arrays of the plan's
+ * output type.  fc selects the velocity or pressure wall maps.
+ */
+fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *const *g);
+/* Spectral SPH divergence sum_a G_a u_a of a velocity (velocity wall maps). */
+fcsph_status fcsph_spectral_div(fcsph_plan *p, const double *const *u, void *div);
+/* Spectral SPH Laplacian: f convolved with dV lap W (kernel Laplacian). */
+fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *lap);
+
+/*
+ * Spectral PPE on the physical lattice (pressure section, eqs. DCTI4PPE,
+ * DCTDFT_PPE and division4PPE): per axis a DFT (periodic), DCT-I (Neumann
+ * walls), DST-I (Dirichlet walls) or a quarter-wave transform (mixed walls);
+ * phi_hat = -rhs_hat / sum_a mu_a with the plan's eigenvalue family, in FP64;
+ * a vanishing eigenvalue sum (the constant mode) gives phi_hat = 0.
+ * rhs: physical array of the plan's output type; phi: physical FP64 array,
+ * 0 on Dirichlet pressure walls.
+ */
+fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi);
+
+/*
+ * One first-order projection step (eqs. uStarRK3 and rhsMomtem with
+ * a = g = 1, z = 0; eqs. PPE and u^n+1):
+ *   u*  = u - dt [ (u . grad) u - nu lap u - force ],  Dirichlet walls <- wall_vel
+ *   lap phi = (rho/dt) div u*,   u <- u* - (dt/rho) grad phi,  walls <- wall_vel
+ * u[a]: FP64 velocity components, updated in place; p_out: FP64 pressure phi
+ * (may be NULL); force[a], wall_vel[a]: FP64 arrays or NULL (zero).  Only the
+ * Dirichlet wall entries of wall_vel are read.
+ */
+fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out,
+                                const double *const *force, const double *const *wall_vel,
+                                double dt, double nu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCSPH_H */

@@ -1,0 +1,304 @@
+"""Python binding of ``libfcsph.so`` (ctypes; argument marshalling only).
+
+Every computation runs in the library's HIP kernels.  torch supplies device
+memory (tensors, the plan workspace) and the HIP stream.  The names mirror the
+C ABI in ``include/fcsph.h``: fc_extend, spectral_grad, spectral_div,
+spectral_lap, ppe_solve, project_step.
+
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fctables
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfcsph.so")
+
+OK, E_INVALID, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_NONFINITE = 0, -1, -2, -3, -4, -5
+PERIODIC, WALLED = 0, 1
+DIRICHLET, NEUMANN = 0, 1
+VELOCITY, PRESSURE = 0, 1
+FP64, FP32_MIXED = 0, 1
+PPE_PHYSICAL, PPE_EXTENDED = 0, 1
+EIG_SPECTRAL, EIG_FD2, EIG_SPH = 0, 1, 2
+KERNEL_WENDLAND_C2 = 0
+
+EXPORTS = [
+    "fcsph_ctx_create", "fcsph_ctx_destroy", "fcsph_ctx_sync", "fcsph_status_string",
+    "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
+    "fcsph_plan_destroy", "fcsph_fc_extend", "fcsph_spectral_grad", "fcsph_spectral_div",
+    "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step",
+]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double),
+        ("axis", ctypes.c_int * 3), ("vel_bc", (ctypes.c_int * 2) * 3),
+        ("prs_bc", (ctypes.c_int * 2) * 3), ("fc_d", ctypes.c_int), ("fc_C", ctypes.c_int),
+        ("fc_M_dir", ctypes.POINTER(ctypes.c_double)), ("fc_M_neu", ctypes.POINTER(ctypes.c_double)),
+        ("kernel", ctypes.c_int), ("h_over_dx", ctypes.c_double), ("prec", ctypes.c_int),
+        ("ppe_domain", ctypes.c_int), ("eig", ctypes.c_int), ("rho", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2606_06247_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    L.fcsph_ctx_create.argtypes = [i, vp, P(vp)]
+    L.fcsph_ctx_destroy.argtypes = [vp]
+    L.fcsph_ctx_sync.argtypes = [vp]
+    L.fcsph_status_string.argtypes = [i]
+    L.fcsph_status_string.restype = ctypes.c_char_p
+    L.fcsph_ctx_last_error.argtypes = [vp]
+    L.fcsph_ctx_last_error.restype = ctypes.c_char_p
+    L.fcsph_plan_workspace_bytes.argtypes = [P(Desc), P(ctypes.c_size_t)]
+    L.fcsph_plan_create.argtypes = [vp, P(Desc), vp, ctypes.c_size_t, P(vp)]
+    L.fcsph_plan_destroy.argtypes = [vp]
+    L.fcsph_fc_extend.argtypes = [vp, i, vp, vp]
+    L.fcsph_spectral_grad.argtypes = [vp, i, vp, P(vp)]
+    L.fcsph_spectral_div.argtypes = [vp, P(vp), vp]
+    L.fcsph_spectral_lap.argtypes = [vp, i, vp, vp]
+    L.fcsph_ppe_solve.argtypes = [vp, vp, vp]
+    L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if f.restype is None or f.restype is ctypes.c_int:
+            if name not in ("fcsph_status_string", "fcsph_ctx_last_error"):
+                f.restype = i
+    _lib = L
+    return L
+
+
+class FcsphError(RuntimeError):
+    pass
+
+
+def _check(status: int, ctx=None, what: str = ""):
+    if status != OK:
+        L = lib()
+        msg = L.fcsph_status_string(status).decode()
+        detail = L.fcsph_ctx_last_error(ctx).decode() if ctx else ""
+        raise FcsphError(f"{what}: {msg} ({status}) {detail}")
+
+
+@dataclass
+class Problem:
+    """Lattice and method parameters (lattice order: x, y[, z])."""
+
+    n: tuple
+    walled: tuple
+    dx: float
+    vel_bc: tuple = None          # per axis ('D'|'N', 'D'|'N')
+    prs_bc: tuple = None
+    h_over_dx: float = 1.3
+    precision: str = "fp64"       # 'fp64' | 'fp32'
+    eig: str = "spectral"         # 'spectral' | 'fd2'
+    rho: float = 1.0
+    fc_d: int = 5
+    fc_C: int = 25
+
+    @property
+    def ndim(self):
+        return len(self.n)
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+    @property
+    def ext_shape(self):
+        return tuple(reversed([k + (self.fc_C if w else 0) for k, w in zip(self.n, self.walled)]))
+
+
+def _bc(c):
+    return {"D": DIRICHLET, "N": NEUMANN}[c]
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        L = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(L.fcsph_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)),
+               None, "fcsph_ctx_create")
+        self.handle = h
+
+    def sync(self):
+        _check(lib().fcsph_ctx_sync(self.handle), self.handle, "fcsph_ctx_sync")
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().fcsph_ctx_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class Plan:
+    """A plan for one lattice; owns its device workspace (a torch tensor)."""
+
+    def __init__(self, ctx: Context, prob: Problem):
+        import torch
+        L = lib()
+        self.ctx, self.prob = ctx, prob
+        tabs = fctables.load(prob.fc_d, prob.fc_C)
+        self._mdir = np.ascontiguousarray(tabs["dirichlet"], dtype=np.float64)
+        self._mneu = np.ascontiguousarray(tabs["neumann"], dtype=np.float64)
+        d = Desc()
+        d.ndim = prob.ndim
+        for a in range(prob.ndim):
+            d.n[a] = prob.n[a]
+            d.axis[a] = WALLED if prob.walled[a] else PERIODIC
+            if prob.walled[a]:
+                for s in range(2):
+                    d.vel_bc[a][s] = _bc(prob.vel_bc[a][s])
+                    d.prs_bc[a][s] = _bc(prob.prs_bc[a][s])
+        d.dx = prob.dx
+        d.fc_d, d.fc_C = prob.fc_d, prob.fc_C
+        d.fc_M_dir = self._mdir.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.fc_M_neu = self._mneu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.kernel = KERNEL_WENDLAND_C2
+        d.h_over_dx = prob.h_over_dx
+        d.prec = FP32_MIXED if prob.precision == "fp32" else FP64
+        d.ppe_domain = PPE_PHYSICAL
+        d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
+        d.rho = prob.rho
+        self.desc = d
+        nbytes = ctypes.c_size_t()
+        _check(L.fcsph_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), None,
+               "fcsph_plan_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _check(L.fcsph_plan_create(ctx.handle, ctypes.byref(d), ctypes.c_void_p(base + off),
+                                   nbytes.value, ctypes.byref(h)), ctx.handle, "fcsph_plan_create")
+        self.handle = h
+        self.out_dtype = torch.float32 if prob.precision == "fp32" else torch.float64
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().fcsph_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+    # -- helpers
+    def _t(self, x, dtype=None):
+        import torch
+        dtype = dtype or torch.float64
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
+            raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
+        return x
+
+    def _phys(self, x, dtype=None):
+        x = self._t(x, dtype)
+        if tuple(x.shape) != self.prob.shape:
+            raise ValueError(f"expected shape {self.prob.shape}, got {tuple(x.shape)}")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def _new(self, dtype=None, shape=None):
+        import torch
+        return torch.empty(shape or self.prob.shape, dtype=dtype or torch.float64,
+                           device=f"cuda:{self.ctx.device}")
+
+    @staticmethod
+    def _ptrs(ts):
+        arr = (ctypes.c_void_p * 3)()
+        for i, t in enumerate(ts):
+            arr[i] = None if t is None else t
+        return arr
+
+    # -- entry points (same names as the C ABI)
+    def fc_extend(self, f, field: int = VELOCITY, out=None):
+        import torch
+        out = self._new(torch.float64, self.prob.ext_shape) if out is None else out
+        self._t(out)
+        if tuple(out.shape) != self.prob.ext_shape:
+            raise ValueError("bad output shape")
+        _check(lib().fcsph_fc_extend(self.handle, field, self._phys(f), ctypes.c_void_p(out.data_ptr())),
+               self.ctx.handle, "fcsph_fc_extend")
+        return out
+
+    def spectral_grad(self, f, field: int = VELOCITY, out=None):
+        out = [self._new(self.out_dtype) for _ in range(self.prob.ndim)] if out is None else out
+        ptrs = self._ptrs([self._phys(o, self.out_dtype).value for o in out])
+        _check(lib().fcsph_spectral_grad(self.handle, field, self._phys(f), ptrs), self.ctx.handle,
+               "fcsph_spectral_grad")
+        return out
+
+    def spectral_div(self, u, out=None):
+        out = self._new(self.out_dtype) if out is None else out
+        ptrs = self._ptrs([self._phys(c).value for c in u])
+        _check(lib().fcsph_spectral_div(self.handle, ptrs, self._phys(out, self.out_dtype)),
+               self.ctx.handle, "fcsph_spectral_div")
+        return out
+
+    def spectral_lap(self, f, field: int = VELOCITY, out=None):
+        out = self._new(self.out_dtype) if out is None else out
+        _check(lib().fcsph_spectral_lap(self.handle, field, self._phys(f), self._phys(out, self.out_dtype)),
+               self.ctx.handle, "fcsph_spectral_lap")
+        return out
+
+    def ppe_solve(self, rhs, out=None):
+        out = self._new() if out is None else out
+        _check(lib().fcsph_ppe_solve(self.handle, self._phys(rhs, self.out_dtype), self._phys(out)),
+               self.ctx.handle, "fcsph_ppe_solve")
+        return out
+
+    def project_step(self, u, dt: float, nu: float, p_out=None, force=None, wall=None):
+        """One FOP step; u (list of tensors) is updated in place."""
+        up = self._ptrs([self._phys(c).value for c in u])
+        fp = self._ptrs([self._phys(c).value for c in force]) if force is not None else None
+        wp = self._ptrs([self._phys(c).value for c in wall]) if wall is not None else None
+        pp = self._phys(p_out) if p_out is not None else None
+        _check(lib().fcsph_project_step(self.handle, up, pp, fp, wp, float(dt), float(nu)),
+               self.ctx.handle, "fcsph_project_step")
+        return u, p_out
+
+
+# module-level aliases with the C ABI names
+def fc_extend(plan: Plan, f, field=VELOCITY, out=None):
+    return plan.fc_extend(f, field, out)
+
+
+def spectral_grad(plan: Plan, f, field=VELOCITY, out=None):
+    return plan.spectral_grad(f, field, out)
+
+
+def spectral_div(plan: Plan, u, out=None):
+    return plan.spectral_div(u, out)
+
+
+def spectral_lap(plan: Plan, f, field=VELOCITY, out=None):
+    return plan.spectral_lap(f, field, out)
+
+
+def ppe_solve(plan: Plan, rhs, out=None):
+    return plan.ppe_solve(rhs, out)
+
+
+def project_step(plan: Plan, u, dt, nu, p_out=None, force=None, wall=None):
+    return plan.project_step(u, dt, nu, p_out, force, wall)

@@ -1,0 +1,290 @@
+// Device-side line FFT engine for gfx950: mixed-radix Stockham stages on a
+// line buffer in LDS, executed cooperatively by a group of TL threads, plus a
+// Bluestein (chirp-z) wrapper for lengths with large prime factors.
+//
+// Stockham stage with radix R on length N, after stages whose radices
+// multiply to Ns: butterfly j (0 <= j < N/R) reads x[j + r N/R], applies the
+// twiddles w^(r k) with k = j mod Ns and w = exp(-2 pi i / (Ns R)), takes the
+// length-R DFT, and writes to (j - k) R + k + r Ns.  Output is in natural
+// order after the last stage.  Each thread keeps its butterflies of the stage
+// in registers between the read and write phases, so a single LDS buffer per
+// line suffices (read phase, barrier, write phase, barrier).
+//
+// Every line group of a workgroup runs the same plan, so the barriers are
+// uniform across the workgroup.
+#pragma once
+#include "internal.h"
+
+namespace fcsph {
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.r, -a.i}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.r * s, a.i * s}; }
+// multiply by -i and +i
+template <typename T>
+__device__ __forceinline__ cpx<T> cmi(cpx<T> a) { return {a.i, -a.r}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cpi(cpx<T> a) { return {-a.i, a.r}; }
+
+// Largest number of butterflies per thread and stage for radix R (bounds the
+// registers a stage holds); the host sizes TL with the same rule.
+__host__ __device__ constexpr int nb_max(int R) {
+  return R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1;
+}
+
+// ---- radix-R DFTs (forward, exp(-2 pi i j k / R)) on a register array ----
+template <typename T, int R>
+struct Dft;
+
+template <typename T>
+struct Dft<T, 2> {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
+    cpx<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <typename T>
+struct Dft<T, 3> {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
+    const T c = T(-0.5);
+    const T s = T(0.86602540378443864676372317075294);   // sin(2 pi / 3)
+    cpx<T> t = cadd(x[1], x[2]);
+    cpx<T> m = {x[0].r + c * t.r, x[0].i + c * t.i};
+    cpx<T> d = csub(x[1], x[2]);
+    cpx<T> sd = {s * d.r, s * d.i};
+    x[0] = cadd(x[0], t);
+    x[1] = cadd(m, cmi(sd));
+    x[2] = cadd(m, cpi(sd));
+  }
+};
+
+template <typename T>
+struct Dft<T, 4> {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
+    cpx<T> a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+    cpx<T> b0 = cadd(x[1], x[3]), b1 = cmi(csub(x[1], x[3]));
+    x[0] = cadd(a0, b0);
+    x[2] = csub(a0, b0);
+    x[1] = cadd(a1, b1);
+    x[3] = csub(a1, b1);
+  }
+};
+
+template <typename T>
+struct Dft<T, 8> {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
+    const T h = T(0.70710678118654752440084436210485);
+    cpx<T> a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = cadd(x[j], x[j + 4]);
+      b[j] = csub(x[j], x[j + 4]);
+    }
+    // b_j *= exp(-2 pi i j / 8)
+    b[1] = {h * (b[1].r + b[1].i), h * (b[1].i - b[1].r)};
+    b[2] = cmi(b[2]);
+    b[3] = {h * (b[3].i - b[3].r), -h * (b[3].r + b[3].i)};
+    Dft<T, 4>::run(a, nullptr, 0);
+    Dft<T, 4>::run(b, nullptr, 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      x[2 * m] = a[m];
+      x[2 * m + 1] = b[m];
+    }
+  }
+};
+
+// Odd radix: X_k = x0 + sum_{j=1..h} (x_j + x_{R-j}) cos(2 pi j k/R)
+//                 - i sum_{j=1..h} (x_j - x_{R-j}) sin(2 pi j k/R),
+// X_{R-k} the same with +i.  cs(m), sn(m) = cos, sin(2 pi m / R).
+template <typename T, int R, typename CS>
+__device__ __forceinline__ void dft_odd(cpx<T> *x, CS cs_sn) {
+  constexpr int h = (R - 1) / 2;
+  cpx<T> s[h + 1], d[h + 1];
+#pragma unroll
+  for (int j = 1; j <= h; ++j) {
+    s[j] = cadd(x[j], x[R - j]);
+    d[j] = csub(x[j], x[R - j]);
+  }
+  const cpx<T> x0 = x[0];
+  cpx<T> tot = x0;
+#pragma unroll
+  for (int j = 1; j <= h; ++j) tot = cadd(tot, s[j]);
+#pragma unroll
+  for (int k = 1; k <= h; ++k) {
+    cpx<T> A = x0, Bv = {T(0), T(0)};
+#pragma unroll
+    for (int j = 1; j <= h; ++j) {
+      const int m = (j * k) % R;
+      T c, sn;
+      cs_sn(m, c, sn);
+      A.r += s[j].r * c;
+      A.i += s[j].i * c;
+      Bv.r += d[j].r * sn;
+      Bv.i += d[j].i * sn;
+    }
+    x[k] = cadd(A, cmi(Bv));
+    x[R - k] = cadd(A, cpi(Bv));
+  }
+  x[0] = tot;
+}
+
+template <typename T>
+struct Dft<T, 5> {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
+    dft_odd<T, 5>(x, [](int m, T &c, T &s) {
+      constexpr double C1 = 0.30901699437494742410229341718282, C2 = -0.80901699437494742410229341718282;
+      constexpr double S1 = 0.95105651629515357211643933337938, S2 = 0.58778525229247312916870595463907;
+      c = T(m == 1 || m == 4 ? C1 : C2);
+      s = T(m == 1 ? S1 : m == 2 ? S2 : m == 3 ? -S2 : -S1);
+    });
+  }
+};
+
+template <typename T>
+struct Dft<T, 7> {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
+    dft_odd<T, 7>(x, [](int m, T &c, T &s) {
+      constexpr double C1 = 0.62348980185873353052500488400424, C2 = -0.22252093395631440428890256449679,
+                       C3 = -0.90096886790241912623610231950745;
+      constexpr double S1 = 0.78183148246802980870844452667406, S2 = 0.97492791218182360701813168299393,
+                       S3 = 0.43388373911755812047576833284836;
+      const int mm = m <= 3 ? m : 7 - m;
+      const double sg = m <= 3 ? 1.0 : -1.0;
+      c = T(mm == 1 ? C1 : mm == 2 ? C2 : C3);
+      s = T(sg * (mm == 1 ? S1 : mm == 2 ? S2 : S3));
+    });
+  }
+};
+
+// Larger odd radices read cos / sin(2 pi m / R) from the line's root table:
+// tw[m N / R] = exp(-2 pi i m / R).
+template <typename T, int R>
+struct Dft {
+  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *tw, int base) {
+    dft_odd<T, R>(x, [&](int m, T &c, T &s) {
+      const cpx<T> w = tw[m * base];
+      c = w.r;
+      s = -w.i;
+    });
+  }
+};
+
+// One Stockham stage.  N: work length; Ns: product of previous radices.
+template <typename T, int R>
+__device__ __forceinline__ void stockham_stage(cpx<T> *buf, int N, int Ns, const cpx<T> *tw,
+                                               int lt, int TL, bool active) {
+  constexpr int NB = nb_max(R);
+  const int NR = N / R;
+  const int tstride = N / (Ns * R);
+  cpx<T> v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lt + b * TL;
+    if (active && j < NR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NR];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lt + b * TL;
+    if (active && j < NR) {
+      const int k = j % Ns;
+      if (k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * tstride]);
+      }
+      Dft<T, R>::run(v[b], tw, NR);
+      const int o = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Forward FFT of length N = prod(radix) in place on buf (natural order).
+template <typename T>
+__device__ __forceinline__ void fft_stockham(cpx<T> *buf, const LinePlan &p, int N, int lt, int TL,
+                                             bool active) {
+  const cpx<T> *tw = static_cast<const cpx<T> *>(p.tw);
+  int Ns = 1;
+  for (int s = 0; s < p.nstages; ++s) {
+    const int R = p.radix[s];
+    switch (R) {
+      case 2: stockham_stage<T, 2>(buf, N, Ns, tw, lt, TL, active); break;
+      case 3: stockham_stage<T, 3>(buf, N, Ns, tw, lt, TL, active); break;
+      case 4: stockham_stage<T, 4>(buf, N, Ns, tw, lt, TL, active); break;
+      case 5: stockham_stage<T, 5>(buf, N, Ns, tw, lt, TL, active); break;
+      case 7: stockham_stage<T, 7>(buf, N, Ns, tw, lt, TL, active); break;
+      case 8: stockham_stage<T, 8>(buf, N, Ns, tw, lt, TL, active); break;
+      case 11: stockham_stage<T, 11>(buf, N, Ns, tw, lt, TL, active); break;
+      case 13: stockham_stage<T, 13>(buf, N, Ns, tw, lt, TL, active); break;
+      default: break;   // the host never builds other radices
+    }
+    Ns *= R;
+  }
+}
+
+// Forward DFT of length p.n on buf[0..n) (in place, result in buf[0..n)).
+// conj_in / conj_out conjugate the input / output, which turns the forward
+// transform into the unnormalised inverse.  Ends with a barrier.  An inactive
+// line group touches no memory but executes the same barriers.
+template <typename T>
+__device__ __forceinline__ void line_dft(cpx<T> *buf, const LinePlan &p, int lt, int TL, bool conj_in,
+                                         bool conj_out, bool active = true) {
+  if (!active) {
+    lt = 1 << 30;           // every index loop below starts past its bound
+  }
+  if (!p.blue) {
+    if (conj_in) {
+      for (int j = lt; j < p.n; j += TL) buf[j].i = -buf[j].i;
+      __syncthreads();
+    }
+    fft_stockham<T>(buf, p, p.n, lt, TL, active);
+    if (conj_out) {
+      for (int j = lt; j < p.n; j += TL) buf[j].i = -buf[j].i;
+      __syncthreads();
+    }
+    return;
+  }
+  const cpx<T> *chirp = static_cast<const cpx<T> *>(p.chirp);
+  const cpx<T> *filt = static_cast<const cpx<T> *>(p.filt);
+  // a_j = x_j w_j (zero padded to M)
+  for (int j = lt; j < p.M; j += TL) {
+    cpx<T> v = {T(0), T(0)};
+    if (j < p.n) {
+      v = buf[j];
+      if (conj_in) v.i = -v.i;
+      v = cmul(v, chirp[j]);
+    }
+    buf[j] = v;
+  }
+  __syncthreads();
+  fft_stockham<T>(buf, p, p.M, lt, TL, active);
+  // pointwise product with the filter spectrum; conjugate for the inverse FFT
+  for (int j = lt; j < p.M; j += TL) buf[j] = cconj(cmul(buf[j], filt[j]));
+  __syncthreads();
+  fft_stockham<T>(buf, p, p.M, lt, TL, active);
+  for (int k = lt; k < p.n; k += TL) {
+    cpx<T> v = cmul(cconj(buf[k]), chirp[k]);
+    if (conj_out) v.i = -v.i;
+    buf[k] = v;
+  }
+  __syncthreads();
+}
+
+}  // namespace fcsph

@@ -1,0 +1,910 @@
+// Host side of the library: C ABI, argument validation, plan construction
+// (tables computed in long double and rounded once), workspace layout and the
+// launch sequences of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fcsph.h"
+#include "internal.h"
+
+using namespace fcsph;
+
+struct fcsph_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+};
+
+namespace {
+
+typedef long double LD;
+const LD kPi = 3.141592653589793238462643383279502884L;
+
+// ----------------------------------------------------------------- workspace
+struct Bump {
+  char *base = nullptr;   // null: dry run (size only)
+  size_t off = 0;
+  void *take(size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    void *p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+// Host staging of a table before copy to the workspace.
+struct Upload {
+  void *dst;
+  std::vector<char> data;
+};
+
+// ----------------------------------------------------------------- line plans
+bool factor_direct(int n, std::vector<int> &rad) {
+  rad.clear();
+  int m = n;
+  while (m % 8 == 0 && m > 8) { rad.push_back(8); m /= 8; }
+  if (m % 8 == 0) { rad.push_back(8); m /= 8; }
+  while (m % 4 == 0) { rad.push_back(4); m /= 4; }
+  while (m % 2 == 0) { rad.push_back(2); m /= 2; }
+  const int odd[] = {3, 5, 7, 11, 13};
+  for (int p : odd)
+    while (m % p == 0) { rad.push_back(p); m /= p; }
+  if (m != 1) return false;
+  if (rad.empty()) rad.push_back(1);
+  return (int)rad.size() <= kMaxStages;
+}
+
+bool smooth7(int m) {
+  const int ps[] = {2, 3, 5, 7};
+  for (int p : ps)
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+int nb_max_host(int R) {
+  return R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1;
+}
+
+template <typename T>
+void put_cpx(std::vector<char> &v, size_t idx, LD re, LD im) {
+  cpx<T> c = {static_cast<T>(re), static_cast<T>(im)};
+  std::memcpy(v.data() + idx * sizeof(cpx<T>), &c, sizeof(c));
+}
+
+struct LineSpec {
+  LinePlan p{};
+  size_t bytes_tables = 0;
+};
+
+// Build a line plan for length n.  min_TL forces a minimum thread count per
+// line (used where the kernel keeps E / TL spectrum values in registers).
+bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> &up, LinePlan &p) {
+  std::memset(&p, 0, sizeof(p));
+  p.n = n;
+  std::vector<int> rad;
+  int M = n;
+  if (n == 1) {
+    rad = {};
+  } else if (factor_direct(n, rad)) {
+    p.blue = 0;
+  } else {
+    p.blue = 1;
+    M = 2 * n - 1;
+    while (!smooth7(M)) ++M;
+    if (!factor_direct(M, rad)) return false;
+  }
+  p.M = M;
+  p.nstages = (int)rad.size();
+  if (n == 1) p.nstages = 0;
+  for (int s = 0; s < p.nstages; ++s) p.radix[s] = rad[s];
+  int tl = 64;
+  for (int s = 0; s < p.nstages; ++s) {
+    const int R = rad[s];
+    const int need = (M / R + nb_max_host(R) - 1) / nb_max_host(R);
+    tl = std::max(tl, need);
+  }
+  tl = std::max(tl, min_TL);
+  tl = (tl + 63) / 64 * 64;
+  if (tl > kMaxThreads) return false;
+  p.TL = tl;
+  const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  // twiddles exp(-2 pi i t / M)
+  {
+    Upload u;
+    u.data.resize((size_t)M * es);
+    for (int t = 0; t < M; ++t) {
+      const LD a = -2.0L * kPi * (LD)t / (LD)M;
+      if (fp32) put_cpx<float>(u.data, t, cosl(a), sinl(a));
+      else put_cpx<double>(u.data, t, cosl(a), sinl(a));
+    }
+    u.dst = ws.take(u.data.size());
+    p.tw = u.dst;
+    up.push_back(std::move(u));
+  }
+  if (p.blue) {
+    // chirp w_j = exp(-pi i (j^2 mod 2n) / n)
+    std::vector<LD> cr(n), ci(n);
+    for (int j = 0; j < n; ++j) {
+      const long long q = ((long long)j * j) % (2LL * n);
+      const LD a = -kPi * (LD)q / (LD)n;
+      cr[j] = cosl(a);
+      ci[j] = sinl(a);
+    }
+    Upload uc;
+    uc.data.resize((size_t)n * es);
+    for (int j = 0; j < n; ++j) {
+      if (fp32) put_cpx<float>(uc.data, j, cr[j], ci[j]);
+      else put_cpx<double>(uc.data, j, cr[j], ci[j]);
+    }
+    uc.dst = ws.take(uc.data.size());
+    p.chirp = uc.dst;
+    up.push_back(std::move(uc));
+    // filter b_m = conj(w_m) for |m| < n (wrapped mod M); filt = DFT_M(b) / M
+    std::vector<LD> br(M, 0.0L), bi(M, 0.0L);
+    for (int m = 0; m < n; ++m) {
+      br[m] = cr[m];
+      bi[m] = -ci[m];
+      if (m > 0) {
+        br[M - m] = cr[m];
+        bi[M - m] = -ci[m];
+      }
+    }
+    std::vector<LD> twr(M), twi(M);
+    for (int t = 0; t < M; ++t) {
+      const LD a = -2.0L * kPi * (LD)t / (LD)M;
+      twr[t] = cosl(a);
+      twi[t] = sinl(a);
+    }
+    Upload uf;
+    uf.data.resize((size_t)M * es);
+    for (int k = 0; k < M; ++k) {
+      LD sr = 0.0L, si = 0.0L;
+      long long idx = 0;
+      for (int m = 0; m < M; ++m) {
+        if (br[m] != 0.0L || bi[m] != 0.0L) {
+          sr += br[m] * twr[idx] - bi[m] * twi[idx];
+          si += br[m] * twi[idx] + bi[m] * twr[idx];
+        }
+        idx += k;
+        if (idx >= M) idx -= M;
+      }
+      if (fp32) put_cpx<float>(uf.data, k, sr / M, si / M);
+      else put_cpx<double>(uf.data, k, sr / M, si / M);
+    }
+    uf.dst = ws.take(uf.data.size());
+    p.filt = uf.dst;
+    up.push_back(std::move(uf));
+  }
+  return true;
+}
+
+// Workgroup line count for a plan and per-line buffer size.
+int pick_B(const LinePlan &p, bool fp32, int want) {
+  const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  int B = want;
+  while (B > 1 && ((size_t)B * p.M * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
+  return B;
+}
+
+// ----------------------------------------------------------------- kernel taps
+// Wendland C2 (q = r/h, s = 1 - q/2):  grad W = -(5 alpha/h^2) s^3 x,
+// lap W = -(5 alpha/h^2) s^2 (2 - 5q/2) in 2D, (3 - 3q) in 3D.
+void wendland_taps(int ndim, double dx, double hod, const int *E, std::vector<double> W[4]) {
+  const int cube = ndim == 2 ? kSymW * kSymW : kSymW * kSymW * kSymW;
+  for (int q = 0; q < 4; ++q) W[q].assign(cube, 0.0);
+  const LD h = (LD)hod * (LD)dx;
+  const LD alpha = ndim == 2 ? 7.0L / (4.0L * kPi * h * h) : 21.0L / (16.0L * kPi * h * h * h);
+  const LD dV = ndim == 2 ? (LD)dx * dx : (LD)dx * dx * dx;
+  LD norm = 1.0L;
+  for (int a = 0; a < ndim; ++a) norm *= (LD)E[a];
+  const int zr = ndim == 3 ? kSymR : 0;
+  for (int sz = -zr; sz <= zr; ++sz)
+    for (int sy = -kSymR; sy <= kSymR; ++sy)
+      for (int sx = -kSymR; sx <= kSymR; ++sx) {
+        const LD r2 = (LD)(sx * sx + sy * sy + sz * sz);
+        const LD r = sqrtl(r2) * (LD)dx;
+        const LD q = r / h;
+        if (!(q < 2.0L)) continue;
+        const LD s = 1.0L - q / 2.0L;
+        const LD pre = -5.0L * alpha / (h * h);
+        const LD g = pre * s * s * s * dV;
+        const LD lap = pre * s * s * (ndim == 2 ? (2.0L - 2.5L * q) : (3.0L - 3.0L * q)) * dV;
+        const int idx = ndim == 2 ? (sy + kSymR) * kSymW + (sx + kSymR)
+                                  : ((sz + kSymR) * kSymW + (sy + kSymR)) * kSymW + (sx + kSymR);
+        W[0][idx] = (double)(g * (LD)sx * (LD)dx / norm);
+        W[1][idx] = (double)(g * (LD)sy * (LD)dx / norm);
+        if (ndim == 3) W[2][idx] = (double)(g * (LD)sz * (LD)dx / norm);
+        W[3][idx] = (double)(lap / norm);
+      }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- the plan
+struct fcsph_plan {
+  fcsph_ctx *ctx = nullptr;
+  fcsph_desc d{};
+  bool fp32 = false;
+  int nd = 2;
+  int n[3] = {1, 1, 1};
+  int E[3] = {1, 1, 1};
+  int walled[3] = {0, 0, 0};
+  int H = 0;            // x half spectrum
+  // FC maps (device)
+  const double *M_dir = nullptr, *M_neu = nullptr;
+  // line plans
+  LinePlan op[3];       // operator DFT along each axis (length E[a])
+  LinePlan trig[3];     // PPE transform along each axis
+  int trig_kind[3] = {0, 0, 0};
+  int ncoef[3] = {0, 0, 0};
+  const double *mu[3] = {nullptr, nullptr, nullptr};
+  // symbols
+  SymTables st{};
+  // scratch
+  void *S[3] = {nullptr, nullptr, nullptr};   // input spectra
+  void *O[12] = {};                            // output spectra
+  void *Y[3] = {nullptr, nullptr, nullptr};    // 3D: y-extended spectra
+  size_t spec_elems = 0;
+  double *ustar[3] = {nullptr, nullptr, nullptr};
+  void *rhs = nullptr;          // PPE right-hand side (output type)
+  double *phi = nullptr;        // pressure scratch
+  void *coef = nullptr;         // PPE coefficient rows
+  int cpitch = 0;
+  double *ext_scratch = nullptr;  // intermediate of a multi-axis FC extension
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+fcsph_status fail(fcsph_ctx *c, fcsph_status s, const std::string &msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+fcsph_status hip_fail(fcsph_ctx *c, hipError_t e, const char *where) {
+  return fail(c, FCSPH_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+FcWalls walls_for(const fcsph_plan *p, int axis, int fc) {
+  FcWalls w{};
+  w.on = p->walled[axis];
+  w.C = p->d.fc_C;
+  w.d = p->d.fc_d;
+  if (w.on) {
+    const int(*bc)[2] = fc == FCSPH_FIELD_VELOCITY ? p->d.vel_bc : p->d.prs_bc;
+    w.Mlo = bc[axis][0] == FCSPH_BC_NEUMANN ? p->M_neu : p->M_dir;
+    w.Mhi = bc[axis][1] == FCSPH_BC_NEUMANN ? p->M_neu : p->M_dir;
+  }
+  return w;
+}
+
+fcsph_status validate(const fcsph_desc *d, std::string &msg) {
+  if (!d) { msg = "null descriptor"; return FCSPH_E_INVALID; }
+  if (d->ndim != 2 && d->ndim != 3) { msg = "ndim must be 2 or 3"; return FCSPH_E_INVALID; }
+  if (!(d->dx > 0.0) || !std::isfinite(d->dx)) { msg = "dx must be positive"; return FCSPH_E_INVALID; }
+  if (d->kernel != FCSPH_KERNEL_WENDLAND_C2) { msg = "unknown kernel"; return FCSPH_E_INVALID; }
+  if (!(d->h_over_dx > 0.0) || 2.0 * d->h_over_dx >= kSymR + 1) {
+    msg = "h_over_dx must be in (0, " + std::to_string((kSymR + 1) / 2.0) + ")";
+    return FCSPH_E_UNSUPPORTED;
+  }
+  if (d->prec != FCSPH_FP64 && d->prec != FCSPH_FP32_MIXED) { msg = "bad precision"; return FCSPH_E_INVALID; }
+  if (d->ppe_domain != FCSPH_PPE_PHYSICAL) { msg = "only the physical-domain PPE is built"; return FCSPH_E_UNSUPPORTED; }
+  if (d->eig != FCSPH_EIG_SPECTRAL && d->eig != FCSPH_EIG_FD2) { msg = "eigenvalue family not built"; return FCSPH_E_UNSUPPORTED; }
+  if (!(d->rho > 0.0)) { msg = "rho must be positive"; return FCSPH_E_INVALID; }
+  bool any_wall = false;
+  for (int a = 0; a < d->ndim; ++a) {
+    if (d->n[a] < 2) { msg = "n must be >= 2"; return FCSPH_E_INVALID; }
+    if (d->axis[a] != FCSPH_AXIS_PERIODIC && d->axis[a] != FCSPH_AXIS_WALLED) { msg = "bad axis kind"; return FCSPH_E_INVALID; }
+    if (d->axis[a] == FCSPH_AXIS_WALLED) {
+      any_wall = true;
+      if (d->n[a] < 2 * d->fc_d) { msg = "walled axis needs n >= 2 fc_d"; return FCSPH_E_INVALID; }
+      for (int s = 0; s < 2; ++s) {
+        if ((d->vel_bc[a][s] != 0 && d->vel_bc[a][s] != 1) || (d->prs_bc[a][s] != 0 && d->prs_bc[a][s] != 1)) {
+          msg = "bad wall type";
+          return FCSPH_E_INVALID;
+        }
+      }
+    }
+    const int E = d->n[a] + (d->axis[a] == FCSPH_AXIS_WALLED ? d->fc_C : 0);
+    if (2.0 * 2.0 * d->h_over_dx >= (double)E) { msg = "kernel support exceeds half the extended period"; return FCSPH_E_INVALID; }
+  }
+  if (any_wall) {
+    if (d->fc_d < 1 || d->fc_C < 1 || d->fc_d > 16 || d->fc_C > 64) { msg = "bad FC sizes"; return FCSPH_E_INVALID; }
+    if (!d->fc_M_dir || !d->fc_M_neu) { msg = "FC maps required for walled axes"; return FCSPH_E_INVALID; }
+  }
+  if (d->ndim == 3) {
+    if (d->axis[0] != FCSPH_AXIS_PERIODIC || d->axis[2] != FCSPH_AXIS_PERIODIC || d->axis[1] != FCSPH_AXIS_WALLED) {
+      msg = "3D lattices are built for walls in y only";
+      return FCSPH_E_UNSUPPORTED;
+    }
+  }
+  return FCSPH_OK;
+}
+
+// Lay out the plan in the workspace (dry run when ws.base is null).
+fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Upload> &up, std::string &msg) {
+  p->d = *d;
+  p->fp32 = d->prec == FCSPH_FP32_MIXED;
+  p->nd = d->ndim;
+  for (int a = 0; a < 3; ++a) {
+    p->n[a] = a < p->nd ? d->n[a] : 1;
+    p->walled[a] = a < p->nd ? (d->axis[a] == FCSPH_AXIS_WALLED) : 0;
+    p->E[a] = p->n[a] + (p->walled[a] ? d->fc_C : 0);
+  }
+  p->H = p->E[0] / 2 + 1;
+  const bool f32 = p->fp32;
+  const size_t ce = f32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  const size_t te = f32 ? sizeof(float) : sizeof(double);
+  bool any_wall = p->walled[0] || p->walled[1] || p->walled[2];
+  // FC maps
+  if (any_wall) {
+    const size_t mb = (size_t)d->fc_C * d->fc_d * sizeof(double);
+    Upload a, b;
+    a.data.assign((const char *)d->fc_M_dir, (const char *)d->fc_M_dir + mb);
+    b.data.assign((const char *)d->fc_M_neu, (const char *)d->fc_M_neu + mb);
+    a.dst = ws.take(mb);
+    b.dst = ws.take(mb);
+    p->M_dir = (const double *)a.dst;
+    p->M_neu = (const double *)b.dst;
+    up.push_back(std::move(a));
+    up.push_back(std::move(b));
+  }
+  // operator line plans
+  for (int a = 0; a < p->nd; ++a) {
+    const int minTL = (a == 0) ? 64 : (p->E[a] + 7) / 8;   // cols kernels keep E/TL <= 8 values
+    if (!make_line_plan(p->E[a], f32, minTL, ws, up, p->op[a])) {
+      msg = "cannot plan a DFT of length " + std::to_string(p->E[a]);
+      return FCSPH_E_UNSUPPORTED;
+    }
+  }
+  // symbols
+  {
+    std::vector<double> W[4];
+    wendland_taps(p->nd, d->dx, d->h_over_dx, p->E, W);
+    p->st.ndim = p->nd;
+    for (int a = 0; a < 3; ++a) p->st.E[a] = p->E[a];
+    for (int q = 0; q < 4; ++q) {
+      Upload u;
+      u.data.assign((const char *)W[q].data(), (const char *)(W[q].data() + W[q].size()));
+      u.dst = ws.take(u.data.size());
+      p->st.W[q] = (const double *)u.dst;
+      up.push_back(std::move(u));
+    }
+    for (int a = 0; a < p->nd; ++a) {
+      Upload u;
+      const int E = p->E[a];
+      u.data.resize((size_t)E * (kSymR + 1) * sizeof(double2));
+      double2 *t = (double2 *)u.data.data();
+      for (int k = 0; k < E; ++k)
+        for (int s = 0; s <= kSymR; ++s) {
+          const long long q = ((long long)k * s) % E;
+          const LD ang = -2.0L * kPi * (LD)q / (LD)E;
+          t[(size_t)k * (kSymR + 1) + s] = make_double2((double)cosl(ang), (double)sinl(ang));
+        }
+      u.dst = ws.take(u.data.size());
+      p->st.ph[a] = (const double2 *)u.dst;
+      up.push_back(std::move(u));
+    }
+  }
+  // PPE plans and eigenvalues
+  for (int a = 0; a < p->nd; ++a) {
+    const int nn = p->n[a];
+    int L, kind;
+    if (!p->walled[a]) {
+      kind = TRIG_DFT;
+      L = nn;
+    } else if (d->prs_bc[a][0] != d->prs_bc[a][1]) {
+      p->trig_kind[a] = -1;     // quarter-wave transforms: not built
+      continue;
+    } else {
+      kind = d->prs_bc[a][0] == FCSPH_BC_NEUMANN ? TRIG_DCT1 : TRIG_DST1;
+      L = 2 * (nn - 1);
+    }
+    p->trig_kind[a] = kind;
+    p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : nn - 2);
+    const int minTL = (a == 0) ? 64 : 64;
+    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a])) {
+      msg = "cannot plan a PPE transform of length " + std::to_string(L);
+      return FCSPH_E_UNSUPPORTED;
+    }
+    // eigenvalues indexed by storage position
+    std::vector<double> mu(nn, 0.0);
+    const LD dx = d->dx;
+    for (int k = 0; k < nn; ++k) {
+      LD th;   // mode angle per grid step
+      if (kind == TRIG_DFT) {
+        const int ks = (k <= nn / 2) ? k : k - nn;
+        th = 2.0L * kPi * (LD)ks / (LD)nn;
+      } else if (kind == TRIG_DCT1 || a != 0) {
+        th = kPi * (LD)k / (LD)(nn - 1);            // position = mode (lines, DCT rows)
+      } else {
+        th = kPi * (LD)(k + 1) / (LD)(nn - 1);      // DST-I rows: position p <-> mode p+1
+      }
+      LD m;
+      if (d->eig == FCSPH_EIG_SPECTRAL) m = (th / dx) * (th / dx);
+      else m = 4.0L / (dx * dx) * sinl(th / 2.0L) * sinl(th / 2.0L);
+      mu[k] = (double)m;
+    }
+    Upload u;
+    u.data.assign((const char *)mu.data(), (const char *)(mu.data() + mu.size()));
+    u.dst = ws.take(u.data.size());
+    p->mu[a] = (const double *)u.dst;
+    up.push_back(std::move(u));
+  }
+  // scratch
+  const size_t P = (size_t)p->n[0] * p->n[1] * p->n[2];
+  size_t rows = (size_t)p->n[1] * p->n[2];
+  size_t rows_ext = (size_t)p->E[1] * p->n[2];     // 3D y-extended rows
+  p->spec_elems = std::max(rows, rows_ext) * p->H;
+  const size_t sb = p->spec_elems * ce;
+  for (int i = 0; i < 3; ++i) p->S[i] = ws.take(sb);
+  const int nO = p->nd == 2 ? 6 : 12;
+  for (int i = 0; i < nO; ++i) p->O[i] = ws.take(sb);
+  if (p->nd == 3)
+    for (int i = 0; i < 3; ++i) p->Y[i] = ws.take(sb);
+  for (int a = 0; a < p->nd; ++a) p->ustar[a] = (double *)ws.take(P * sizeof(double));
+  p->rhs = ws.take(P * te);
+  p->phi = (double *)ws.take(P * sizeof(double));
+  p->cpitch = p->trig_kind[0] == TRIG_DFT ? p->ncoef[0] : (std::max(p->ncoef[0], 1) + 1) / 2;
+  p->coef = ws.take((size_t)p->cpitch * rows * ce);
+  p->ext_scratch = (double *)ws.take((size_t)p->E[0] * p->E[1] * p->E[2] * sizeof(double));
+  p->ws_bytes = ws.off + 256;
+  return FCSPH_OK;
+}
+
+// ----------------------------------------------------------------- pipelines
+bool chk(fcsph_plan *p, hipError_t e, const char *where, fcsph_status &st) {
+  if (e != hipSuccess) {
+    st = hip_fail(p->ctx, e, where);
+    return false;
+  }
+  return true;
+}
+
+// x-pass forward over the rows of a physical field f; rows (2l, 2l+1) packed.
+hipError_t x_fwd_single(fcsph_plan *p, const double *f, int fc, void *S) {
+  RowsFwdArgs a{};
+  a.plan = p->op[0];
+  const int rows = p->n[1] * p->n[2];
+  a.nlines = (rows + 1) / 2;
+  a.nx = p->n[0];
+  a.E = p->E[0];
+  a.H = p->H;
+  a.fc = walls_for(p, 0, fc);
+  a.inA = f;
+  a.inB = f + p->n[0];
+  a.strideA = a.strideB = 2L * p->n[0];
+  a.nB = rows / 2;
+  a.outA = S;
+  a.outB = (char *)S + (size_t)p->H * (p->fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
+  a.ostrideA = a.ostrideB = 2L * p->H;
+  a.B = pick_B(a.plan, p->fp32, 4);
+  a.ldsM = a.plan.M;
+  return launch_rows_fwd(a, p->fp32, p->ctx->stream);
+}
+
+// x-pass forward of two fields with the same wall maps, packed row by row.
+hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc, void *S0, void *S1) {
+  RowsFwdArgs a{};
+  a.plan = p->op[0];
+  const int rows = p->n[1] * p->n[2];
+  a.nlines = rows;
+  a.nx = p->n[0];
+  a.E = p->E[0];
+  a.H = p->H;
+  a.fc = walls_for(p, 0, fc);
+  a.inA = f0;
+  a.inB = f1;
+  a.strideA = a.strideB = p->n[0];
+  a.nB = rows;
+  a.outA = S0;
+  a.outB = S1;
+  a.ostrideA = a.ostrideB = p->H;
+  a.B = pick_B(a.plan, p->fp32, 4);
+  a.ldsM = a.plan.M;
+  return launch_rows_fwd(a, p->fp32, p->ctx->stream);
+}
+
+// 2D strided y pass with symbol multiplication.
+ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
+  ColsArgs c{};
+  c.plan = p->op[1];
+  c.mode = mode;
+  c.ninner = p->H;
+  c.nouter = 1;
+  c.es = p->H;
+  c.es_out = p->H;
+  c.os_in = c.os_out = 0;
+  c.nload = p->n[1];
+  c.nstore = p->n[1];
+  c.fc = walls_for(p, 1, fc);
+  c.st = p->st;
+  c.line_axis = 1;
+  c.inner_axis = 0;
+  c.outer_axis = -1;
+  c.B = pick_B(c.plan, p->fp32, 4);
+  c.ldsM = c.plan.M;
+  return c;
+}
+
+hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void *out0, void *out1,
+                       bool out_double, double scale) {
+  RowsInvArgs a{};
+  a.plan = p->op[0];
+  a.nrows = p->n[1] * p->n[2];
+  a.nx = p->n[0];
+  a.E = p->E[0];
+  a.H = p->H;
+  a.B = pick_B(a.plan, p->fp32, 4);
+  a.ldsM = a.plan.M;
+  a.spec[0] = spec0;
+  a.spec[1] = spec1;
+  a.spec_pitch = p->H;
+  a.out[0] = out0;
+  a.out[1] = out1;
+  a.out_is_double = out_double ? 1 : 0;
+  a.scale = scale;
+  return launch_rows_inv(a, EPI_STORE, p->fp32, p->ctx->stream);
+}
+
+WallInfo wall_info(fcsph_plan *p) {
+  WallInfo w{};
+  w.ndim = p->nd;
+  for (int a = 0; a < 3; ++a) {
+    w.n[a] = p->n[a];
+    w.walled[a] = p->walled[a];
+    for (int s = 0; s < 2; ++s) w.dir[a][s] = p->walled[a] && p->d.vel_bc[a][s] == FCSPH_BC_DIRICHLET;
+  }
+  return w;
+}
+
+fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
+  fcsph_status st = FCSPH_OK;
+  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D PPE not built yet");
+  for (int a = 0; a < p->nd; ++a)
+    if (p->trig_kind[a] < 0)
+      return fail(p->ctx, FCSPH_E_UNSUPPORTED, "mixed Dirichlet/Neumann pressure walls on one axis are not built");
+  const bool f32 = p->fp32;
+  // P1: rows forward
+  PpeRowsArgs r{};
+  r.plan = p->trig[0];
+  r.kind = p->trig_kind[0];
+  r.inverse = 0;
+  r.nrows = p->n[1];
+  r.nx = p->n[0];
+  r.ncoef = p->ncoef[0];
+  r.cpitch = p->cpitch;
+  r.in_real = f32 ? nullptr : (const double *)rhs;
+  r.in_float = f32 ? (const float *)rhs : nullptr;
+  r.coef = p->coef;
+  r.B = pick_B(r.plan, f32, 4);
+  r.ldsM = r.plan.M;
+  if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
+  // P2: columns forward, divide, inverse
+  PpeColsArgs c{};
+  c.plan = p->trig[1];
+  c.kind = p->trig_kind[1];
+  c.ninner = p->cpitch;
+  c.nouter = 1;
+  c.es = p->cpitch;
+  c.os = 0;
+  c.nline = p->n[1];
+  c.ncoef = p->ncoef[1];
+  c.solve = 1;
+  c.mu_line = p->mu[1];
+  c.mu_inner = p->mu[0];
+  c.inner_packed = p->trig_kind[0] != TRIG_DFT;
+  c.inner_nmodes = p->ncoef[0];
+  c.mu_outer = nullptr;
+  c.scale = p->trig_kind[1] == TRIG_DFT ? 1.0 / p->n[1] : 1.0 / (2.0 * (p->n[1] - 1));
+  c.data = p->coef;
+  c.B = pick_B(c.plan, f32, 4);
+  c.ldsM = c.plan.M;
+  if (!chk(p, launch_ppe_cols(c, f32, p->ctx->stream), "ppe cols", st)) return st;
+  // P3: rows inverse
+  r.inverse = 1;
+  r.in_real = nullptr;
+  r.in_float = nullptr;
+  r.out = phi;
+  r.scale = p->trig_kind[0] == TRIG_DFT ? 1.0 / p->n[0] : 1.0 / (2.0 * (p->n[0] - 1));
+  if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows inverse", st)) return st;
+  return FCSPH_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *fcsph_status_string(fcsph_status s) {
+  switch (s) {
+    case FCSPH_OK: return "ok";
+    case FCSPH_E_INVALID: return "invalid argument";
+    case FCSPH_E_UNSUPPORTED: return "unsupported";
+    case FCSPH_E_WORKSPACE: return "workspace too small or misaligned";
+    case FCSPH_E_HIP: return "HIP error";
+    case FCSPH_E_NONFINITE: return "non-finite values";
+  }
+  return "unknown status";
+}
+
+fcsph_status fcsph_ctx_create(int device, void *hip_stream, fcsph_ctx **out) {
+  if (!out) return FCSPH_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FCSPH_E_INVALID;
+  fcsph_ctx *c = new (std::nothrow) fcsph_ctx;
+  if (!c) return FCSPH_E_INVALID;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return FCSPH_E_HIP;
+  }
+  *out = c;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_ctx_destroy(fcsph_ctx *c) {
+  delete c;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_ctx_sync(fcsph_ctx *c) {
+  if (!c) return FCSPH_E_INVALID;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "device");
+  return FCSPH_OK;
+}
+
+const char *fcsph_ctx_last_error(fcsph_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+
+fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes) {
+  if (!bytes) return FCSPH_E_INVALID;
+  std::string msg;
+  fcsph_status s = validate(d, msg);
+  if (s != FCSPH_OK) return s;
+  fcsph_plan tmp;
+  Bump ws;
+  std::vector<Upload> up;
+  s = layout(&tmp, d, ws, up, msg);
+  if (s != FCSPH_OK) return s;
+  *bytes = tmp.ws_bytes;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_plan_create(fcsph_ctx *c, const fcsph_desc *d, void *workspace, size_t bytes,
+                               fcsph_plan **out) {
+  if (!c || !out) return FCSPH_E_INVALID;
+  *out = nullptr;
+  std::string msg;
+  fcsph_status s = validate(d, msg);
+  if (s != FCSPH_OK) return fail(c, s, msg);
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(c, FCSPH_E_WORKSPACE, "workspace null or not 256-byte aligned");
+  fcsph_plan *p = new (std::nothrow) fcsph_plan;
+  if (!p) return fail(c, FCSPH_E_INVALID, "out of host memory");
+  p->ctx = c;
+  Bump ws;
+  ws.base = (char *)workspace;
+  std::vector<Upload> up;
+  s = layout(p, d, ws, up, msg);
+  if (s != FCSPH_OK) {
+    delete p;
+    return fail(c, s, msg);
+  }
+  if (p->ws_bytes > bytes) {
+    delete p;
+    return fail(c, FCSPH_E_WORKSPACE, "workspace too small: need " + std::to_string(ws.off + 256));
+  }
+  for (auto &u : up) {
+    hipError_t e = hipMemcpyAsync(u.dst, u.data.data(), u.data.size(), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(c, e, "table upload");
+    }
+  }
+  // host staging buffers are pageable: finish the copies before they go away
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(c, e, "table upload sync");
+  }
+  *out = p;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_plan_destroy(fcsph_plan *p) {
+  delete p;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_fc_extend(fcsph_plan *p, int fc, const double *f, double *f_ext) {
+  if (!p || !f || !f_ext) return p ? fail(p->ctx, FCSPH_E_INVALID, "null pointer") : FCSPH_E_INVALID;
+  if (fc != FCSPH_FIELD_VELOCITY && fc != FCSPH_FIELD_PRESSURE) return fail(p->ctx, FCSPH_E_INVALID, "bad field class");
+  fcsph_status st = FCSPH_OK;
+  int shape[3] = {p->n[0], p->n[1], p->n[2]};
+  int nw = 0, last = -1;
+  for (int a = 0; a < p->nd; ++a)
+    if (p->walled[a]) { ++nw; last = a; }
+  if (nw == 0) {
+    size_t P = (size_t)shape[0] * shape[1] * shape[2];
+    if (!chk(p, hipMemcpyAsync(f_ext, f, P * sizeof(double), hipMemcpyDeviceToDevice, p->ctx->stream), "copy", st)) return st;
+    return FCSPH_OK;
+  }
+  // apply the walled axes in order x, y, z; with two walled axes the first
+  // result goes to the plan's extension scratch
+  if (nw > 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "more than two walled axes");
+  const double *src = f;
+  for (int a = 0; a < p->nd; ++a) {
+    if (!p->walled[a]) continue;
+    double *dst = (a == last) ? f_ext : p->ext_scratch;
+    FcWalls w = walls_for(p, a, fc);
+    if (!chk(p, launch_fc_extend_axis(src, dst, p->nd, shape, a, w, p->ctx->stream), "fc_extend", st)) return st;
+    shape[a] += p->d.fc_C;
+    src = dst;
+  }
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *const *g) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!f || !g) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  for (int a = 0; a < p->nd; ++a)
+    if (!g[a]) return fail(p->ctx, FCSPH_E_INVALID, "null output");
+  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
+  fcsph_status st = FCSPH_OK;
+  if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "grad x", st)) return st;
+  ColsArgs c = cols_base(p, COLS_OP, fc);
+  c.in[0] = p->S[0];
+  c.out[0][0] = p->O[0];
+  c.out[0][1] = p->O[1];
+  c.nout = 2;
+  c.sym[0] = SYM_GX;
+  c.sym[1] = SYM_GY;
+  if (!chk(p, launch_cols(c, 1, p->fp32, p->ctx->stream), "grad y", st)) return st;
+  if (!chk(p, x_inv_store(p, p->O[0], p->O[1], g[0], g[1], !p->fp32, 1.0), "grad x inv", st)) return st;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *lap) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!f || !lap) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
+  fcsph_status st = FCSPH_OK;
+  if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
+  ColsArgs c = cols_base(p, COLS_OP, fc);
+  c.in[0] = p->S[0];
+  c.out[0][0] = p->O[0];
+  c.nout = 1;
+  c.sym[0] = SYM_LAP;
+  if (!chk(p, launch_cols(c, 1, p->fp32, p->ctx->stream), "lap y", st)) return st;
+  if (!chk(p, x_inv_store(p, p->O[0], nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
+  return FCSPH_OK;
+}
+
+static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, void *out, bool out_double,
+                             double scale) {
+  fcsph_status st = FCSPH_OK;
+  if (!chk(p, x_fwd_pair(p, u0, u1, FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
+  ColsArgs c = cols_base(p, COLS_DIV, FCSPH_FIELD_VELOCITY);
+  c.in[0] = p->S[0];
+  c.in[1] = p->S[1];
+  c.out[0][0] = p->O[0];
+  c.nout = 1;
+  c.sym[0] = SYM_GX;
+  c.sym[1] = SYM_GY;
+  if (!chk(p, launch_cols(c, 1, p->fp32, p->ctx->stream), "div y", st)) return st;
+  if (!chk(p, x_inv_store(p, p->O[0], nullptr, out, nullptr, out_double, scale), "div x inv", st)) return st;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_spectral_div(fcsph_plan *p, const double *const *u, void *div) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!u || !div) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  for (int a = 0; a < p->nd; ++a)
+    if (!u[a]) return fail(p->ctx, FCSPH_E_INVALID, "null input");
+  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
+  return div_impl(p, u[0], u[1], div, !p->fp32, 1.0);
+}
+
+fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!rhs || !phi) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  return run_ppe(p, rhs, phi);
+}
+
+fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, const double *const *force,
+                                const double *const *wall_vel, double dt, double nu) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!u) return fail(p->ctx, FCSPH_E_INVALID, "null velocity");
+  for (int a = 0; a < p->nd; ++a)
+    if (!u[a]) return fail(p->ctx, FCSPH_E_INVALID, "null velocity component");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(nu >= 0.0) || !std::isfinite(nu))
+    return fail(p->ctx, FCSPH_E_INVALID, "dt must be positive and nu non-negative");
+  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D step not built yet");
+  fcsph_status st = FCSPH_OK;
+  hipStream_t s = p->ctx->stream;
+  const bool f32 = p->fp32;
+  // A: u* = u - dt [(u.grad)u - nu lap u - f], Dirichlet walls <- wall data
+  if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "step A x", st)) return st;
+  ColsArgs c = cols_base(p, COLS_OP, FCSPH_FIELD_VELOCITY);
+  c.in[0] = p->S[0];
+  c.in[1] = p->S[1];
+  c.out[0][0] = p->O[0];
+  c.out[0][1] = p->O[1];
+  c.out[0][2] = p->O[2];
+  c.out[1][0] = p->O[3];
+  c.out[1][1] = p->O[4];
+  c.out[1][2] = p->O[5];
+  c.nout = 3;
+  c.sym[0] = SYM_GX;
+  c.sym[1] = SYM_GY;
+  c.sym[2] = SYM_LAP;
+  if (!chk(p, launch_cols(c, 2, f32, s), "step A y", st)) return st;
+  RowsInvArgs r{};
+  r.plan = p->op[0];
+  r.nrows = p->n[1];
+  r.nx = p->n[0];
+  r.E = p->E[0];
+  r.H = p->H;
+  r.B = 1;
+  r.ldsM = r.plan.M;
+  r.spec[0] = p->O[0];
+  r.spec[1] = p->O[1];
+  r.spec[2] = p->O[3];
+  r.spec[3] = p->O[4];
+  r.spec[4] = p->O[2];
+  r.spec[5] = p->O[5];
+  r.spec_pitch = p->H;
+  r.u[0] = u[0];
+  r.u[1] = u[1];
+  r.f[0] = force ? force[0] : nullptr;
+  r.f[1] = force ? force[1] : nullptr;
+  r.wall[0] = wall_vel ? wall_vel[0] : nullptr;
+  r.wall[1] = wall_vel ? wall_vel[1] : nullptr;
+  r.ustar[0] = p->ustar[0];
+  r.ustar[1] = p->ustar[1];
+  r.dt = dt;
+  r.nu = nu;
+  r.dt_over_rho = dt / p->d.rho;
+  r.wi = wall_info(p);
+  if (3ull * r.ldsM * (f32 ? 8 : 16) > (size_t)kMaxLds)
+    return fail(p->ctx, FCSPH_E_UNSUPPORTED, "x line too long for the fused step kernel");
+  if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;
+  // B: b = (rho/dt) div u*
+  st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
+  if (st != FCSPH_OK) return st;
+  // C: PPE
+  double *phi = p_out ? p_out : p->phi;
+  st = run_ppe(p, p->rhs, phi);
+  if (st != FCSPH_OK) return st;
+  // D: u = u* - dt/rho grad phi, walls reset
+  if (!chk(p, x_fwd_single(p, phi, FCSPH_FIELD_PRESSURE, p->S[0]), "step D x", st)) return st;
+  ColsArgs cd = cols_base(p, COLS_OP, FCSPH_FIELD_PRESSURE);
+  cd.in[0] = p->S[0];
+  cd.out[0][0] = p->O[0];
+  cd.out[0][1] = p->O[1];
+  cd.nout = 2;
+  cd.sym[0] = SYM_GX;
+  cd.sym[1] = SYM_GY;
+  if (!chk(p, launch_cols(cd, 1, f32, s), "step D y", st)) return st;
+  RowsInvArgs rd = r;
+  rd.spec[0] = p->O[0];
+  rd.spec[1] = p->O[1];
+  rd.B = pick_B(rd.plan, f32, 4);
+  rd.unew[0] = u[0];
+  rd.unew[1] = u[1];
+  if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, f32, s), "step D x inv", st)) return st;
+  return FCSPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Internal structures shared by the host library and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fcsph {
+
+constexpr int kMaxStages = 16;
+constexpr int kSymR = 3;                 // largest tap offset per axis (|s_a| <= 3)
+constexpr int kSymW = 2 * kSymR + 1;     // taps per axis in the dense weight cube
+constexpr int kMaxLds = 160 * 1024;      // LDS per workgroup on gfx950
+constexpr int kMaxThreads = 512;         // workgroup size bound of the line kernels
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T r, i;
+};
+
+// One batched 1D DFT of length n along a line, executed by a group of TL
+// threads on a line buffer of M complex values in LDS.  Direct Stockham when
+// n factors into the supported radices, otherwise Bluestein with an M-point
+// smooth FFT.  Table pointers are cpx<T> device arrays inside the workspace.
+struct LinePlan {
+  int n;           // DFT length
+  int M;           // FFT work length (== n when direct)
+  int blue;        // 1: Bluestein
+  int nstages;
+  int radix[kMaxStages];
+  int TL;          // threads per line the plan is sized for
+  const void *tw;     // [M]  exp(-2 pi i t / M)
+  const void *chirp;  // [n]  exp(-pi i (t^2 mod 2n) / n)        (Bluestein)
+  const void *filt;   // [M]  DFT_M(wrapped conj chirp) / M       (Bluestein)
+};
+
+// FC(Gram) maps of the two walls of one axis (C x d, row-major, FP64).
+struct FcWalls {
+  int on;              // axis is walled
+  int C, d;
+  const double *Mlo;   // map of the low wall (index 0)
+  const double *Mhi;   // map of the high wall (index n-1)
+};
+
+// Spectral symbol of one operator: dense tap weights (already scaled by
+// 1/prod(E_a)) on a kSymW^ndim cube, and per-axis phase tables
+// ph_a[k * (kSymR+1) + s] = exp(-2 pi i k s / E_a), s = 0..kSymR.
+struct SymTables {
+  int ndim;
+  int E[3];
+  const double *W[4];        // grad x, grad y, grad z, lap
+  const double2 *ph[3];      // per axis phase table (FP64)
+};
+
+enum SymCode { SYM_GX = 0, SYM_GY = 1, SYM_GZ = 2, SYM_LAP = 3 };
+
+// ---------------------------------------------------------------- x passes
+struct RowsFwdArgs {
+  LinePlan plan;
+  int nlines;          // complex lines (row pairs)
+  int nx, E, H;        // physical, extended, half-spectrum length (E/2+1)
+  FcWalls fc;          // x-axis FC (on = 0 for a periodic x axis)
+  const double *inA, *inB;   // real rows (inB may be null)
+  long strideA, strideB;     // elements between consecutive lines
+  int nB;              // lines [0, nB) have a B row
+  void *outA, *outB;   // cpx<T> half-spectrum rows
+  long ostrideA, ostrideB;   // complex elements between consecutive lines
+  int B;               // line groups per workgroup
+  int ldsM;            // complex slots per line buffer
+};
+
+enum RowsEpi {
+  EPI_STORE = 0,       // store the two real outputs (scaled), T or double output
+  EPI_STEP_A2 = 1,     // 2D: u* from (Gx u, Gy u), (Gx v, Gy v), (L u, L v)
+  EPI_STEP_D2 = 2,     // 2D: projection from (Gx phi, Gy phi)
+  EPI_STEP_A3 = 3,     // 3D: u* from 12 derivatives in 6 packed lines
+  EPI_STEP_D3 = 4      // 3D: projection from 3 gradients in 2 packed lines
+};
+
+struct WallInfo {
+  int ndim;
+  int n[3];
+  int walled[3];
+  int dir[3][2];       // 1 if the velocity wall is Dirichlet
+};
+
+struct RowsInvArgs {
+  LinePlan plan;
+  int nrows;           // real rows handled (2D: ny, 3D: ny*nz)
+  int nx, E, H;
+  int B;               // line groups per workgroup
+  int ldsM;
+  // EPI_STORE: line l packs rows (2l, 2l+1) of one output spectrum array
+  const void *spec[6]; // cpx<T> spectrum row arrays (row pitch H)
+  long spec_pitch;     // complex elements per row
+  void *out[2];        // EPI_STORE outputs (row pitch nx)
+  int out_is_double;
+  double scale;
+  // step epilogues
+  const double *u[3], *f[3], *wall[3];
+  double *ustar[3];
+  double *unew[3];
+  double dt, nu, dt_over_rho;
+  WallInfo wi;
+};
+
+// ---------------------------------------------------------------- strided passes
+enum ColsMode { COLS_FWD = 0, COLS_OP = 1, COLS_INV = 2, COLS_DIV = 3 };
+
+struct ColsArgs {
+  LinePlan plan;
+  int mode;
+  int ninner;          // contiguous index count (half spectrum in x)
+  int nouter;          // outer lines (3D: the other transverse axis)
+  long es;             // element stride along the line (complex elements)
+  long os_in, os_out;  // outer stride of input / output arrays
+  long es_out;         // element stride of the output
+  int nload;           // values loaded per line (physical or extended length)
+  int nstore;          // values stored per line
+  FcWalls fc;          // FC along the line axis (COLS_FWD / COLS_OP / COLS_DIV)
+  // inputs / outputs (cpx<T>); blockIdx.y selects an input field for COLS_OP
+  const void *in[3];
+  void *out[3][4];
+  int nout;
+  int sym[4];          // symbol code per output (COLS_OP)
+  // symbol evaluation
+  SymTables st;
+  int line_axis;       // lattice axis of the line
+  int inner_axis;      // lattice axis of the inner index (x)
+  int outer_axis;      // lattice axis of the outer index (-1: none)
+  int B;               // lines (adjacent inner indices) per workgroup
+  int ldsM;
+};
+
+// ---------------------------------------------------------------- PPE passes
+enum TrigKind { TRIG_DFT = 0, TRIG_DCT1 = 1, TRIG_DST1 = 2 };
+
+struct PpeRowsArgs {
+  LinePlan plan;       // complex FFT of the extended trig length
+  int kind;            // TrigKind of the x axis
+  int inverse;         // 0: forward (real rows -> packed coefficients), 1: inverse
+  int nrows, nx;
+  int ncoef;           // coefficients per row (DCT1: n, DST1: n-2, DFT: n/2+1)
+  int cpitch;          // complex elements per coefficient row
+  int jlo;             // first unknown index (DST1: 1)
+  const double *in_real;   // forward input (double), or null when in_float used
+  const float *in_float;
+  void *coef;          // cpx<T> coefficient rows
+  double *out;         // inverse output (physical rows)
+  double scale;
+  int B, ldsM;
+};
+
+struct PpeColsArgs {
+  LinePlan plan;
+  int kind;            // TrigKind of the line axis
+  int ninner, nouter;
+  long es, os;         // strides in complex elements
+  int nline;           // physical points on the line axis
+  int ncoef;           // modes on the line axis
+  int jlo;             // first unknown index on the line axis
+  int solve;           // 1: forward, divide, inverse; 0: forward only; 2: inverse only
+  const double *mu_line;   // eigenvalues along the line
+  const double *mu_inner;  // eigenvalues along the inner axis
+  int inner_packed;        // inner index c holds modes (2c, 2c+1) in (re, im)
+  int inner_nmodes;
+  const double *mu_outer;  // eigenvalues along the outer axis (or null)
+  double scale;
+  void *data;          // cpx<T>, in place
+  int B, ldsM;
+};
+
+// ---------------------------------------------------------------- FC standalone
+struct FcExtArgs {
+  const double *in;
+  double *out;
+  int axis_len;        // physical length along the axis
+  long stride;         // element stride along the axis
+  long nlines;         // number of lines
+  long inner;          // lines are (outer, inner) with inner contiguous
+  long outer_stride_in, outer_stride_out;
+  long total_in_per_line_stride;
+  FcWalls fc;
+};
+
+// launchers (kernels.hip); return hipError_t
+hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s);
+hipError_t launch_rows_inv(const RowsInvArgs &a, int epi, bool fp32, hipStream_t s);
+hipError_t launch_cols(const ColsArgs &a, int ninputs_grid, bool fp32, hipStream_t s);
+hipError_t launch_ppe_rows(const PpeRowsArgs &a, bool fp32, hipStream_t s);
+hipError_t launch_ppe_cols(const PpeColsArgs &a, bool fp32, hipStream_t s);
+hipError_t launch_fc_extend_axis(const double *in, double *out, int ndim, const int *shape_in,
+                                 int axis, const FcWalls &fc, hipStream_t s);
+
+}  // namespace fcsph

@@ -1,0 +1,839 @@
+// HIP kernels of the FC(Gram)-based spectral ISPH step (gfx950).
+//
+// Pass structure of one spectral SPH operator on a 2D lattice (x fastest):
+//   rows_fwd : FC along x (FP64) + real-to-complex DFT of every row, two real
+//              rows packed into one complex line; writes the x half spectrum
+//   cols OP  : per x wavenumber, FC along y (FP64, on complex data) + DFT along
+//              y, multiplication by the operator symbol(s), inverse DFT along
+//              y, restriction to the physical rows
+//   rows_inv : inverse complex-to-real DFT along x, restriction to the
+//              physical columns, fused point-wise epilogue
+// 3D adds a forward and an inverse strided pass.  The PPE uses the same line
+// engine with even / odd extensions (DCT-I / DST-I) or plain DFTs.
+#include <algorithm>
+
+#include "fft_device.h"
+#include "internal.h"
+
+namespace fcsph {
+
+template <typename T>
+__device__ __forceinline__ cpx<T> to_cpx(double r, double i) {
+  return {static_cast<T>(r), static_cast<T>(i)};
+}
+
+// FC continuation value i (0-based, i < C) of a real line given by a
+// callback returning line values as double.
+template <typename Get>
+__device__ __forceinline__ double fc_cont(const FcWalls &fc, int n, int i, Get get) {
+  const double *hi = fc.Mhi + (size_t)i * fc.d;
+  const double *lo = fc.Mlo + (size_t)(fc.C - 1 - i) * fc.d;
+  double acc = 0.0;
+  for (int j = 0; j < fc.d; ++j) acc = fma(hi[j], get(n - fc.d + j), acc);
+  for (int j = 0; j < fc.d; ++j) acc = fma(lo[j], get(fc.d - 1 - j), acc);
+  return acc;
+}
+
+// ============================================================= rows forward
+template <typename T>
+__global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(RowsFwdArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
+  const int TL = a.plan.TL;
+  const int g = threadIdx.x / TL;
+  const int lt = threadIdx.x - g * TL;
+  const int line = blockIdx.x * a.B + g;
+  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  const bool active = line < a.nlines;
+  const double *pa = active ? a.inA + (size_t)line * a.strideA : nullptr;
+  const double *pb = (active && line < a.nB && a.inB) ? a.inB + (size_t)line * a.strideB : nullptr;
+  for (int j = lt; j < a.nx; j += TL)
+    buf[j] = to_cpx<T>(pa ? pa[j] : 0.0, pb ? pb[j] : 0.0);
+  if (a.fc.on) {
+    for (int i = lt; i < a.fc.C; i += TL) {
+      double ra = pa ? fc_cont(a.fc, a.nx, i, [&](int j) { return pa[j]; }) : 0.0;
+      double rb = pb ? fc_cont(a.fc, a.nx, i, [&](int j) { return pb[j]; }) : 0.0;
+      buf[a.nx + i] = to_cpx<T>(ra, rb);
+    }
+  }
+  __syncthreads();
+  line_dft<T>(buf, a.plan, lt, TL, false, false);
+  if (!active) return;
+  cpx<T> *oa = static_cast<cpx<T> *>(a.outA) + (size_t)line * a.ostrideA;
+  cpx<T> *ob = pb ? static_cast<cpx<T> *>(a.outB) + (size_t)line * a.ostrideB : nullptr;
+  const T half = T(0.5);
+  for (int k = lt; k < a.H; k += TL) {
+    const cpx<T> z = buf[k];
+    const cpx<T> zc = cconj(buf[k == 0 ? 0 : a.E - k]);
+    oa[k] = cscale(cadd(z, zc), half);
+    if (ob) ob[k] = cscale(cmi(csub(z, zc)), half);
+  }
+}
+
+// ============================================================= rows inverse
+__device__ __forceinline__ bool is_dirichlet_point(const WallInfo &w, int x, int y, int z) {
+  const int c[3] = {x, y, z};
+  for (int a = 0; a < w.ndim; ++a) {
+    if (!w.walled[a]) continue;
+    if (c[a] == 0 && w.dir[a][0]) return true;
+    if (c[a] == w.n[a] - 1 && w.dir[a][1]) return true;
+  }
+  return false;
+}
+
+// Load one packed complex line Z = A + i B from two half spectra (length H)
+// of a real length-E signal: Z[k] = A[k] + i B[k], Z[E-k] = conj(A[k]) + i conj(B[k]).
+template <typename T>
+__device__ __forceinline__ void load_packed_c2r(cpx<T> *buf, const cpx<T> *A, const cpx<T> *Bp,
+                                                int E, int H, int lt, int TL) {
+  for (int k = lt; k < H; k += TL) {
+    cpx<T> av = A ? A[k] : cpx<T>{T(0), T(0)};
+    cpx<T> bv = Bp ? Bp[k] : cpx<T>{T(0), T(0)};
+    const bool selfconj = (k == 0) || (2 * k == E);
+    if (selfconj) {
+      av.i = T(0);
+      bv.i = T(0);
+    }
+    buf[k] = {av.r - bv.i, av.i + bv.r};
+    if (!selfconj) buf[E - k] = {av.r + bv.i, bv.r - av.i};
+  }
+}
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
+  const int TL = a.plan.TL;
+  const int g = threadIdx.x / TL;
+  const int lt = threadIdx.x - g * TL;
+  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  const long P = a.spec_pitch;
+
+  if constexpr (EPI == EPI_STORE) {
+    // line = blockIdx.x * B + g; pack rows (2 line, 2 line + 1) of spec[0] when
+    // spec[1] is null, otherwise row `line` of spec[0] and spec[1]
+    const int line = blockIdx.x * a.B + g;
+    const bool pair = a.spec[1] != nullptr;
+    int rA = pair ? line : 2 * line;
+    int rB = pair ? line : 2 * line + 1;
+    const bool okA = rA < a.nrows, okB = rB < a.nrows;
+    const cpx<T> *sA = okA ? static_cast<const cpx<T> *>(a.spec[0]) + (size_t)rA * P : nullptr;
+    const cpx<T> *sB = okB ? static_cast<const cpx<T> *>(pair ? a.spec[1] : a.spec[0]) + (size_t)rB * P : nullptr;
+    load_packed_c2r<T>(buf, sA, sB, a.E, a.H, lt, TL);
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, true, true);
+    const int oB = pair ? 1 : 0;
+    for (int x = lt; x < a.nx; x += TL) {
+      const cpx<T> z = buf[x];
+      if (a.out_is_double) {
+        if (okA) static_cast<double *>(a.out[0])[(size_t)rA * a.nx + x] = a.scale * (double)z.r;
+        if (okB) static_cast<double *>(a.out[oB])[(size_t)rB * a.nx + x] = a.scale * (double)z.i;
+      } else {
+        if (okA) static_cast<float *>(a.out[0])[(size_t)rA * a.nx + x] = (float)(a.scale * (double)z.r);
+        if (okB) static_cast<float *>(a.out[oB])[(size_t)rB * a.nx + x] = (float)(a.scale * (double)z.i);
+      }
+    }
+  } else if constexpr (EPI == EPI_STEP_D2) {
+    const int row = blockIdx.x * a.B + g;
+    const bool ok = row < a.nrows;
+    const cpx<T> *sA = ok ? static_cast<const cpx<T> *>(a.spec[0]) + (size_t)row * P : nullptr;
+    const cpx<T> *sB = ok ? static_cast<const cpx<T> *>(a.spec[1]) + (size_t)row * P : nullptr;
+    load_packed_c2r<T>(buf, sA, sB, a.E, a.H, lt, TL);
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, true, true);
+    if (!ok) return;
+    const size_t ro = (size_t)row * a.nx;
+    for (int x = lt; x < a.nx; x += TL) {
+      double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)buf[x].r;
+      double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)buf[x].i;
+      if (is_dirichlet_point(a.wi, x, row, 0)) {
+        un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
+        vn = a.wall[1] ? a.wall[1][ro + x] : 0.0;
+      }
+      a.unew[0][ro + x] = un;
+      a.unew[1][ro + x] = vn;
+    }
+  } else {
+    // One row per workgroup; NL packed lines, processed by the workgroup's
+    // line groups in rounds (a group without a line in a round stays idle but
+    // keeps the barriers).  Line buffers: NL consecutive slots of ldsM.
+    //  A2: 0 (Gx u, Gy u) 1 (Gx v, Gy v) 2 (L u, L v)            from spec[2q], spec[2q+1]
+    //  A3: 0 (Gx u, Gy u) 1 (Gz u, Gx v) 2 (Gy v, Gz v) 3 (Gx w, Gy w) 4 (Gz w, L u) 5 (L v, L w)
+    //      from spec[q] and the spectrum that follows it at nrows * spec_pitch
+    //  D3: 0 (Gx p, Gy p) from spec[0], spec[1];  1 (Gz p, 0) from spec[2]
+    constexpr int NL = EPI == EPI_STEP_A2 ? 3 : EPI == EPI_STEP_A3 ? 6 : 2;
+    const int G = blockDim.x / TL;
+    const int row = blockIdx.x;
+    const size_t plane = (size_t)a.nrows * P;
+    for (int r0 = 0; r0 < NL; r0 += G) {
+      const int q = r0 + g;
+      const bool act = q < NL;
+      cpx<T> *lb = smem + (size_t)(act ? q : 0) * a.ldsM;
+      if (act) {
+        const cpx<T> *sA, *sB;
+        if constexpr (EPI == EPI_STEP_A2) {
+          sA = static_cast<const cpx<T> *>(a.spec[2 * q]) + (size_t)row * P;
+          sB = static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + (size_t)row * P;
+        } else if constexpr (EPI == EPI_STEP_A3) {
+          const cpx<T> *base = static_cast<const cpx<T> *>(a.spec[q]);
+          sA = base + (size_t)row * P;
+          sB = base + plane + (size_t)row * P;
+        } else {
+          sA = static_cast<const cpx<T> *>(a.spec[q == 0 ? 0 : 2]) + (size_t)row * P;
+          sB = q == 0 ? static_cast<const cpx<T> *>(a.spec[1]) + (size_t)row * P : nullptr;
+        }
+        load_packed_c2r<T>(lb, sA, sB, a.E, a.H, lt, TL);
+      }
+      __syncthreads();
+      line_dft<T>(lb, a.plan, lt, TL, true, true, act);
+    }
+    const size_t ro = (size_t)row * a.nx;
+    if constexpr (EPI == EPI_STEP_A2) {
+      const cpx<T> *b0 = smem, *b1 = smem + a.ldsM, *b2 = smem + 2 * (size_t)a.ldsM;
+      for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+        const double u = a.u[0][ro + x], v = a.u[1][ro + x];
+        const double gxu = b0[x].r, gyu = b0[x].i, gxv = b1[x].r, gyv = b1[x].i;
+        const double lu = b2[x].r, lv = b2[x].i;
+        const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
+        const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
+        double us = u - a.dt * (u * gxu + v * gyu - a.nu * lu - fx);
+        double vs = v - a.dt * (u * gxv + v * gyv - a.nu * lv - fy);
+        if (is_dirichlet_point(a.wi, x, row, 0)) {
+          us = a.wall[0] ? a.wall[0][ro + x] : 0.0;
+          vs = a.wall[1] ? a.wall[1][ro + x] : 0.0;
+        }
+        a.ustar[0][ro + x] = us;
+        a.ustar[1][ro + x] = vs;
+      }
+    } else if constexpr (EPI == EPI_STEP_A3) {
+      const cpx<T> *b[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) b[k] = smem + (size_t)k * a.ldsM;
+      const int y = row % a.wi.n[1], z = row / a.wi.n[1];
+      for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+        const double u = a.u[0][ro + x], v = a.u[1][ro + x], w = a.u[2][ro + x];
+        const double gxu = b[0][x].r, gyu = b[0][x].i, gzu = b[1][x].r;
+        const double gxv = b[1][x].i, gyv = b[2][x].r, gzv = b[2][x].i;
+        const double gxw = b[3][x].r, gyw = b[3][x].i, gzw = b[4][x].r;
+        const double lu = b[4][x].i, lv = b[5][x].r, lw = b[5][x].i;
+        const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
+        const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
+        const double fz = a.f[2] ? a.f[2][ro + x] : 0.0;
+        double us = u - a.dt * (u * gxu + v * gyu + w * gzu - a.nu * lu - fx);
+        double vs = v - a.dt * (u * gxv + v * gyv + w * gzv - a.nu * lv - fy);
+        double ws = w - a.dt * (u * gxw + v * gyw + w * gzw - a.nu * lw - fz);
+        if (is_dirichlet_point(a.wi, x, y, z)) {
+          us = a.wall[0] ? a.wall[0][ro + x] : 0.0;
+          vs = a.wall[1] ? a.wall[1][ro + x] : 0.0;
+          ws = a.wall[2] ? a.wall[2][ro + x] : 0.0;
+        }
+        a.ustar[0][ro + x] = us;
+        a.ustar[1][ro + x] = vs;
+        a.ustar[2][ro + x] = ws;
+      }
+    } else {
+      const cpx<T> *b0 = smem, *b1 = smem + a.ldsM;
+      const int y = row % a.wi.n[1], z = row / a.wi.n[1];
+      for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+        double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)b0[x].r;
+        double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)b0[x].i;
+        double wn = a.ustar[2][ro + x] - a.dt_over_rho * (double)b1[x].r;
+        if (is_dirichlet_point(a.wi, x, y, z)) {
+          un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
+          vn = a.wall[1] ? a.wall[1][ro + x] : 0.0;
+          wn = a.wall[2] ? a.wall[2][ro + x] : 0.0;
+        }
+        a.unew[0][ro + x] = un;
+        a.unew[1][ro + x] = vn;
+        a.unew[2][ro + x] = wn;
+      }
+    }
+  }
+}
+
+// ============================================================= strided passes
+// Phase factor exp(-2 pi i k s / E) from a per-axis table (s may be negative).
+__device__ __forceinline__ double2 phase(const double2 *ph, int k, int s) {
+  const int as = s < 0 ? -s : s;
+  double2 v = ph[(size_t)k * (kSymR + 1) + as];
+  if (s < 0) v.y = -v.y;
+  return v;
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Coefficients R[s] (s = -kSymR..kSymR along the line axis) of the symbol of
+// operator q at fixed wavenumbers of the transverse axes:
+//   S(k) = sum_s R[s] exp(-2 pi i k_line s / E_line).
+__device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
+  const double *W = a.st.W[q];
+  for (int s = 0; s < kSymW; ++s) R[s] = make_double2(0.0, 0.0);
+  if (a.st.ndim == 2) {
+    // W[(sy + R) * kSymW + (sx + R)]; line axis y, inner axis x
+    for (int sl = -kSymR; sl <= kSymR; ++sl) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int si = -kSymR; si <= kSymR; ++si) {
+        const int li = (a.line_axis == 1) ? (sl + kSymR) * kSymW + (si + kSymR)
+                                          : (si + kSymR) * kSymW + (sl + kSymR);
+        const double w = W[li];
+        if (w == 0.0) continue;
+        const double2 p = phase(a.st.ph[a.inner_axis], kin, si);
+        acc.x += w * p.x;
+        acc.y += w * p.y;
+      }
+      R[sl + kSymR] = acc;
+    }
+  } else {
+    // W[(sz + R) * kSymW^2 + (sy + R) * kSymW + (sx + R)]
+    int off[3];
+    for (int sl = -kSymR; sl <= kSymR; ++sl) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int si = -kSymR; si <= kSymR; ++si) {
+        const double2 pi_ = phase(a.st.ph[a.inner_axis], kin, si);
+        for (int so = -kSymR; so <= kSymR; ++so) {
+          off[a.line_axis] = sl;
+          off[a.inner_axis] = si;
+          off[a.outer_axis] = so;
+          const double w = W[(off[2] + kSymR) * kSymW * kSymW + (off[1] + kSymR) * kSymW + (off[0] + kSymR)];
+          if (w == 0.0) continue;
+          const double2 p = zmul(pi_, phase(a.st.ph[a.outer_axis], kout, so));
+          acc.x += w * p.x;
+          acc.y += w * p.y;
+        }
+      }
+      R[sl + kSymR] = acc;
+    }
+  }
+}
+
+__device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
+  double2 acc = R[kSymR];
+  for (int s = 1; s <= kSymR; ++s) {
+    const double2 p = ph_line[(size_t)k * (kSymR + 1) + s];   // exp(-2 pi i k s / E)
+    const double2 rp = R[kSymR + s], rm = R[kSymR - s];
+    // rp * p + rm * conj(p)
+    acc.x += (rp.x + rm.x) * p.x - (rp.y - rm.y) * p.y;
+    acc.y += (rp.x - rm.x) * p.y + (rp.y + rm.y) * p.x;
+  }
+  return acc;
+}
+
+constexpr int kXMax = 8;   // spectrum values kept in registers per thread
+
+template <typename T>
+__device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const cpx<T> *in,
+                                          int c0, size_t obase, int n) {
+  for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
+    const int l = idx % a.B, j = idx / a.B;
+    const int c = c0 + l;
+    cpx<T> v = {T(0), T(0)};
+    if (c < a.ninner) v = in[obase + (size_t)j * a.es + c];
+    smem[(size_t)l * a.ldsM + j] = v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem, cpx<T> *out,
+                                           int c0, size_t obase, int n) {
+  for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
+    const int l = idx % a.B, j = idx / a.B;
+    const int c = c0 + l;
+    if (c < a.ninner) out[obase + (size_t)j * a.es_out + c] = smem[(size_t)l * a.ldsM + j];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void cols_fc(const ColsArgs &a, cpx<T> *buf, int lt, int TL) {
+  const int n = a.nload;
+  for (int i = lt; i < a.fc.C; i += TL) {
+    const double re = fc_cont(a.fc, n, i, [&](int j) { return (double)buf[j].r; });
+    const double im = fc_cont(a.fc, n, i, [&](int j) { return (double)buf[j].i; });
+    buf[n + i] = to_cpx<T>(re, im);
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kMaxThreads) k_cols(ColsArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
+  const int TL = a.plan.TL;
+  const int g = threadIdx.x / TL;
+  const int lt = threadIdx.x - g * TL;
+  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  const int npanel = (a.ninner + a.B - 1) / a.B;
+  const int o = blockIdx.x / npanel;
+  const int c0 = (blockIdx.x - o * npanel) * a.B;
+  const int c = c0 + g;
+  const size_t obase_in = (size_t)o * a.os_in, obase_out = (size_t)o * a.os_out;
+  const int E = a.plan.n;
+  const double2 *ph_line = a.st.ph[a.line_axis];
+
+  if constexpr (MODE == COLS_FWD || MODE == COLS_INV) {
+    const cpx<T> *in = static_cast<const cpx<T> *>(a.in[0]);
+    cols_load<T>(a, smem, in, c0, obase_in, a.nload);
+    __syncthreads();
+    if (MODE == COLS_FWD && a.fc.on) {
+      cols_fc<T>(a, buf, lt, TL);
+      __syncthreads();
+    }
+    constexpr bool inv = MODE == COLS_INV;
+    line_dft<T>(buf, a.plan, lt, TL, inv, inv);
+    cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[0][0]), c0, obase_out, a.nstore);
+  } else if constexpr (MODE == COLS_OP) {
+    const int f = blockIdx.y;
+    const cpx<T> *in = static_cast<const cpx<T> *>(a.in[f]);
+    cols_load<T>(a, smem, in, c0, obase_in, a.nload);
+    __syncthreads();
+    if (a.fc.on) {
+      cols_fc<T>(a, buf, lt, TL);
+      __syncthreads();
+    }
+    line_dft<T>(buf, a.plan, lt, TL, false, false);
+    cpx<T> X[kXMax];
+#pragma unroll
+    for (int m = 0; m < kXMax; ++m) {
+      const int k = lt + m * TL;
+      X[m] = k < E ? buf[k] : cpx<T>{T(0), T(0)};
+    }
+    for (int q = 0; q < a.nout; ++q) {
+      double2 R[kSymW];
+      sym_line_coeffs(a, a.sym[q], c < a.ninner ? c : 0, o, R);
+      __syncthreads();   // the previous output's store has finished reading buf
+#pragma unroll
+      for (int m = 0; m < kXMax; ++m) {
+        const int k = lt + m * TL;
+        if (k < E) {
+          const double2 sv = sym_eval(R, ph_line, k);
+          buf[k] = cmul(to_cpx<T>(sv.x, sv.y), X[m]);
+        }
+      }
+      __syncthreads();
+      line_dft<T>(buf, a.plan, lt, TL, true, true);
+      cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][q]), c0, obase_out, a.nstore);
+    }
+  } else {
+    // COLS_DIV: out = sum_f S_f DFT(FC(in_f)), one output
+    cpx<T> acc[kXMax];
+#pragma unroll
+    for (int m = 0; m < kXMax; ++m) acc[m] = {T(0), T(0)};
+    const int nin = a.st.ndim;
+    for (int f = 0; f < nin; ++f) {
+      __syncthreads();
+      cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[f]), c0, obase_in, a.nload);
+      __syncthreads();
+      if (a.fc.on) {
+        cols_fc<T>(a, buf, lt, TL);
+        __syncthreads();
+      }
+      line_dft<T>(buf, a.plan, lt, TL, false, false);
+      double2 R[kSymW];
+      sym_line_coeffs(a, a.sym[f], c < a.ninner ? c : 0, o, R);
+#pragma unroll
+      for (int m = 0; m < kXMax; ++m) {
+        const int k = lt + m * TL;
+        if (k < E) {
+          const double2 sv = sym_eval(R, ph_line, k);
+          acc[m] = cadd(acc[m], cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kXMax; ++m) {
+      const int k = lt + m * TL;
+      if (k < E) buf[k] = acc[m];
+    }
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, true, true);
+    cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[0][0]), c0, obase_out, a.nstore);
+  }
+}
+
+// ============================================================= PPE rows
+// Coefficient row layout: DCT-I / DST-I rows are real; coefficient m of a row
+// is stored in component (m & 1) of complex slot m >> 1.  DFT rows are complex
+// half spectra.
+template <typename T>
+__device__ __forceinline__ void put_real_coef(cpx<T> *row, int m, T v) {
+  T *p = reinterpret_cast<T *>(row + (m >> 1));
+  p[m & 1] = v;
+}
+template <typename T>
+__device__ __forceinline__ T get_real_coef(const cpx<T> *row, int m) {
+  const T *p = reinterpret_cast<const T *>(row + (m >> 1));
+  return p[m & 1];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
+  const int TL = a.plan.TL;
+  const int g = threadIdx.x / TL;
+  const int lt = threadIdx.x - g * TL;
+  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  const int line = blockIdx.x * a.B + g;
+  const int rA = 2 * line, rB = 2 * line + 1;
+  const bool okA = rA < a.nrows, okB = rB < a.nrows;
+  const int n = a.nx, L = a.plan.n;
+  cpx<T> *cA = static_cast<cpx<T> *>(a.coef) + (size_t)rA * a.cpitch;
+  cpx<T> *cB = static_cast<cpx<T> *>(a.coef) + (size_t)rB * a.cpitch;
+
+  if (!a.inverse) {
+    auto val = [&](int r, int j) -> double {
+      const size_t o = (size_t)r * n + j;
+      return a.in_real ? a.in_real[o] : (double)a.in_float[o];
+    };
+    if (a.kind == TRIG_DFT) {
+      for (int j = lt; j < n; j += TL)
+        buf[j] = to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0);
+    } else if (a.kind == TRIG_DCT1) {
+      // even extension of length 2(n-1)
+      for (int j = lt; j < L; j += TL) {
+        const int s = j < n ? j : L - j;
+        buf[j] = to_cpx<T>(okA ? val(rA, s) : 0.0, okB ? val(rB, s) : 0.0);
+      }
+    } else {
+      // odd extension of the interior values, length 2(n-1)
+      for (int j = lt; j < L; j += TL) {
+        double va = 0.0, vb = 0.0, sg = 1.0;
+        int s = j;
+        if (j > n - 1) {
+          s = L - j;
+          sg = -1.0;
+        }
+        if (s > 0 && s < n - 1) {
+          va = okA ? sg * val(rA, s) : 0.0;
+          vb = okB ? sg * val(rB, s) : 0.0;
+        }
+        buf[j] = to_cpx<T>(va, vb);
+      }
+    }
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, false, false);
+    if (a.kind == TRIG_DFT) {
+      const T half = T(0.5);
+      for (int k = lt; k < a.ncoef; k += TL) {
+        const cpx<T> z = buf[k], zc = cconj(buf[k == 0 ? 0 : n - k]);
+        if (okA) cA[k] = cscale(cadd(z, zc), half);
+        if (okB) cB[k] = cscale(cmi(csub(z, zc)), half);
+      }
+    } else if (a.kind == TRIG_DCT1) {
+      for (int k = lt; k < a.ncoef; k += TL) {
+        if (okA) put_real_coef<T>(cA, k, buf[k].r);
+        if (okB) put_real_coef<T>(cB, k, buf[k].i);
+      }
+    } else {
+      // Z = -i S_a + S_b: S_a = -Im Z, S_b = Re Z, modes 1..n-2 stored at m - 1
+      for (int k = lt; k < a.ncoef; k += TL) {
+        const cpx<T> z = buf[k + 1];
+        if (okA) put_real_coef<T>(cA, k, -z.i);
+        if (okB) put_real_coef<T>(cB, k, z.r);
+      }
+    }
+    return;
+  }
+
+  // inverse: coefficient rows -> physical rows (scaled)
+  if (a.kind == TRIG_DFT) {
+    load_packed_c2r<T>(buf, okA ? cA : nullptr, okB ? cB : nullptr, n, a.ncoef, lt, TL);
+  } else if (a.kind == TRIG_DCT1) {
+    for (int j = lt; j < L; j += TL) {
+      const int s = j < n ? j : L - j;
+      buf[j] = {okA ? get_real_coef<T>(cA, s) : T(0), okB ? get_real_coef<T>(cB, s) : T(0)};
+    }
+  } else {
+    for (int j = lt; j < L; j += TL) {
+      T va = T(0), vb = T(0);
+      int s = j;
+      T sg = T(1);
+      if (j > n - 1) {
+        s = L - j;
+        sg = T(-1);
+      }
+      if (s > 0 && s < n - 1) {
+        va = okA ? sg * get_real_coef<T>(cA, s - 1) : T(0);
+        vb = okB ? sg * get_real_coef<T>(cB, s - 1) : T(0);
+      }
+      buf[j] = {va, vb};
+    }
+  }
+  __syncthreads();
+  const bool inv = a.kind == TRIG_DFT;
+  line_dft<T>(buf, a.plan, lt, TL, inv, inv);
+  for (int x = lt; x < n; x += TL) {
+    double va, vb;
+    if (a.kind == TRIG_DST1) {
+      const bool wall = (x == 0 || x == n - 1);
+      va = wall ? 0.0 : -(double)buf[x].i;
+      vb = wall ? 0.0 : (double)buf[x].r;
+    } else {
+      va = (double)buf[x].r;
+      vb = (double)buf[x].i;
+    }
+    if (okA) a.out[(size_t)rA * n + x] = a.scale * va;
+    if (okB) a.out[(size_t)rB * n + x] = a.scale * vb;
+  }
+}
+
+// ============================================================= PPE strided pass
+// Symmetric extension of buf[0..n) to length L and transform.  Coefficients
+// (is_values = false) or values (true) of the complex line end up in buf[0..n).
+template <typename T>
+__device__ __forceinline__ void ppe_line_transform(cpx<T> *buf, const PpeColsArgs &a, int lt, int TL,
+                                                   bool is_values) {
+  const int n = a.nline, L = a.plan.n;
+  if (a.kind == TRIG_DCT1) {
+    for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, false, false);
+  } else if (a.kind == TRIG_DST1) {
+    // odd extension: positions 0 and n-1 are zero, j > n-1 holds -buf[L-j]
+    if (lt == 0) {
+      buf[0] = {T(0), T(0)};
+      buf[n - 1] = {T(0), T(0)};
+    }
+    for (int j = n + lt; j < L; j += TL) {
+      const cpx<T> v = buf[L - j];
+      buf[j] = {-v.r, -v.i};
+    }
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, false, false);
+    // the DST-I of the complex line is i Z
+    for (int j = lt; j < n; j += TL) buf[j] = cpi(buf[j]);
+    if (is_values && lt == 0) {
+      buf[0] = {T(0), T(0)};
+      buf[n - 1] = {T(0), T(0)};
+    }
+    __syncthreads();
+  } else {
+    line_dft<T>(buf, a.plan, lt, TL, is_values, is_values);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(PpeColsArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
+  const int TL = a.plan.TL;
+  const int g = threadIdx.x / TL;
+  const int lt = threadIdx.x - g * TL;
+  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  const int npanel = (a.ninner + a.B - 1) / a.B;
+  const int o = blockIdx.x / npanel;
+  const int c0 = (blockIdx.x - o * npanel) * a.B;
+  const int c = c0 + g;
+  cpx<T> *data = static_cast<cpx<T> *>(a.data) + (size_t)o * a.os;
+  const int n = a.nline;
+
+  for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
+    const int l = idx % a.B, j = idx / a.B;
+    const int cc = c0 + l;
+    cpx<T> v = {T(0), T(0)};
+    if (cc < a.ninner) v = data[(size_t)j * a.es + cc];
+    smem[(size_t)l * a.ldsM + j] = v;
+  }
+  __syncthreads();
+  ppe_line_transform<T>(buf, a, lt, TL, a.solve == 2);
+  if (a.solve == 1) {
+    // divide by -(mu_inner + mu_line + mu_outer) in FP64; a vanishing sum
+    // (the constant mode) gives zero
+    const double mo = a.mu_outer ? a.mu_outer[o] : 0.0;
+    double mir = 0.0, mii = 0.0;
+    if (c < a.ninner) {
+      if (a.inner_packed) {
+        mir = a.mu_inner[2 * c];
+        mii = (2 * c + 1 < a.inner_nmodes) ? a.mu_inner[2 * c + 1] : 1.0;
+      } else {
+        mir = mii = a.mu_inner[c];
+      }
+    }
+    for (int k = lt; k < n; k += TL) {
+      const bool valid = a.kind != TRIG_DST1 || (k >= 1 && k <= n - 2);
+      const double ml = valid ? a.mu_line[k] + mo : 0.0;
+      const double sr = mir + ml, si = mii + ml;
+      const cpx<T> v = buf[k];
+      const double vr = (valid && sr != 0.0) ? -(double)v.r / sr : 0.0;
+      const double vi = (valid && si != 0.0) ? -(double)v.i / si : 0.0;
+      buf[k] = to_cpx<T>(vr * a.scale, vi * a.scale);
+    }
+    __syncthreads();
+    ppe_line_transform<T>(buf, a, lt, TL, true);
+  }
+  for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
+    const int l = idx % a.B, j = idx / a.B;
+    const int cc = c0 + l;
+    if (cc < a.ninner) data[(size_t)j * a.es + cc] = smem[(size_t)l * a.ldsM + j];
+  }
+}
+
+// ============================================================= FC standalone
+// Array viewed as [outer][len][inner]; output [outer][len + C][inner].
+__global__ void k_fc_extend(const double *in, double *out, long outer, int len, long inner,
+                            FcWalls fc) {
+  const long Lo = len + fc.C;
+  const long total = outer * Lo * inner;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long c = idx % inner;
+    const long j = (idx / inner) % Lo;
+    const long o = idx / (inner * Lo);
+    const double *line = in + o * len * inner + c;
+    double v;
+    if (j < len) {
+      v = line[j * inner];
+    } else {
+      v = fc_cont(fc, len, (int)(j - len), [&](int jj) { return line[(long)jj * inner]; });
+    }
+    out[idx] = v;
+  }
+}
+
+// ============================================================= launchers
+static size_t lds_bytes(int B, int ldsM, bool fp32) {
+  return (size_t)B * ldsM * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
+}
+
+template <typename K>
+static hipError_t set_lds(K kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s) {
+  const dim3 grid((a.nlines + a.B - 1) / a.B), block(a.B * a.plan.TL);
+  const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
+  hipError_t e;
+  if (fp32) {
+    if ((e = set_lds(k_rows_fwd<float>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rows_fwd<float>, grid, block, lds, s, a);
+  } else {
+    if ((e = set_lds(k_rows_fwd<double>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rows_fwd<double>, grid, block, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int EPI>
+static hipError_t rows_inv_t(const RowsInvArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  hipError_t e = set_lds(k_rows_inv<T, EPI>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_rows_inv<T, EPI>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t rows_inv_dispatch(const RowsInvArgs &a, int epi, hipStream_t s) {
+  const int TL = a.plan.TL;
+  dim3 grid, block;
+  size_t lds;
+  switch (epi) {
+    case EPI_STORE: {
+      const bool pair = a.spec[1] != nullptr;
+      const int nl = pair ? a.nrows : (a.nrows + 1) / 2;
+      grid = dim3((nl + a.B - 1) / a.B);
+      block = dim3(a.B * TL);
+      lds = lds_bytes(a.B, a.ldsM, sizeof(T) == 4);
+      return rows_inv_t<T, EPI_STORE>(a, grid, block, lds, s);
+    }
+    case EPI_STEP_D2:
+      grid = dim3((a.nrows + a.B - 1) / a.B);
+      block = dim3(a.B * TL);
+      lds = lds_bytes(a.B, a.ldsM, sizeof(T) == 4);
+      return rows_inv_t<T, EPI_STEP_D2>(a, grid, block, lds, s);
+    case EPI_STEP_A2:
+    case EPI_STEP_A3:
+    case EPI_STEP_D3: {
+      const int NL = epi == EPI_STEP_A2 ? 3 : epi == EPI_STEP_A3 ? 6 : 2;
+      const int G = std::max(1, std::min(NL, kMaxThreads / TL));
+      grid = dim3(a.nrows);
+      block = dim3(G * TL);
+      lds = lds_bytes(NL, a.ldsM, sizeof(T) == 4);
+      if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+      if (epi == EPI_STEP_A2) return rows_inv_t<T, EPI_STEP_A2>(a, grid, block, lds, s);
+      if (epi == EPI_STEP_A3) return rows_inv_t<T, EPI_STEP_A3>(a, grid, block, lds, s);
+      return rows_inv_t<T, EPI_STEP_D3>(a, grid, block, lds, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rows_inv(const RowsInvArgs &a, int epi, bool fp32, hipStream_t s) {
+  return fp32 ? rows_inv_dispatch<float>(a, epi, s) : rows_inv_dispatch<double>(a, epi, s);
+}
+
+template <typename T, int MODE>
+static hipError_t cols_t(const ColsArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  hipError_t e = set_lds(k_cols<T, MODE>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cols<T, MODE>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t cols_dispatch(const ColsArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  switch (a.mode) {
+    case COLS_FWD: return cols_t<T, COLS_FWD>(a, grid, block, lds, s);
+    case COLS_INV: return cols_t<T, COLS_INV>(a, grid, block, lds, s);
+    case COLS_OP: return cols_t<T, COLS_OP>(a, grid, block, lds, s);
+    case COLS_DIV: return cols_t<T, COLS_DIV>(a, grid, block, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s) {
+  const int npanel = (a.ninner + a.B - 1) / a.B;
+  const dim3 grid(npanel * a.nouter, ngrid_y), block(a.B * a.plan.TL);
+  const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
+  return fp32 ? cols_dispatch<float>(a, grid, block, lds, s) : cols_dispatch<double>(a, grid, block, lds, s);
+}
+
+hipError_t launch_ppe_rows(const PpeRowsArgs &a, bool fp32, hipStream_t s) {
+  const int nl = (a.nrows + 1) / 2;
+  const dim3 grid((nl + a.B - 1) / a.B), block(a.B * a.plan.TL);
+  const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
+  hipError_t e;
+  if (fp32) {
+    if ((e = set_lds(k_ppe_rows<float>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ppe_rows<float>, grid, block, lds, s, a);
+  } else {
+    if ((e = set_lds(k_ppe_rows<double>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ppe_rows<double>, grid, block, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ppe_cols(const PpeColsArgs &a, bool fp32, hipStream_t s) {
+  const int npanel = (a.ninner + a.B - 1) / a.B;
+  const dim3 grid(npanel * a.nouter), block(a.B * a.plan.TL);
+  const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
+  hipError_t e;
+  if (fp32) {
+    if ((e = set_lds(k_ppe_cols<float>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ppe_cols<float>, grid, block, lds, s, a);
+  } else {
+    if ((e = set_lds(k_ppe_cols<double>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ppe_cols<double>, grid, block, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fc_extend_axis(const double *in, double *out, int ndim, const int *shape_in,
+                                 int axis, const FcWalls &fc, hipStream_t s) {
+  // shape_in in lattice order (x, y, z); axis in lattice order
+  long inner = 1, outer = 1;
+  for (int a = 0; a < axis; ++a) inner *= shape_in[a];
+  for (int a = axis + 1; a < ndim; ++a) outer *= shape_in[a];
+  const int len = shape_in[axis];
+  const long total = outer * (long)(len + fc.C) * inner;
+  const int block = 256;
+  long nblk = (total + block - 1) / block;
+  if (nblk > 65535L * 16) nblk = 65535L * 16;
+  hipLaunchKernelGGL(k_fc_extend, dim3((unsigned)nblk), dim3(block), 0, s, in, out, outer, len,
+                     inner, fc);
+  return hipGetLastError();
+}
+
+}  // namespace fcsph
