@@ -99,6 +99,19 @@ const char *fcsph_status_string(fcsph_status s);
 /* Text of the last error on this context (never NULL). */
 const char *fcsph_ctx_last_error(fcsph_ctx *c);
 
+/*
+ * Kernel timing (a profiling aid, not part of the method).  While enabled,
+ * every kernel the library launches on this context is bracketed by two HIP
+ * events recorded on the context stream.  fcsph_ctx_read_timing waits for the
+ * stream, aggregates the elapsed times by kernel kind since the last read and
+ * clears the record: for up to `cap` kinds it writes a NUL-terminated name
+ * (at most 31 characters) into names + 32 * i, the launch count and the total
+ * milliseconds; *n receives the number of kinds written.
+ */
+fcsph_status fcsph_ctx_set_timing(fcsph_ctx *c, int enable);
+fcsph_status fcsph_ctx_read_timing(fcsph_ctx *c, int cap, char *names, int *counts,
+                                   double *total_ms, int *n);
+
 /* Bytes of device workspace a plan for *d needs (tables + scratch); the
  * workspace must be 256-byte aligned. */
 fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes);

@@ -34,7 +34,8 @@ EXPORTS = [
     "fcsph_ctx_create", "fcsph_ctx_destroy", "fcsph_ctx_sync", "fcsph_status_string",
     "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
     "fcsph_plan_destroy", "fcsph_fc_extend", "fcsph_spectral_grad", "fcsph_spectral_div",
-    "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step",
+    "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_ctx_set_timing",
+    "fcsph_ctx_read_timing",
 ]
 
 
@@ -78,6 +79,8 @@ def lib() -> ctypes.CDLL:
     L.fcsph_spectral_lap.argtypes = [vp, i, vp, vp]
     L.fcsph_ppe_solve.argtypes = [vp, vp, vp]
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
+    L.fcsph_ctx_set_timing.argtypes = [vp, i]
+    L.fcsph_ctx_read_timing.argtypes = [vp, i, ctypes.c_char_p, P(i), P(d), P(i)]
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:
@@ -147,6 +150,24 @@ class Context:
 
     def sync(self):
         _check(lib().fcsph_ctx_sync(self.handle), self.handle, "fcsph_ctx_sync")
+
+    def set_timing(self, on: bool):
+        _check(lib().fcsph_ctx_set_timing(self.handle, int(bool(on))), self.handle, "set_timing")
+
+    def read_timing(self) -> dict:
+        """{kernel kind: (launches, total ms)} since the last read (waits for the stream)."""
+        cap = 64
+        names = ctypes.create_string_buffer(32 * cap)
+        counts = (ctypes.c_int * cap)()
+        tot = (ctypes.c_double * cap)()
+        n = ctypes.c_int()
+        _check(lib().fcsph_ctx_read_timing(self.handle, cap, names, counts, tot, ctypes.byref(n)),
+               self.handle, "read_timing")
+        out = {}
+        for k in range(n.value):
+            name = names.raw[32 * k:32 * (k + 1)].split(b"\0")[0].decode()
+            out[name] = (counts[k], tot[k])
+        return out
 
     def __del__(self):
         try:

@@ -16,11 +16,52 @@
 
 using namespace fcsph;
 
+struct TimedLaunch {
+  const char *name;
+  hipEvent_t start, stop;
+};
+
 struct fcsph_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
+  bool timing = false;
+  std::vector<TimedLaunch> launches;     // recorded while timing is on
+  std::vector<hipEvent_t> event_pool;    // reusable events
 };
+
+namespace {
+hipEvent_t pool_event(fcsph_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when the context records timings.
+struct LaunchTimer {
+  fcsph_ctx *c;
+  const char *name;
+  hipEvent_t a = nullptr, b = nullptr;
+  LaunchTimer(fcsph_ctx *ctx, const char *n) : c(ctx), name(n) {
+    if (c && c->timing) {
+      a = pool_event(c);
+      b = pool_event(c);
+      if (a) hipEventRecord(a, c->stream);
+    }
+  }
+  ~LaunchTimer() {
+    if (a && b) {
+      hipEventRecord(b, c->stream);
+      c->launches.push_back({name, a, b});
+    }
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -487,6 +528,7 @@ hipError_t x_fwd_single(fcsph_plan *p, const double *f, int fc, void *S) {
   a.ostrideA = a.ostrideB = 2L * p->H;
   a.B = pick_B(a.plan, p->fp32, 4);
   a.ldsM = a.plan.M;
+  LaunchTimer t(p->ctx, "rows_fwd");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
 }
 
@@ -509,6 +551,7 @@ hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc,
   a.ostrideA = a.ostrideB = p->H;
   a.B = pick_B(a.plan, p->fp32, 4);
   a.ldsM = a.plan.M;
+  LaunchTimer t(p->ctx, "rows_fwd_pair");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
 }
 
@@ -534,6 +577,11 @@ ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
   return c;
 }
 
+hipError_t cols_launch(fcsph_plan *p, const ColsArgs &c, int gy, const char *name) {
+  LaunchTimer t(p->ctx, name);
+  return launch_cols(c, gy, p->fp32, p->ctx->stream);
+}
+
 hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void *out0, void *out1,
                        bool out_double, double scale) {
   RowsInvArgs a{};
@@ -551,6 +599,7 @@ hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void
   a.out[1] = out1;
   a.out_is_double = out_double ? 1 : 0;
   a.scale = scale;
+  LaunchTimer t(p->ctx, "rows_inv_store");
   return launch_rows_inv(a, EPI_STORE, p->fp32, p->ctx->stream);
 }
 
@@ -586,7 +635,10 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.coef = p->coef;
   r.B = pick_B(r.plan, f32, 4);
   r.ldsM = r.plan.M;
-  if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
+  {
+    LaunchTimer t(p->ctx, "ppe_rows_fwd");
+    if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
+  }
   // P2: columns forward, divide, inverse
   PpeColsArgs c{};
   c.plan = p->trig[1];
@@ -607,14 +659,20 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   c.data = p->coef;
   c.B = pick_B(c.plan, f32, 4);
   c.ldsM = c.plan.M;
-  if (!chk(p, launch_ppe_cols(c, f32, p->ctx->stream), "ppe cols", st)) return st;
+  {
+    LaunchTimer t(p->ctx, "ppe_cols_solve");
+    if (!chk(p, launch_ppe_cols(c, f32, p->ctx->stream), "ppe cols", st)) return st;
+  }
   // P3: rows inverse
   r.inverse = 1;
   r.in_real = nullptr;
   r.in_float = nullptr;
   r.out = phi;
   r.scale = p->trig_kind[0] == TRIG_DFT ? 1.0 / p->n[0] : 1.0 / (2.0 * (p->n[0] - 1));
-  if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows inverse", st)) return st;
+  {
+    LaunchTimer t(p->ctx, "ppe_rows_inv");
+    if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows inverse", st)) return st;
+  }
   return FCSPH_OK;
 }
 
@@ -653,6 +711,12 @@ fcsph_status fcsph_ctx_create(int device, void *hip_stream, fcsph_ctx **out) {
 }
 
 fcsph_status fcsph_ctx_destroy(fcsph_ctx *c) {
+  if (!c) return FCSPH_OK;
+  for (auto &l : c->launches) {
+    hipEventDestroy(l.start);
+    hipEventDestroy(l.stop);
+  }
+  for (auto e : c->event_pool) hipEventDestroy(e);
   delete c;
   return FCSPH_OK;
 }
@@ -667,6 +731,46 @@ fcsph_status fcsph_ctx_sync(fcsph_ctx *c) {
 }
 
 const char *fcsph_ctx_last_error(fcsph_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+
+fcsph_status fcsph_ctx_set_timing(fcsph_ctx *c, int enable) {
+  if (!c) return FCSPH_E_INVALID;
+  c->timing = enable != 0;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_ctx_read_timing(fcsph_ctx *c, int cap, char *names, int *counts, double *total_ms,
+                                   int *n) {
+  if (!c || !n || cap < 0 || (cap > 0 && (!names || !counts || !total_ms))) return FCSPH_E_INVALID;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+  std::vector<std::string> kinds;
+  std::vector<int> cnt;
+  std::vector<double> tot;
+  for (auto &l : c->launches) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, l.start, l.stop);
+    size_t k = 0;
+    while (k < kinds.size() && kinds[k] != l.name) ++k;
+    if (k == kinds.size()) {
+      kinds.push_back(l.name);
+      cnt.push_back(0);
+      tot.push_back(0.0);
+    }
+    cnt[k] += 1;
+    tot[k] += ms;
+    c->event_pool.push_back(l.start);
+    c->event_pool.push_back(l.stop);
+  }
+  c->launches.clear();
+  int w = 0;
+  for (size_t k = 0; k < kinds.size() && w < cap; ++k, ++w) {
+    std::snprintf(names + 32 * w, 32, "%s", kinds[k].c_str());
+    counts[w] = cnt[k];
+    total_ms[w] = tot[k];
+  }
+  *n = w;
+  return FCSPH_OK;
+}
 
 fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes) {
   if (!bytes) return FCSPH_E_INVALID;
@@ -748,6 +852,7 @@ fcsph_status fcsph_fc_extend(fcsph_plan *p, int fc, const double *f, double *f_e
     if (!p->walled[a]) continue;
     double *dst = (a == last) ? f_ext : p->ext_scratch;
     FcWalls w = walls_for(p, a, fc);
+    LaunchTimer t(p->ctx, "fc_extend");
     if (!chk(p, launch_fc_extend_axis(src, dst, p->nd, shape, a, w, p->ctx->stream), "fc_extend", st)) return st;
     shape[a] += p->d.fc_C;
     src = dst;
@@ -770,7 +875,7 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
   c.nout = 2;
   c.sym[0] = SYM_GX;
   c.sym[1] = SYM_GY;
-  if (!chk(p, launch_cols(c, 1, p->fp32, p->ctx->stream), "grad y", st)) return st;
+  if (!chk(p, cols_launch(p, c, 1, "cols_op"), "grad y", st)) return st;
   if (!chk(p, x_inv_store(p, p->O[0], p->O[1], g[0], g[1], !p->fp32, 1.0), "grad x inv", st)) return st;
   return FCSPH_OK;
 }
@@ -786,7 +891,7 @@ fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *la
   c.out[0][0] = p->O[0];
   c.nout = 1;
   c.sym[0] = SYM_LAP;
-  if (!chk(p, launch_cols(c, 1, p->fp32, p->ctx->stream), "lap y", st)) return st;
+  if (!chk(p, cols_launch(p, c, 1, "cols_op"), "lap y", st)) return st;
   if (!chk(p, x_inv_store(p, p->O[0], nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
   return FCSPH_OK;
 }
@@ -802,7 +907,7 @@ static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, 
   c.nout = 1;
   c.sym[0] = SYM_GX;
   c.sym[1] = SYM_GY;
-  if (!chk(p, launch_cols(c, 1, p->fp32, p->ctx->stream), "div y", st)) return st;
+  if (!chk(p, cols_launch(p, c, 1, "cols_div"), "div y", st)) return st;
   if (!chk(p, x_inv_store(p, p->O[0], nullptr, out, nullptr, out_double, scale), "div x inv", st)) return st;
   return FCSPH_OK;
 }
@@ -849,7 +954,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   c.sym[0] = SYM_GX;
   c.sym[1] = SYM_GY;
   c.sym[2] = SYM_LAP;
-  if (!chk(p, launch_cols(c, 2, f32, s), "step A y", st)) return st;
+  if (!chk(p, cols_launch(p, c, 2, "cols_op_step_a"), "step A y", st)) return st;
   RowsInvArgs r{};
   r.plan = p->op[0];
   r.nrows = p->n[1];
@@ -879,7 +984,10 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   r.wi = wall_info(p);
   if (3ull * r.ldsM * (f32 ? 8 : 16) > (size_t)kMaxLds)
     return fail(p->ctx, FCSPH_E_UNSUPPORTED, "x line too long for the fused step kernel");
-  if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;
+  {
+    LaunchTimer t(p->ctx, "rows_inv_step_a");
+    if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;
+  }
   // B: b = (rho/dt) div u*
   st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
   if (st != FCSPH_OK) return st;
@@ -896,14 +1004,17 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   cd.nout = 2;
   cd.sym[0] = SYM_GX;
   cd.sym[1] = SYM_GY;
-  if (!chk(p, launch_cols(cd, 1, f32, s), "step D y", st)) return st;
+  if (!chk(p, cols_launch(p, cd, 1, "cols_op_step_d"), "step D y", st)) return st;
   RowsInvArgs rd = r;
   rd.spec[0] = p->O[0];
   rd.spec[1] = p->O[1];
   rd.B = pick_B(rd.plan, f32, 4);
   rd.unew[0] = u[0];
   rd.unew[1] = u[1];
-  if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, f32, s), "step D x inv", st)) return st;
+  {
+    LaunchTimer t(p->ctx, "rows_inv_step_d");
+    if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, f32, s), "step D x inv", st)) return st;
+  }
   return FCSPH_OK;
 }
 

@@ -23,16 +23,17 @@ def grid(n, dx):
     return list(reversed(mesh))            # [x, y(, z)] each with numpy shape
 
 
-def poly_trig_2d(n: int, seed: int, dx: float | None = None) -> np.ndarray:
+def poly_trig_2d(n, seed: int, dx: float | None = None) -> np.ndarray:
     """Cubic polynomial + 8 terms a_i sin(k_i x + phi_i) cos(l_i y + psi_i).
 
     Draw order: 10 coefficients c_ab ~ N(0,1) for a + b <= 3 in lexicographic
     (a, b); then per term i: a_i ~ N(0,1), K_i ~ U{1..4}, L_i ~ U{1..4},
     phi_i ~ U(0, 2pi), psi_i ~ U(0, 2pi); k_i = pi K_i, l_i = pi L_i.
-    The lattice is n x n on [0, 1]^2 (dx = 1/(n-1)) unless dx is given.
+    n is an int (n x n lattice) or (nx, ny); dx = 1/(n-1) unless given.
     """
-    dx = 1.0 / (n - 1) if dx is None else dx
-    x, y = grid((n, n), dx)
+    nx, ny = (n, n) if np.isscalar(n) else n
+    dx = 1.0 / (nx - 1) if dx is None else dx
+    x, y = grid((nx, ny), dx)
     rng = np.random.default_rng(seed)
     f = np.zeros_like(x)
     for a in range(4):
@@ -110,6 +111,16 @@ class DecayingVortexFlow:
         for b, m, nn in self.pterms:
             p += b * np.cos(m * x) * np.cos(nn * y)
         return np.exp(-t) * p
+
+    def force_parts(self):
+        """(A, B) with force(t) = exp(-t) A + exp(-2t) B: the linear terms
+        (du/dt, grad p, viscous) decay like exp(-t), the advection like exp(-2t)."""
+        fa0 = self.force(0.0)
+        fa1 = self.force(1.0)
+        e1, e2 = np.exp(-1.0), np.exp(-2.0)
+        A = [(f1 - e2 * f0) / (e1 - e2) for f0, f1 in zip(fa0, fa1)]
+        B = [f0 - a for f0, a in zip(fa0, A)]
+        return A, B
 
     def force(self, t):
         x, y = self.x, self.y

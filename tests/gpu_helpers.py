@@ -45,3 +45,32 @@ def to_dev(a):
 
 def to_np(t):
     return t.detach().cpu().numpy().astype(np.float64)
+
+
+def fft_tol(direct, fft, floor=1e-11, factor=20.0):
+    """Parity tolerance of an FFT-evaluated circular convolution: the larger of
+    the FP64 gate and `factor` times the rounding error that an FP64 FFT
+    evaluation of the same convolution shows on this input (oracle direct tap
+    sum vs oracle FFT mode).  The FFT rounds relative to the norm of the whole
+    extended line, which the continuation can make much larger than the
+    physical field for non-smooth data."""
+    return max(floor, factor * rel_l2(fft, direct))
+
+
+def fc_rounding_bound(f, lat, bcs, tables):
+    """Element-wise bound on the FP64 rounding of the FC extension: every
+    continuation value is a 2d-term dot product, so its error is at most
+    gamma * sum |M_ij| |x_j| per axis, with the errors of earlier axes carried
+    through |M|.  Returns the bound array (zero on physical points)."""
+    import numpy as np
+    from oracle import fc as ofc
+
+    class Abs:
+        def M(self, bc):
+            return np.abs(tables.M(bc))
+    d = tables.M_D.shape[1]
+    eps = np.finfo(np.float64).eps / 2
+    gamma = 2 * d * eps / (1 - 2 * d * eps)
+    A = ofc.extend(np.abs(f), lat.walled, bcs, Abs())     # |M| applied along every walled axis
+    nw = sum(1 for w in lat.walled if w)
+    return (nw + 1) * gamma * A * 2.0
