@@ -53,7 +53,7 @@ def algorithmic_bytes(n: int, C: int) -> dict:
     }
 
 
-def cpu_baseline(n: int, steps: int) -> dict:
+def cpu_baseline(n: int, steps: int, budget_s: float) -> dict:
     """The oracle (direct tap sums, dense per-axis PPE) on the host cores."""
     import numpy as np
     from oracle import fcgram, step
@@ -70,39 +70,42 @@ def cpu_baseline(n: int, steps: int) -> dict:
     dx = 1.0 / (n - 1)
     dt = min(0.2 * dx, 0.1 * dx * dx / nu)
     flow = synth.DecayingVortexFlow(n, nu)
-    u = list(flow.velocity(0.0))
-    forces = [list(flow.force((k + 0.5) * dt)) for k in range(steps)]
-    walls = [list(flow.velocity((k + 1) * dt)) for k in range(steps)]
-    t0 = time.perf_counter()
-    for k in range(steps):
-        u, _ = step.project_step(lat, tabs, u, force=forces[k], wall=walls[k], dt=dt, nu=nu)
-    el = time.perf_counter() - t0
-    assert all(np.all(np.isfinite(c)) for c in u)
-    return {"value": round(n * n * steps / el / 1e6, 4), "unit": "Mpts/s", "cores": int(cores),
+    u0 = list(flow.velocity(0.0))
+    A, B = flow.force_parts()
+    u = u0
+    done = 0
+    el = 0.0
+    while done < steps and el < budget_s:
+        c = done % CYCLE
+        if c == 0:
+            u = [x.copy() for x in u0]
+        th = (c + 0.5) * dt
+        f = [math.exp(-th) * a + math.exp(-2 * th) * b for a, b in zip(A, B)]
+        w = [math.exp(-(c + 1) * dt) * x for x in u0]
+        t0 = time.perf_counter()
+        u, _ = step.project_step(lat, tabs, u, force=f, wall=w, dt=dt, nu=nu)
+        el += time.perf_counter() - t0
+        done += 1
+    assert all(np.all(np.isfinite(x)) for x in u)
+    return {"value": round(n * n * done / el / 1e6, 4), "unit": "Mpts/s", "cores": int(cores),
             "kind": "oracle",
-            "sample": f"{steps} FOP steps of the same {n}x{n} workload from t=0 (oracle direct mode), "
-                      f"{el:.1f} s"}
+            "sample": f"{done} FOP steps of the same {n}x{n} workload (oracle direct mode, same "
+                      f"restart cycle), {el:.1f} s of step time"}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--cpu-steps", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
-        return 2
+def algorithmic_bytes_direct(n: int) -> dict:
+    R = n * n * 8
+    return {"direct_step_a": 6 * R, "direct_div": 3 * R, "direct_step_d": 5 * R,
+            "ppe_rows_fwd": 2 * R, "ppe_cols_solve": 2 * R, "ppe_rows_inv": 2 * R}
 
-    import numpy as np
+
+def run_gpu(op_eval: str, n: int, steps: int, warmup: int) -> dict:
+    """Time `steps` FOP steps of the n x n workload with one operator evaluation."""
     import torch
 
     from paper_2606_06247_amd import api, synth
 
-    n, C = args.n, 25
+    C = 25
     nu, rho = 1e-3, 1.0
     dx = 1.0 / (n - 1)
     dt = min(0.2 * dx, 0.1 * dx * dx / nu)
@@ -122,7 +125,7 @@ def main() -> int:
 
     ctx = api.Context(0)
     prob = api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
-                       prs_bc=(("N", "N"), ("N", "N")), rho=rho)
+                       prs_bc=(("N", "N"), ("N", "N")), rho=rho, op_eval=op_eval)
     plan = api.Plan(ctx, prob)
 
     def step(k):
@@ -132,7 +135,7 @@ def main() -> int:
             u[1].copy_(u0[1])
         plan.project_step(u, dt, nu, p_out=p, force=forces[c], wall=walls[c])
 
-    for k in range(args.warmup):
+    for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
     ctx.read_timing()
@@ -142,7 +145,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for k in range(args.steps):
+    for k in range(steps):
         step(k)
     e1.record(stream)
     torch.cuda.synchronize()
@@ -151,11 +154,9 @@ def main() -> int:
     kern = ctx.read_timing()
     gpu_ms = e0.elapsed_time(e1)
     wall_s = t1 - t0
-    ms_per_step = 1e3 * wall_s / args.steps
-    value = n * n * args.steps / wall_s / 1e6
+    ms_per_step = 1e3 * wall_s / steps
     finite = bool(all(torch.isfinite(c).all().item() for c in u))
-
-    ab = algorithmic_bytes(n, C)
+    ab = algorithmic_bytes(n, C) if op_eval == "fft" else algorithmic_bytes_direct(n)
     per_kernel = {}
     for name, (cnt, tot) in sorted(kern.items(), key=lambda kv: -kv[1][1]):
         avg_ms = tot / cnt
@@ -166,26 +167,62 @@ def main() -> int:
     dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
     dom_avg_s = kern[dom][1] / kern[dom][0] * 1e-3
     achieved = ab[dom] / dom_avg_s / 1e9
-    step_bytes = sum(ab[k] * kern[k][0] for k in kern if k in ab) / args.steps
+    step_bytes = sum(ab[k] * kern[k][0] for k in kern if k in ab) / steps
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": ab[dom],
                 "step_algorithmic_GB": round(step_bytes / 1e9, 4),
                 "step_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return {"value": round(n * n * steps / wall_s / 1e6, 2), "ms_per_step": round(ms_per_step, 4),
+            "gpu_event_ms": round(gpu_ms, 3), "state_finite": finite, "roofline": roofline,
+            "kernels": per_kernel}
 
-    out = {"metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--op-eval", choices=["fft", "direct"], default="fft")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the other operator evaluation on the same workload")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_MiB": args.copy_probe, "bytes": src.numel() * 8}))
+        return 0
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
+        return 2
+    n = args.n
+    head = run_gpu(args.op_eval, n, args.steps, args.warmup)
+    out = {"metric": METRIC, "value": head["value"], "unit": "Mpts/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"2D {n}x{n} FC(Gram)-spectral ISPH first-order projection step, "
                                   "walls on 4 sides (Dirichlet velocity, Neumann pressure), "
-                                  f"FC(Gram) d=5 C={C} (extended {n + C}x{n + C}), Wendland C2 h=1.3dx, "
+                                  f"FC(Gram) d=5 C=25 (extended {n + 25}x{n + 25}), Wendland C2 h=1.3dx, "
                                   "nu=1e-3, manufactured decaying-vortex flow, restart every 25 steps",
-                      "n": n, "precision": "fp64", "gpu_event_ms": round(gpu_ms, 3),
-                      "state_finite": finite},
-           "roofline": roofline, "kernels": per_kernel}
+                      "n": n, "precision": "fp64", "op_eval": args.op_eval,
+                      "gpu_event_ms": head["gpu_event_ms"], "state_finite": head["state_finite"]},
+           "roofline": head["roofline"], "kernels": head["kernels"]}
+    if not args.no_variants:
+        other = "direct" if args.op_eval == "fft" else "fft"
+        v = run_gpu(other, n, args.steps, args.warmup)
+        out["variants"] = {f"op_eval={other}": {k: v[k] for k in ("value", "ms_per_step", "roofline", "kernels")}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

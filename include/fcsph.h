@@ -50,6 +50,11 @@ typedef enum { FCSPH_FP64 = 0, FCSPH_FP32_MIXED = 1 } fcsph_precision;
 typedef enum { FCSPH_PPE_PHYSICAL = 0, FCSPH_PPE_EXTENDED = 1 } fcsph_ppe_domain;
 typedef enum { FCSPH_EIG_SPECTRAL = 0, FCSPH_EIG_FD2 = 1, FCSPH_EIG_SPH = 2 } fcsph_eig;
 typedef enum { FCSPH_KERNEL_WENDLAND_C2 = 0 } fcsph_kernel;
+/* How the circular convolutions of the operators are evaluated: through the
+ * DFT of the FC-extended field (the paper's convolution-theorem route) or as
+ * direct tap sums over the compact kernel support (same result up to
+ * rounding; every input read once). */
+typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1 } fcsph_op_eval;
 
 /*
  * Problem descriptor.  Axes are indexed 0 = x, 1 = y, 2 = z.
@@ -67,6 +72,7 @@ typedef enum { FCSPH_KERNEL_WENDLAND_C2 = 0 } fcsph_kernel;
  *  kernel, h_over_dx   SPH kernel and smoothing length h / dx
  *  prec        fcsph_precision;  ppe_domain  fcsph_ppe_domain;  eig  fcsph_eig
  *  rho         fluid density
+ *  op_eval     fcsph_op_eval
  */
 typedef struct {
   int ndim;
@@ -84,6 +90,7 @@ typedef struct {
   int ppe_domain;
   int eig;
   double rho;
+  int op_eval;
 } fcsph_desc;
 
 typedef struct fcsph_ctx fcsph_ctx;

@@ -29,6 +29,7 @@ FP64, FP32_MIXED = 0, 1
 PPE_PHYSICAL, PPE_EXTENDED = 0, 1
 EIG_SPECTRAL, EIG_FD2, EIG_SPH = 0, 1, 2
 KERNEL_WENDLAND_C2 = 0
+OPS_FFT, OPS_DIRECT = 0, 1
 
 EXPORTS = [
     "fcsph_ctx_create", "fcsph_ctx_destroy", "fcsph_ctx_sync", "fcsph_status_string",
@@ -47,6 +48,7 @@ class Desc(ctypes.Structure):
         ("fc_M_dir", ctypes.POINTER(ctypes.c_double)), ("fc_M_neu", ctypes.POINTER(ctypes.c_double)),
         ("kernel", ctypes.c_int), ("h_over_dx", ctypes.c_double), ("prec", ctypes.c_int),
         ("ppe_domain", ctypes.c_int), ("eig", ctypes.c_int), ("rho", ctypes.c_double),
+        ("op_eval", ctypes.c_int),
     ]
 
 
@@ -115,6 +117,7 @@ class Problem:
     precision: str = "fp64"       # 'fp64' | 'fp32'
     eig: str = "spectral"         # 'spectral' | 'fd2'
     rho: float = 1.0
+    op_eval: str = "fft"          # 'fft' | 'direct'
     fc_d: int = 5
     fc_C: int = 25
 
@@ -206,6 +209,7 @@ class Plan:
         d.ppe_domain = PPE_PHYSICAL
         d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
         d.rho = prob.rho
+        d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT}[prob.op_eval]
         self.desc = d
         nbytes = ctypes.c_size_t()
         _check(L.fcsph_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), None,

@@ -35,6 +35,37 @@ __device__ __forceinline__ cpx<T> cmi(cpx<T> a) { return {a.i, -a.r}; }
 template <typename T>
 __device__ __forceinline__ cpx<T> cpi(cpx<T> a) { return {-a.i, a.r}; }
 
+// Strided loop that keeps up to U loads in flight: ld(i) for U indices, then
+// use(i, value) for them.  A plain loop that stores each loaded value to LDS
+// waits for every load in turn.
+template <int U, typename V, typename Ld, typename Use>
+__device__ __forceinline__ void batched(int start, int end, int step, Ld ld, Use use) {
+  for (int base = start; base < end; base += U * step) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * step;
+      if (i < end) v[u] = ld(i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * step;
+      if (i < end) use(i, v[u]);
+    }
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8).  Remapping b so that every XCD receives a contiguous range of
+// panels makes neighbouring panels - which share cache lines - meet in the
+// same L2.  The map is a bijection of [0, nb).
+__device__ __forceinline__ int xcd_panel(int b, int nb) {
+  constexpr int NX = 8;
+  const int per = nb / NX, rem = nb % NX;
+  const int x = b % NX, k = b / NX;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 // Largest number of butterflies per thread and stage for radix R (bounds the
 // registers a stage holds); the host sizes TL with the same rule.
 __host__ __device__ constexpr int nb_max(int R) {
@@ -105,22 +136,27 @@ struct Dft<T, 8> {
   }
 };
 
-// Odd radix: X_k = x0 + sum_{j=1..h} (x_j + x_{R-j}) cos(2 pi j k/R)
-//                 - i sum_{j=1..h} (x_j - x_{R-j}) sin(2 pi j k/R),
-// X_{R-k} the same with +i.  cs(m), sn(m) = cos, sin(2 pi m / R).
-template <typename T, int R, typename CS>
-__device__ __forceinline__ void dft_odd(cpx<T> *x, CS cs_sn) {
+// Odd radix, computed in place and stored as it goes:
+//   X_k     = x0 + sum_{j=1..h} (x_j + x_{R-j}) cos(2 pi j k/R) - i sum_j (x_j - x_{R-j}) sin(2 pi j k/R)
+//   X_{R-k} = the same with +i,   X_0 = sum_j x_j.
+// x[j] is overwritten by x_j + x_{R-j} and x[R-j] by x_j - x_{R-j}; each pair
+// of outputs is handed to put(r, value) as soon as it is formed, so the
+// registers hold the R inputs and two accumulators only.  cs_sn(m, c, s)
+// gives cos / sin(2 pi m / R).
+template <typename T, int R, typename CS, typename Put>
+__device__ __forceinline__ void dft_odd_store(cpx<T> *x, CS cs_sn, Put put) {
   constexpr int h = (R - 1) / 2;
-  cpx<T> s[h + 1], d[h + 1];
 #pragma unroll
   for (int j = 1; j <= h; ++j) {
-    s[j] = cadd(x[j], x[R - j]);
-    d[j] = csub(x[j], x[R - j]);
+    const cpx<T> a = x[j], b = x[R - j];
+    x[j] = cadd(a, b);
+    x[R - j] = csub(a, b);
   }
   const cpx<T> x0 = x[0];
   cpx<T> tot = x0;
 #pragma unroll
-  for (int j = 1; j <= h; ++j) tot = cadd(tot, s[j]);
+  for (int j = 1; j <= h; ++j) tot = cadd(tot, x[j]);
+  put(0, tot);
 #pragma unroll
   for (int k = 1; k <= h; ++k) {
     cpx<T> A = x0, Bv = {T(0), T(0)};
@@ -129,33 +165,34 @@ __device__ __forceinline__ void dft_odd(cpx<T> *x, CS cs_sn) {
       const int m = (j * k) % R;
       T c, sn;
       cs_sn(m, c, sn);
-      A.r += s[j].r * c;
-      A.i += s[j].i * c;
-      Bv.r += d[j].r * sn;
-      Bv.i += d[j].i * sn;
+      A.r += x[j].r * c;
+      A.i += x[j].i * c;
+      Bv.r += x[R - j].r * sn;
+      Bv.i += x[R - j].i * sn;
     }
-    x[k] = cadd(A, cmi(Bv));
-    x[R - k] = cadd(A, cpi(Bv));
+    put(k, cadd(A, cmi(Bv)));
+    put(R - k, cadd(A, cpi(Bv)));
   }
-  x[0] = tot;
 }
 
 template <typename T>
 struct Dft<T, 5> {
-  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
-    dft_odd<T, 5>(x, [](int m, T &c, T &s) {
+  template <typename Put>
+  __device__ __forceinline__ static void run_store(cpx<T> *x, const cpx<T> *, int, Put put) {
+    dft_odd_store<T, 5>(x, [](int m, T &c, T &s) {
       constexpr double C1 = 0.30901699437494742410229341718282, C2 = -0.80901699437494742410229341718282;
       constexpr double S1 = 0.95105651629515357211643933337938, S2 = 0.58778525229247312916870595463907;
       c = T(m == 1 || m == 4 ? C1 : C2);
       s = T(m == 1 ? S1 : m == 2 ? S2 : m == 3 ? -S2 : -S1);
-    });
+    }, put);
   }
 };
 
 template <typename T>
 struct Dft<T, 7> {
-  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *, int) {
-    dft_odd<T, 7>(x, [](int m, T &c, T &s) {
+  template <typename Put>
+  __device__ __forceinline__ static void run_store(cpx<T> *x, const cpx<T> *, int, Put put) {
+    dft_odd_store<T, 7>(x, [](int m, T &c, T &s) {
       constexpr double C1 = 0.62348980185873353052500488400424, C2 = -0.22252093395631440428890256449679,
                        C3 = -0.90096886790241912623610231950745;
       constexpr double S1 = 0.78183148246802980870844452667406, S2 = 0.97492791218182360701813168299393,
@@ -164,7 +201,7 @@ struct Dft<T, 7> {
       const double sg = m <= 3 ? 1.0 : -1.0;
       c = T(mm == 1 ? C1 : mm == 2 ? C2 : C3);
       s = T(sg * (mm == 1 ? S1 : mm == 2 ? S2 : S3));
-    });
+    }, put);
   }
 };
 
@@ -172,14 +209,19 @@ struct Dft<T, 7> {
 // tw[m N / R] = exp(-2 pi i m / R).
 template <typename T, int R>
 struct Dft {
-  __device__ __forceinline__ static void run(cpx<T> *x, const cpx<T> *tw, int base) {
-    dft_odd<T, R>(x, [&](int m, T &c, T &s) {
+  template <typename Put>
+  __device__ __forceinline__ static void run_store(cpx<T> *x, const cpx<T> *tw, int base, Put put) {
+    dft_odd_store<T, R>(x, [&](int m, T &c, T &s) {
       const cpx<T> w = tw[m * base];
       c = w.r;
       s = -w.i;
-    });
+    }, put);
   }
 };
+
+// Radices 2, 4 and 8 compute in registers and then store.
+template <typename T, int R>
+__device__ __forceinline__ constexpr bool is_pow2_radix() { return R == 2 || R == 3 || R == 4 || R == 8; }
 
 // One Stockham stage.  N: work length; Ns: product of previous radices.
 template <typename T, int R>
@@ -207,10 +249,14 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, int N, int Ns, const
 #pragma unroll
         for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * tstride]);
       }
-      Dft<T, R>::run(v[b], tw, NR);
       const int o = (j - k) * R + k;
+      if constexpr (is_pow2_radix<T, R>()) {
+        Dft<T, R>::run(v[b], tw, NR);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
+        for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
+      } else {
+        Dft<T, R>::run_store(v[b], tw, NR, [&](int r, cpx<T> val) { buf[o + r * Ns] = val; });
+      }
     }
   }
   __syncthreads();

@@ -266,6 +266,36 @@ void wendland_taps(int ndim, double dx, double hod, const int *E, std::vector<do
       }
 }
 
+// Compact tap list for the direct evaluation (un-normalised weights).
+std::vector<Tap> wendland_tap_list(int ndim, double dx, double hod, int &reach) {
+  std::vector<Tap> out;
+  const LD h = (LD)hod * (LD)dx;
+  const LD alpha = ndim == 2 ? 7.0L / (4.0L * kPi * h * h) : 21.0L / (16.0L * kPi * h * h * h);
+  const LD dV = ndim == 2 ? (LD)dx * dx : (LD)dx * dx * dx;
+  const int zr = ndim == 3 ? kSymR : 0;
+  reach = 0;
+  for (int sz = -zr; sz <= zr; ++sz)
+    for (int sy = -kSymR; sy <= kSymR; ++sy)
+      for (int sx = -kSymR; sx <= kSymR; ++sx) {
+        const LD q = sqrtl((LD)(sx * sx + sy * sy + sz * sz)) * (LD)dx / h;
+        if (!(q < 2.0L)) continue;
+        const LD s = 1.0L - q / 2.0L;
+        const LD pre = -5.0L * alpha / (h * h);
+        const LD g = pre * s * s * s * dV;
+        Tap t{};
+        t.s[0] = sx;
+        t.s[1] = sy;
+        t.s[2] = sz;
+        t.w[0] = (double)(g * (LD)sx * (LD)dx);
+        t.w[1] = (double)(g * (LD)sy * (LD)dx);
+        t.w[2] = (double)(g * (LD)sz * (LD)dx);
+        t.w[3] = (double)(pre * s * s * (ndim == 2 ? (2.0L - 2.5L * q) : (3.0L - 3.0L * q)) * dV);
+        out.push_back(t);
+        reach = std::max(reach, std::max(std::abs(sx), std::max(std::abs(sy), std::abs(sz))));
+      }
+  return out;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- the plan
@@ -299,6 +329,11 @@ struct fcsph_plan {
   void *coef = nullptr;         // PPE coefficient rows
   int cpitch = 0;
   double *ext_scratch = nullptr;  // intermediate of a multi-axis FC extension
+  bool direct = false;            // operators as direct tap sums
+  double wd2[3][kSymW * kSymW] = {};   // 2D dense tap weights (grad x, grad y, lap)
+  double *ghx[3] = {}, *ghy[3] = {};    // FC ghost values of up to 3 direct-pass inputs
+  const Tap *taps = nullptr;
+  int ntaps = 0, reach = 0;
   size_t ws_bytes = 0;
 };
 
@@ -336,6 +371,8 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
     return FCSPH_E_UNSUPPORTED;
   }
   if (d->prec != FCSPH_FP64 && d->prec != FCSPH_FP32_MIXED) { msg = "bad precision"; return FCSPH_E_INVALID; }
+  if (d->op_eval != FCSPH_OPS_FFT && d->op_eval != FCSPH_OPS_DIRECT) { msg = "bad op_eval"; return FCSPH_E_INVALID; }
+  if (d->op_eval == FCSPH_OPS_DIRECT && d->ndim != 2) { msg = "direct evaluation is built for 2D"; return FCSPH_E_UNSUPPORTED; }
   if (d->ppe_domain != FCSPH_PPE_PHYSICAL) { msg = "only the physical-domain PPE is built"; return FCSPH_E_UNSUPPORTED; }
   if (d->eig != FCSPH_EIG_SPECTRAL && d->eig != FCSPH_EIG_FD2) { msg = "eigenvalue family not built"; return FCSPH_E_UNSUPPORTED; }
   if (!(d->rho > 0.0)) { msg = "rho must be positive"; return FCSPH_E_INVALID; }
@@ -404,6 +441,24 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       msg = "cannot plan a DFT of length " + std::to_string(p->E[a]);
       return FCSPH_E_UNSUPPORTED;
     }
+  }
+  // direct tap list
+  p->direct = d->op_eval == FCSPH_OPS_DIRECT;
+  {
+    std::vector<Tap> tl = wendland_tap_list(p->nd, d->dx, d->h_over_dx, p->reach);
+    Upload u;
+    u.data.assign((const char *)tl.data(), (const char *)(tl.data() + tl.size()));
+    u.dst = ws.take(u.data.size());
+    p->taps = (const Tap *)u.dst;
+    p->ntaps = (int)tl.size();
+    up.push_back(std::move(u));
+    if (p->nd == 2)
+      for (const Tap &t : tl) {
+        const int wi = (t.s[1] + kSymR) * kSymW + (t.s[0] + kSymR);
+        p->wd2[0][wi] = t.w[0];
+        p->wd2[1][wi] = t.w[1];
+        p->wd2[2][wi] = t.w[3];
+      }
   }
   // symbols
   {
@@ -496,6 +551,10 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->cpitch = p->trig_kind[0] == TRIG_DFT ? p->ncoef[0] : (std::max(p->ncoef[0], 1) + 1) / 2;
   p->coef = ws.take((size_t)p->cpitch * rows * ce);
   p->ext_scratch = (double *)ws.take((size_t)p->E[0] * p->E[1] * p->E[2] * sizeof(double));
+  for (int i = 0; i < 3; ++i) {
+    p->ghx[i] = (double *)ws.take((size_t)p->n[1] * p->n[2] * 2 * kSymR * sizeof(double));
+    p->ghy[i] = (double *)ws.take((size_t)2 * kSymR * (p->n[0] + 2 * kSymR) * p->n[2] * sizeof(double));
+  }
   p->ws_bytes = ws.off + 256;
   return FCSPH_OK;
 }
@@ -612,6 +671,40 @@ WallInfo wall_info(fcsph_plan *p) {
     for (int s = 0; s < 2; ++s) w.dir[a][s] = p->walled[a] && p->d.vel_bc[a][s] == FCSPH_BC_DIRICHLET;
   }
   return w;
+}
+
+DirectArgs direct_base(fcsph_plan *p, int fc) {
+  DirectArgs a{};
+  a.ndim = p->nd;
+  for (int q = 0; q < 3; ++q) {
+    a.n[q] = p->n[q];
+    a.walled[q] = p->walled[q];
+    a.fc[q] = walls_for(p, q, fc);
+  }
+  a.R = p->reach;
+  a.taps = p->taps;
+  a.ntaps = p->ntaps;
+  for (int q = 0; q < 3; ++q)
+    for (int i = 0; i < kSymW * kSymW; ++i) a.wd[q][i] = p->wd2[q][i];
+  for (int q = 0; q < 3; ++q) {
+    a.gx[q] = p->ghx[q];
+    a.gy[q] = p->ghy[q];
+  }
+  a.out_is_double = p->fp32 ? 0 : 1;
+  a.scale = 1.0;
+  a.wi = wall_info(p);
+  return a;
+}
+
+hipError_t direct_launch(fcsph_plan *p, const DirectArgs &a, int mode, const char *name) {
+  const int nf = (mode == DIR_DIV || mode == DIR_STEP_A) ? 2 : 1;
+  {
+    LaunchTimer t(p->ctx, "direct_ghost");
+    hipError_t e = launch_ghost2d(a, nf, p->ctx->stream);
+    if (e != hipSuccess) return e;
+  }
+  LaunchTimer t(p->ctx, name);
+  return launch_direct(a, mode, p->ctx->stream);
 }
 
 fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
@@ -867,6 +960,14 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
     if (!g[a]) return fail(p->ctx, FCSPH_E_INVALID, "null output");
   if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
   fcsph_status st = FCSPH_OK;
+  if (p->direct) {
+    DirectArgs a = direct_base(p, fc);
+    a.in[0] = f;
+    a.out[0] = g[0];
+    a.out[1] = g[1];
+    if (!chk(p, direct_launch(p, a, DIR_OPS, "direct_ops"), "grad", st)) return st;
+    return FCSPH_OK;
+  }
   if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "grad x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, fc);
   c.in[0] = p->S[0];
@@ -885,6 +986,13 @@ fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *la
   if (!f || !lap) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
   if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
   fcsph_status st = FCSPH_OK;
+  if (p->direct) {
+    DirectArgs a = direct_base(p, fc);
+    a.in[0] = f;
+    a.out[3] = lap;
+    if (!chk(p, direct_launch(p, a, DIR_OPS, "direct_ops"), "lap", st)) return st;
+    return FCSPH_OK;
+  }
   if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, fc);
   c.in[0] = p->S[0];
@@ -899,6 +1007,16 @@ fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *la
 static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, void *out, bool out_double,
                              double scale) {
   fcsph_status st = FCSPH_OK;
+  if (p->direct) {
+    DirectArgs a = direct_base(p, FCSPH_FIELD_VELOCITY);
+    a.in[0] = u0;
+    a.in[1] = u1;
+    a.out[0] = out;
+    a.out_is_double = out_double ? 1 : 0;
+    a.scale = scale;
+    if (!chk(p, direct_launch(p, a, DIR_DIV, "direct_div"), "div", st)) return st;
+    return FCSPH_OK;
+  }
   if (!chk(p, x_fwd_pair(p, u0, u1, FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
   ColsArgs c = cols_base(p, COLS_DIV, FCSPH_FIELD_VELOCITY);
   c.in[0] = p->S[0];
@@ -939,6 +1057,35 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   fcsph_status st = FCSPH_OK;
   hipStream_t s = p->ctx->stream;
   const bool f32 = p->fp32;
+  if (p->direct) {
+    DirectArgs a = direct_base(p, FCSPH_FIELD_VELOCITY);
+    a.in[0] = u[0];
+    a.in[1] = u[1];
+    for (int q = 0; q < 2; ++q) {
+      a.f[q] = force ? force[q] : nullptr;
+      a.wall[q] = wall_vel ? wall_vel[q] : nullptr;
+      a.ustar[q] = p->ustar[q];
+    }
+    a.dt = dt;
+    a.nu = nu;
+    a.dt_over_rho = dt / p->d.rho;
+    if (!chk(p, direct_launch(p, a, DIR_STEP_A, "direct_step_a"), "step A", st)) return st;
+    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
+    if (st != FCSPH_OK) return st;
+    double *phi = p_out ? p_out : p->phi;
+    st = run_ppe(p, p->rhs, phi);
+    if (st != FCSPH_OK) return st;
+    DirectArgs b = direct_base(p, FCSPH_FIELD_PRESSURE);
+    b.in[0] = phi;
+    for (int q = 0; q < 2; ++q) {
+      b.wall[q] = wall_vel ? wall_vel[q] : nullptr;
+      b.ustar_in[q] = p->ustar[q];
+      b.unew[q] = u[q];
+    }
+    b.dt_over_rho = dt / p->d.rho;
+    if (!chk(p, direct_launch(p, b, DIR_STEP_D, "direct_step_d"), "step D", st)) return st;
+    return FCSPH_OK;
+  }
   // A: u* = u - dt [(u.grad)u - nu lap u - f], Dirichlet walls <- wall data
   if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "step A x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, FCSPH_FIELD_VELOCITY);

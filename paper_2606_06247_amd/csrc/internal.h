@@ -169,6 +169,50 @@ struct PpeColsArgs {
   int B, ldsM;
 };
 
+// ---------------------------------------------------------------- direct tap sums
+// One tap of the compact kernel: lattice offset and the un-normalised weights
+// dV d_x W, dV d_y W, dV d_z W, dV lap W at that offset.
+struct Tap {
+  int s[3];
+  int pad;
+  double w[4];
+};
+
+enum DirectMode {
+  DIR_OPS = 0,       // grad / lap of one field into up to 4 outputs
+  DIR_DIV = 1,       // scale * sum_a G_a u_a
+  DIR_STEP_A = 2,    // u* (fused advection, viscosity, forcing, wall data)
+  DIR_STEP_D = 3     // projection u = u* - dt/rho grad phi, wall reset
+};
+
+struct DirectArgs {
+  int ndim;
+  int n[3];
+  int walled[3];
+  int R;               // tap reach per axis (|s_a| <= R)
+  FcWalls fc[3];       // per axis, for the field class being differentiated
+  const Tap *taps;
+  int ntaps;
+  double wd[3][kSymW * kSymW];   // 2D dense weights (grad x, grad y, lap) at [(sy+R)*W + sx+R]
+  const double *in[3]; // input fields (OPS: in[0]; DIV / STEP_A: velocity; STEP_D: phi)
+  // outputs
+  void *out[4];        // OPS: grad x, y, z, lap (null = skip); DIV: out[0]
+  int out_is_double;
+  double scale;
+  // step
+  const double *f[3], *wall[3], *ustar_in[3];
+  double *ustar[3], *unew[3];
+  double dt, nu, dt_over_rho;
+  WallInfo wi;
+  // FC ghost values of the inputs within R points of the lattice (2D):
+  // gx[f] [ny][2R] (x = -R..-1, nx..nx+R-1), gy[f] [2R][nx+2R] (same slots in y,
+  // column index x + R, corners included); filled by the ghost kernel
+  double *gx[3], *gy[3];
+};
+
+hipError_t launch_direct(const DirectArgs &a, int mode, hipStream_t s);
+hipError_t launch_ghost2d(const DirectArgs &a, int nfields, hipStream_t s);
+
 // ---------------------------------------------------------------- FC standalone
 struct FcExtArgs {
   const double *in;

@@ -23,9 +23,26 @@ __device__ __forceinline__ cpx<T> to_cpx(double r, double i) {
 }
 
 // FC continuation value i (0-based, i < C) of a real line given by a
-// callback returning line values as double.
+// callback returning line values as double.  d = 5 is unrolled so that the
+// 2d loads are issued together.
 template <typename Get>
 __device__ __forceinline__ double fc_cont(const FcWalls &fc, int n, int i, Get get) {
+  if (fc.d == 5) {
+    const double *hi = fc.Mhi + (size_t)i * 5;
+    const double *lo = fc.Mlo + (size_t)(fc.C - 1 - i) * 5;
+    double v[10], m[10];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      v[j] = get(n - 5 + j);
+      m[j] = hi[j];
+      v[5 + j] = get(4 - j);
+      m[5 + j] = lo[j];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc = fma(m[j], v[j], acc);
+    return acc;
+  }
   const double *hi = fc.Mhi + (size_t)i * fc.d;
   const double *lo = fc.Mlo + (size_t)(fc.C - 1 - i) * fc.d;
   double acc = 0.0;
@@ -47,8 +64,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(RowsFwdArgs a) {
   const bool active = line < a.nlines;
   const double *pa = active ? a.inA + (size_t)line * a.strideA : nullptr;
   const double *pb = (active && line < a.nB && a.inB) ? a.inB + (size_t)line * a.strideB : nullptr;
-  for (int j = lt; j < a.nx; j += TL)
-    buf[j] = to_cpx<T>(pa ? pa[j] : 0.0, pb ? pb[j] : 0.0);
+  batched<8, cpx<T>>(lt, a.nx, TL, [&](int j) { return to_cpx<T>(pa ? pa[j] : 0.0, pb ? pb[j] : 0.0); },
+                     [&](int j, cpx<T> v) { buf[j] = v; });
   if (a.fc.on) {
     for (int i = lt; i < a.fc.C; i += TL) {
       double ra = pa ? fc_cont(a.fc, a.nx, i, [&](int j) { return pa[j]; }) : 0.0;
@@ -86,17 +103,23 @@ __device__ __forceinline__ bool is_dirichlet_point(const WallInfo &w, int x, int
 template <typename T>
 __device__ __forceinline__ void load_packed_c2r(cpx<T> *buf, const cpx<T> *A, const cpx<T> *Bp,
                                                 int E, int H, int lt, int TL) {
-  for (int k = lt; k < H; k += TL) {
-    cpx<T> av = A ? A[k] : cpx<T>{T(0), T(0)};
-    cpx<T> bv = Bp ? Bp[k] : cpx<T>{T(0), T(0)};
-    const bool selfconj = (k == 0) || (2 * k == E);
-    if (selfconj) {
-      av.i = T(0);
-      bv.i = T(0);
-    }
-    buf[k] = {av.r - bv.i, av.i + bv.r};
-    if (!selfconj) buf[E - k] = {av.r + bv.i, bv.r - av.i};
-  }
+  struct AB {
+    cpx<T> a, b;
+  };
+  batched<4, AB>(lt, H, TL,
+                 [&](int k) {
+                   return AB{A ? A[k] : cpx<T>{T(0), T(0)}, Bp ? Bp[k] : cpx<T>{T(0), T(0)}};
+                 },
+                 [&](int k, AB v) {
+                   cpx<T> av = v.a, bv = v.b;
+                   const bool selfconj = (k == 0) || (2 * k == E);
+                   if (selfconj) {
+                     av.i = T(0);
+                     bv.i = T(0);
+                   }
+                   buf[k] = {av.r - bv.i, av.i + bv.r};
+                   if (!selfconj) buf[E - k] = {av.r + bv.i, bv.r - av.i};
+                 });
 }
 
 template <typename T, int EPI>
@@ -325,13 +348,16 @@ constexpr int kXMax = 8;   // spectrum values kept in registers per thread
 template <typename T>
 __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const cpx<T> *in,
                                           int c0, size_t obase, int n) {
-  for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
-    const int l = idx % a.B, j = idx / a.B;
-    const int c = c0 + l;
-    cpx<T> v = {T(0), T(0)};
-    if (c < a.ninner) v = in[obase + (size_t)j * a.es + c];
-    smem[(size_t)l * a.ldsM + j] = v;
-  }
+  batched<8, cpx<T>>(threadIdx.x, a.B * n, blockDim.x,
+                     [&](int idx) {
+                       const int l = idx % a.B, j = idx / a.B;
+                       const int c = c0 + l;
+                       return c < a.ninner ? in[obase + (size_t)j * a.es + c] : cpx<T>{T(0), T(0)};
+                     },
+                     [&](int idx, cpx<T> v) {
+                       const int l = idx % a.B, j = idx / a.B;
+                       smem[(size_t)l * a.ldsM + j] = v;
+                     });
 }
 
 template <typename T>
@@ -363,8 +389,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(ColsArgs a) {
   const int lt = threadIdx.x - g * TL;
   cpx<T> *buf = smem + (size_t)g * a.ldsM;
   const int npanel = (a.ninner + a.B - 1) / a.B;
-  const int o = blockIdx.x / npanel;
-  const int c0 = (blockIdx.x - o * npanel) * a.B;
+  const int bid = xcd_panel(blockIdx.x, gridDim.x);
+  const int o = bid / npanel;
+  const int c0 = (bid - o * npanel) * a.B;
   const int c = c0 + g;
   const size_t obase_in = (size_t)o * a.os_in, obase_out = (size_t)o * a.os_out;
   const int E = a.plan.n;
@@ -487,14 +514,14 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
       return a.in_real ? a.in_real[o] : (double)a.in_float[o];
     };
     if (a.kind == TRIG_DFT) {
-      for (int j = lt; j < n; j += TL)
-        buf[j] = to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0);
+      batched<8, cpx<T>>(lt, n, TL, [&](int j) { return to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0); },
+                         [&](int j, cpx<T> v) { buf[j] = v; });
     } else if (a.kind == TRIG_DCT1) {
-      // even extension of length 2(n-1)
-      for (int j = lt; j < L; j += TL) {
-        const int s = j < n ? j : L - j;
-        buf[j] = to_cpx<T>(okA ? val(rA, s) : 0.0, okB ? val(rB, s) : 0.0);
-      }
+      // even extension of length 2(n-1): load the n values, then mirror in LDS
+      batched<8, cpx<T>>(lt, n, TL, [&](int j) { return to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0); },
+                         [&](int j, cpx<T> v) { buf[j] = v; });
+      __syncthreads();
+      for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
     } else {
       // odd extension of the interior values, length 2(n-1)
       for (int j = lt; j < L; j += TL) {
@@ -622,19 +649,23 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(PpeColsArgs a) {
   const int lt = threadIdx.x - g * TL;
   cpx<T> *buf = smem + (size_t)g * a.ldsM;
   const int npanel = (a.ninner + a.B - 1) / a.B;
-  const int o = blockIdx.x / npanel;
-  const int c0 = (blockIdx.x - o * npanel) * a.B;
+  const int bid = xcd_panel(blockIdx.x, gridDim.x);
+  const int o = bid / npanel;
+  const int c0 = (bid - o * npanel) * a.B;
   const int c = c0 + g;
   cpx<T> *data = static_cast<cpx<T> *>(a.data) + (size_t)o * a.os;
   const int n = a.nline;
 
-  for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
-    const int l = idx % a.B, j = idx / a.B;
-    const int cc = c0 + l;
-    cpx<T> v = {T(0), T(0)};
-    if (cc < a.ninner) v = data[(size_t)j * a.es + cc];
-    smem[(size_t)l * a.ldsM + j] = v;
-  }
+  batched<8, cpx<T>>(threadIdx.x, a.B * n, blockDim.x,
+                     [&](int idx) {
+                       const int l = idx % a.B, j = idx / a.B;
+                       const int cc = c0 + l;
+                       return cc < a.ninner ? data[(size_t)j * a.es + cc] : cpx<T>{T(0), T(0)};
+                     },
+                     [&](int idx, cpx<T> v) {
+                       const int l = idx % a.B, j = idx / a.B;
+                       smem[(size_t)l * a.ldsM + j] = v;
+                     });
   __syncthreads();
   ppe_line_transform<T>(buf, a, lt, TL, a.solve == 2);
   if (a.solve == 1) {

@@ -69,10 +69,11 @@ def test_fc_extend(ctx, fc_tables, s):
         assert np.all(err <= bound), float(np.max(err / np.maximum(bound, 1e-300)))
 
 
+@pytest.mark.parametrize("op_eval", ["fft", "direct"])
 @pytest.mark.parametrize("s", CASES_2D, ids=lambda s: f"{s['n']}-{s['walled']}")
-def test_operators(ctx, fc_tables, s):
+def test_operators(ctx, fc_tables, s, op_eval):
     from paper_2606_06247_amd import api
-    plan = api.Plan(ctx, problem(s))
+    plan = api.Plan(ctx, problem(s, op_eval=op_eval))
     ops = operators.Operators(lattice(s), fc_tables)
     opf = operators.Operators(lattice(s), fc_tables, mode="fft")
     f = field(s, 2)
@@ -123,11 +124,12 @@ STEP_CASES = [
 ]
 
 
+@pytest.mark.parametrize("op_eval", ["fft", "direct"])
 @pytest.mark.parametrize("s", STEP_CASES, ids=lambda s: f"{s['n']}-{s['vel']}-{s['prs']}")
-def test_project_step(ctx, fc_tables, s):
+def test_project_step(ctx, fc_tables, s, op_eval):
     import torch
     from paper_2606_06247_amd import api
-    plan = api.Plan(ctx, problem(s))
+    plan = api.Plan(ctx, problem(s, op_eval=op_eval))
     lat = lattice(s)
     smooth = lambda seed: synth.poly_trig_2d(s["n"], seed, dx=s["dx"])
     u = [smooth(10), smooth(11)]
@@ -146,14 +148,15 @@ def test_project_step(ctx, fc_tables, s):
     assert rel_l2(to_np(pd), ref_p) < tol, (rel_l2(to_np(pd), ref_p), tol)
 
 
-def test_decaying_flow_1024_one_step(ctx, fc_tables):
+@pytest.mark.parametrize("op_eval", ["fft", "direct"])
+def test_decaying_flow_1024_one_step(ctx, fc_tables, op_eval):
     """The 1024^2 workload in the launch configuration the bench times: one
     step from the manufactured flow, every output compared with the oracle."""
     import torch
     from paper_2606_06247_amd import api
     n = 1024
     s = spec((n, n), (True, True))
-    plan = api.Plan(ctx, problem(s))
+    plan = api.Plan(ctx, problem(s, op_eval=op_eval))
     nu = 1e-3
     dx = 1.0 / (n - 1)
     dt = min(0.2 * dx, 0.1 * dx * dx / nu)
@@ -168,3 +171,36 @@ def test_decaying_flow_1024_one_step(ctx, fc_tables):
     for a in range(2):
         assert rel_l2(to_np(ud[a]), ref_u[a]) < TOL
     assert rel_l2(to_np(pd), ref_p) < TOL
+
+
+@pytest.mark.parametrize("op_eval", ["fft", "direct"])
+def test_decaying_flow_trajectory_20_steps(ctx, fc_tables, op_eval):
+    """20 consecutive steps on a 128^2 version of the decaying-vortex workload
+    (inside the window where the configured scheme stays bounded): the GPU
+    trajectory follows the oracle's step by step."""
+    import torch
+    from paper_2606_06247_amd import api
+    n = 128
+    s = spec((n, n), (True, True))
+    plan = api.Plan(ctx, problem(s, op_eval=op_eval))
+    nu = 1e-3
+    dx = 1.0 / (n - 1)
+    dt = min(0.2 * dx, 0.1 * dx * dx / nu)
+    flow = synth.DecayingVortexFlow(n, nu)
+    u = list(flow.velocity(0.0))
+    ud = [to_dev(c) for c in u]
+    pd = torch.empty_like(ud[0])
+    lat = lattice(s)
+    uf = [c.copy() for c in u]
+    for k in range(20):
+        f = list(flow.force((k + 0.5) * dt))
+        w = list(flow.velocity((k + 1) * dt))
+        plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
+        u, p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
+        uf, pf = step.project_step(lat, fc_tables, uf, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+    # rounding differences grow with the scheme's corner mode (x1.46 per step),
+    # so the gate is the FP64 FFT-vs-direct trajectory difference of the oracle
+    for a in range(2):
+        tol = fft_tol(u[a], uf[a])
+        assert rel_l2(to_np(ud[a]), u[a]) < tol, (rel_l2(to_np(ud[a]), u[a]), tol)
+    assert rel_l2(to_np(pd), p) < fft_tol(p, pf)
