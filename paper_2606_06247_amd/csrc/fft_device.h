@@ -225,18 +225,22 @@ __device__ __forceinline__ constexpr bool is_pow2_radix() { return R == 2 || R =
 
 // One Stockham stage.  N: work length; Ns: product of previous radices.
 template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(cpx<T> *buf, int N, int Ns, const cpx<T> *tw,
+__device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const cpx<T> *tw,
                                                int lt, int TL, bool active) {
   constexpr int NB = nb_max(R);
   const int NR = N / R;
   const int tstride = N / (Ns * R);
   cpx<T> v[NB][R];
+  cpx<T> w1[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = lt + b * TL;
     if (active && j < NR) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NR];
+      // radix <= 4: one twiddle per butterfly, loaded before the barrier, its
+      // powers formed by multiplication; larger radices load each twiddle
+      if constexpr (R <= 4) w1[b] = tw[(j % Ns) * tstride];
     }
   }
   __syncthreads();
@@ -246,8 +250,18 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, int N, int Ns, const
     if (active && j < NR) {
       const int k = j % Ns;
       if (k != 0) {
+        if constexpr (R <= 4) {
+          cpx<T> t = w1[b];
+          v[b][1] = cmul(v[b][1], t);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * tstride]);
+          for (int r = 2; r < R; ++r) {
+            t = cmul(t, w1[b]);
+            v[b][r] = cmul(v[b][r], t);
+          }
+        } else {
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * tstride]);
+        }
       }
       const int o = (j - k) * R + k;
       if constexpr (is_pow2_radix<T, R>()) {
@@ -263,8 +277,10 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, int N, int Ns, const
 }
 
 // Forward FFT of length N = prod(radix) in place on buf (natural order).
-template <typename T>
-__device__ __forceinline__ void fft_stockham(cpx<T> *buf, const LinePlan &p, int N, int lt, int TL,
+// BIG enables the odd radices 17..31 (held whole in registers); only the PPE
+// kernels instantiate it, which keeps the register budget of the others.
+template <typename T, bool BIG = false>
+__device__ __forceinline__ void fft_stockham(Line<T> buf, const LinePlan &p, int N, int lt, int TL,
                                              bool active) {
   const cpx<T> *tw = static_cast<const cpx<T> *>(p.tw);
   int Ns = 1;
@@ -279,7 +295,18 @@ __device__ __forceinline__ void fft_stockham(cpx<T> *buf, const LinePlan &p, int
       case 8: stockham_stage<T, 8>(buf, N, Ns, tw, lt, TL, active); break;
       case 11: stockham_stage<T, 11>(buf, N, Ns, tw, lt, TL, active); break;
       case 13: stockham_stage<T, 13>(buf, N, Ns, tw, lt, TL, active); break;
-      default: break;   // the host never builds other radices
+      default:
+        if constexpr (BIG) {
+          switch (R) {
+            case 17: stockham_stage<T, 17>(buf, N, Ns, tw, lt, TL, active); break;
+            case 19: stockham_stage<T, 19>(buf, N, Ns, tw, lt, TL, active); break;
+            case 23: stockham_stage<T, 23>(buf, N, Ns, tw, lt, TL, active); break;
+            case 29: stockham_stage<T, 29>(buf, N, Ns, tw, lt, TL, active); break;
+            case 31: stockham_stage<T, 31>(buf, N, Ns, tw, lt, TL, active); break;
+            default: break;
+          }
+        }
+        break;   // the host never builds other radices
     }
     Ns *= R;
   }
@@ -289,8 +316,8 @@ __device__ __forceinline__ void fft_stockham(cpx<T> *buf, const LinePlan &p, int
 // conj_in / conj_out conjugate the input / output, which turns the forward
 // transform into the unnormalised inverse.  Ends with a barrier.  An inactive
 // line group touches no memory but executes the same barriers.
-template <typename T>
-__device__ __forceinline__ void line_dft(cpx<T> *buf, const LinePlan &p, int lt, int TL, bool conj_in,
+template <typename T, bool BIG = false>
+__device__ __forceinline__ void line_dft(Line<T> buf, const LinePlan &p, int lt, int TL, bool conj_in,
                                          bool conj_out, bool active = true) {
   if (!active) {
     lt = 1 << 30;           // every index loop below starts past its bound
@@ -300,7 +327,7 @@ __device__ __forceinline__ void line_dft(cpx<T> *buf, const LinePlan &p, int lt,
       for (int j = lt; j < p.n; j += TL) buf[j].i = -buf[j].i;
       __syncthreads();
     }
-    fft_stockham<T>(buf, p, p.n, lt, TL, active);
+    fft_stockham<T, BIG>(buf, p, p.n, lt, TL, active);
     if (conj_out) {
       for (int j = lt; j < p.n; j += TL) buf[j].i = -buf[j].i;
       __syncthreads();
@@ -320,11 +347,11 @@ __device__ __forceinline__ void line_dft(cpx<T> *buf, const LinePlan &p, int lt,
     buf[j] = v;
   }
   __syncthreads();
-  fft_stockham<T>(buf, p, p.M, lt, TL, active);
+  fft_stockham<T, BIG>(buf, p, p.M, lt, TL, active);
   // pointwise product with the filter spectrum; conjugate for the inverse FFT
   for (int j = lt; j < p.M; j += TL) buf[j] = cconj(cmul(buf[j], filt[j]));
   __syncthreads();
-  fft_stockham<T>(buf, p, p.M, lt, TL, active);
+  fft_stockham<T, BIG>(buf, p, p.M, lt, TL, active);
   for (int k = lt; k < p.n; k += TL) {
     cpx<T> v = cmul(cconj(buf[k]), chirp[k]);
     if (conj_out) v.i = -v.i;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -87,7 +88,7 @@ struct Upload {
 };
 
 // ----------------------------------------------------------------- line plans
-bool factor_direct(int n, std::vector<int> &rad) {
+bool factor_direct(int n, std::vector<int> &rad, bool big = false) {
   rad.clear();
   int m = n;
   while (m % 8 == 0 && m > 8) { rad.push_back(8); m /= 8; }
@@ -97,6 +98,11 @@ bool factor_direct(int n, std::vector<int> &rad) {
   const int odd[] = {3, 5, 7, 11, 13};
   for (int p : odd)
     while (m % p == 0) { rad.push_back(p); m /= p; }
+  if (big) {
+    const int odd_big[] = {17, 19, 23, 29, 31};
+    for (int p : odd_big)
+      while (m % p == 0) { rad.push_back(p); m /= p; }
+  }
   if (m != 1) return false;
   if (rad.empty()) rad.push_back(1);
   return (int)rad.size() <= kMaxStages;
@@ -126,14 +132,15 @@ struct LineSpec {
 
 // Build a line plan for length n.  min_TL forces a minimum thread count per
 // line (used where the kernel keeps E / TL spectrum values in registers).
-bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> &up, LinePlan &p) {
+bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> &up, LinePlan &p,
+                    bool big = false) {
   std::memset(&p, 0, sizeof(p));
   p.n = n;
   std::vector<int> rad;
   int M = n;
   if (n == 1) {
     rad = {};
-  } else if (factor_direct(n, rad)) {
+  } else if (factor_direct(n, rad, big)) {
     p.blue = 0;
   } else {
     p.blue = 1;
@@ -155,6 +162,10 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
   tl = (tl + 63) / 64 * 64;
   if (tl > kMaxThreads) return false;
   p.TL = tl;
+  // LDS padding: measured to halve the bank conflicts of power-of-two work
+  // lengths and to double them for the mixed-radix Bluestein lengths
+  p.pad = (M & (M - 1)) == 0 ? 4 : 0;
+  if (const char *e = getenv("FCSPH_LDS_PAD")) p.pad = atoi(e) == 0 ? 0 : (atoi(e) < 0 ? p.pad : atoi(e));
   const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
   // twiddles exp(-2 pi i t / M)
   {
@@ -230,7 +241,7 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
 int pick_B(const LinePlan &p, bool fp32, int want) {
   const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
   int B = want;
-  while (B > 1 && ((size_t)B * p.M * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
+  while (B > 1 && ((size_t)B * padded_len(p.M, p.pad) * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
   return B;
 }
 
@@ -506,7 +517,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     p->trig_kind[a] = kind;
     p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : nn - 2);
     const int minTL = (a == 0) ? 64 : 64;
-    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a])) {
+    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }
@@ -586,7 +597,7 @@ hipError_t x_fwd_single(fcsph_plan *p, const double *f, int fc, void *S) {
   a.outB = (char *)S + (size_t)p->H * (p->fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
   a.ostrideA = a.ostrideB = 2L * p->H;
   a.B = pick_B(a.plan, p->fp32, 4);
-  a.ldsM = a.plan.M;
+  a.ldsM = padded_len(a.plan.M, a.plan.pad);
   LaunchTimer t(p->ctx, "rows_fwd");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
 }
@@ -609,7 +620,7 @@ hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc,
   a.outB = S1;
   a.ostrideA = a.ostrideB = p->H;
   a.B = pick_B(a.plan, p->fp32, 4);
-  a.ldsM = a.plan.M;
+  a.ldsM = padded_len(a.plan.M, a.plan.pad);
   LaunchTimer t(p->ctx, "rows_fwd_pair");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
 }
@@ -632,7 +643,7 @@ ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
   c.inner_axis = 0;
   c.outer_axis = -1;
   c.B = pick_B(c.plan, p->fp32, 4);
-  c.ldsM = c.plan.M;
+  c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }
 
@@ -650,7 +661,7 @@ hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void
   a.E = p->E[0];
   a.H = p->H;
   a.B = pick_B(a.plan, p->fp32, 4);
-  a.ldsM = a.plan.M;
+  a.ldsM = padded_len(a.plan.M, a.plan.pad);
   a.spec[0] = spec0;
   a.spec[1] = spec1;
   a.spec_pitch = p->H;
@@ -727,7 +738,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.B = pick_B(r.plan, f32, 4);
-  r.ldsM = r.plan.M;
+  r.ldsM = padded_len(r.plan.M, r.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_rows_fwd");
     if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
@@ -751,7 +762,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   c.scale = p->trig_kind[1] == TRIG_DFT ? 1.0 / p->n[1] : 1.0 / (2.0 * (p->n[1] - 1));
   c.data = p->coef;
   c.B = pick_B(c.plan, f32, 4);
-  c.ldsM = c.plan.M;
+  c.ldsM = padded_len(c.plan.M, c.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_cols_solve");
     if (!chk(p, launch_ppe_cols(c, f32, p->ctx->stream), "ppe cols", st)) return st;
@@ -1109,7 +1120,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   r.E = p->E[0];
   r.H = p->H;
   r.B = 1;
-  r.ldsM = r.plan.M;
+  r.ldsM = padded_len(r.plan.M, r.plan.pad);
   r.spec[0] = p->O[0];
   r.spec[1] = p->O[1];
   r.spec[2] = p->O[3];

@@ -17,6 +17,20 @@ struct alignas(2 * sizeof(T)) cpx {
   T r, i;
 };
 
+// LDS line buffers hold one padding slot after every 16 complex values, so
+// that the strided accesses of the Stockham stages spread over the LDS banks,
+// and consecutive lines start one bank group apart.
+// The padding is a per-plan choice (pad = 0: none, else one slot per 2^pad).
+__host__ __device__ constexpr int pad_index(int p, int pad) { return pad ? p + (p >> pad) : p; }
+__host__ __device__ constexpr int padded_len(int m, int pad) { return ((pad_index(m, pad) + 8) & ~7) + 1; }
+
+template <typename T>
+struct Line {
+  cpx<T> *p;
+  int sh;     // padding shift, 31 = none
+  __device__ __forceinline__ cpx<T> &operator[](int i) const { return p[i + (i >> sh)]; }
+};
+
 // One batched 1D DFT of length n along a line, executed by a group of TL
 // threads on a line buffer of M complex values in LDS.  Direct Stockham when
 // n factors into the supported radices, otherwise Bluestein with an M-point
@@ -28,6 +42,7 @@ struct LinePlan {
   int nstages;
   int radix[kMaxStages];
   int TL;          // threads per line the plan is sized for
+  int pad;         // LDS padding shift of the line buffers (0: none)
   const void *tw;     // [M]  exp(-2 pi i t / M)
   const void *chirp;  // [n]  exp(-pi i (t^2 mod 2n) / n)        (Bluestein)
   const void *filt;   // [M]  DFT_M(wrapped conj chirp) / M       (Bluestein)

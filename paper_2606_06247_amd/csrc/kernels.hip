@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(RowsFwdArgs a) {
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
   const int line = blockIdx.x * a.B + g;
-  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
   const bool active = line < a.nlines;
   const double *pa = active ? a.inA + (size_t)line * a.strideA : nullptr;
   const double *pb = (active && line < a.nB && a.inB) ? a.inB + (size_t)line * a.strideB : nullptr;
@@ -101,7 +101,7 @@ __device__ __forceinline__ bool is_dirichlet_point(const WallInfo &w, int x, int
 // Load one packed complex line Z = A + i B from two half spectra (length H)
 // of a real length-E signal: Z[k] = A[k] + i B[k], Z[E-k] = conj(A[k]) + i conj(B[k]).
 template <typename T>
-__device__ __forceinline__ void load_packed_c2r(cpx<T> *buf, const cpx<T> *A, const cpx<T> *Bp,
+__device__ __forceinline__ void load_packed_c2r(Line<T> buf, const cpx<T> *A, const cpx<T> *Bp,
                                                 int E, int H, int lt, int TL) {
   struct AB {
     cpx<T> a, b;
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
   const long P = a.spec_pitch;
 
   if constexpr (EPI == EPI_STORE) {
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
     for (int r0 = 0; r0 < NL; r0 += G) {
       const int q = r0 + g;
       const bool act = q < NL;
-      cpx<T> *lb = smem + (size_t)(act ? q : 0) * a.ldsM;
+      Line<T> lb{smem + (size_t)(act ? q : 0) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
       if (act) {
         const cpx<T> *sA, *sB;
         if constexpr (EPI == EPI_STEP_A2) {
@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
     }
     const size_t ro = (size_t)row * a.nx;
     if constexpr (EPI == EPI_STEP_A2) {
-      const cpx<T> *b0 = smem, *b1 = smem + a.ldsM, *b2 = smem + 2 * (size_t)a.ldsM;
+      const int sh = a.plan.pad ? a.plan.pad : 31;
+      const Line<T> b0{smem, sh}, b1{smem + a.ldsM, sh}, b2{smem + 2 * (size_t)a.ldsM, sh};
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         const double u = a.u[0][ro + x], v = a.u[1][ro + x];
         const double gxu = b0[x].r, gyu = b0[x].i, gxv = b1[x].r, gyv = b1[x].i;
@@ -229,9 +230,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
         a.ustar[1][ro + x] = vs;
       }
     } else if constexpr (EPI == EPI_STEP_A3) {
-      const cpx<T> *b[6];
+      Line<T> b[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) b[k] = smem + (size_t)k * a.ldsM;
+      for (int k = 0; k < 6; ++k) b[k] = Line<T>{smem + (size_t)k * a.ldsM, a.plan.pad ? a.plan.pad : 31};
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         const double u = a.u[0][ro + x], v = a.u[1][ro + x], w = a.u[2][ro + x];
@@ -255,7 +256,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
         a.ustar[2][ro + x] = ws;
       }
     } else {
-      const cpx<T> *b0 = smem, *b1 = smem + a.ldsM;
+      const int sh = a.plan.pad ? a.plan.pad : 31;
+      const Line<T> b0{smem, sh}, b1{smem + a.ldsM, sh};
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)b0[x].r;
@@ -356,7 +358,7 @@ __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const
                      },
                      [&](int idx, cpx<T> v) {
                        const int l = idx % a.B, j = idx / a.B;
-                       smem[(size_t)l * a.ldsM + j] = v;
+                       Line<T>{smem + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j] = v;
                      });
 }
 
@@ -366,12 +368,12 @@ __device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
     const int c = c0 + l;
-    if (c < a.ninner) out[obase + (size_t)j * a.es_out + c] = smem[(size_t)l * a.ldsM + j];
+    if (c < a.ninner) out[obase + (size_t)j * a.es_out + c] = Line<T>{const_cast<cpx<T> *>(smem) + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j];
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void cols_fc(const ColsArgs &a, cpx<T> *buf, int lt, int TL) {
+__device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, int TL) {
   const int n = a.nload;
   for (int i = lt; i < a.fc.C; i += TL) {
     const double re = fc_cont(a.fc, n, i, [&](int j) { return (double)buf[j].r; });
@@ -387,7 +389,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(ColsArgs a) {
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const int bid = xcd_panel(blockIdx.x, gridDim.x);
   const int o = bid / npanel;
@@ -500,46 +502,57 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
   const int line = blockIdx.x * a.B + g;
   const int rA = 2 * line, rB = 2 * line + 1;
   const bool okA = rA < a.nrows, okB = rB < a.nrows;
   const int n = a.nx, L = a.plan.n;
   cpx<T> *cA = static_cast<cpx<T> *>(a.coef) + (size_t)rA * a.cpitch;
   cpx<T> *cB = static_cast<cpx<T> *>(a.coef) + (size_t)rB * a.cpitch;
+  auto val = [&](int r, int j) -> double {
+    const size_t o = (size_t)r * n + j;
+    return a.in_real ? a.in_real[o] : (double)a.in_float[o];
+  };
 
+  // ---- line set-up: values (forward) or coefficients (inverse), extended
   if (!a.inverse) {
-    auto val = [&](int r, int j) -> double {
-      const size_t o = (size_t)r * n + j;
-      return a.in_real ? a.in_real[o] : (double)a.in_float[o];
-    };
-    if (a.kind == TRIG_DFT) {
-      batched<8, cpx<T>>(lt, n, TL, [&](int j) { return to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0); },
+    if (a.kind == TRIG_DST1) {
+      // interior values 1..n-2; the odd extension is formed in LDS below
+      batched<8, cpx<T>>(lt, n, TL,
+                         [&](int j) {
+                           const bool in = j > 0 && j < n - 1;
+                           return to_cpx<T>(okA && in ? val(rA, j) : 0.0, okB && in ? val(rB, j) : 0.0);
+                         },
                          [&](int j, cpx<T> v) { buf[j] = v; });
-    } else if (a.kind == TRIG_DCT1) {
-      // even extension of length 2(n-1): load the n values, then mirror in LDS
-      batched<8, cpx<T>>(lt, n, TL, [&](int j) { return to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0); },
-                         [&](int j, cpx<T> v) { buf[j] = v; });
-      __syncthreads();
-      for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
     } else {
-      // odd extension of the interior values, length 2(n-1)
-      for (int j = lt; j < L; j += TL) {
-        double va = 0.0, vb = 0.0, sg = 1.0;
-        int s = j;
-        if (j > n - 1) {
-          s = L - j;
-          sg = -1.0;
-        }
-        if (s > 0 && s < n - 1) {
-          va = okA ? sg * val(rA, s) : 0.0;
-          vb = okB ? sg * val(rB, s) : 0.0;
-        }
-        buf[j] = to_cpx<T>(va, vb);
+      batched<8, cpx<T>>(lt, n, TL, [&](int j) { return to_cpx<T>(okA ? val(rA, j) : 0.0, okB ? val(rB, j) : 0.0); },
+                         [&](int j, cpx<T> v) { buf[j] = v; });
+    }
+  } else {
+    if (a.kind == TRIG_DFT) {
+      load_packed_c2r<T>(buf, okA ? cA : nullptr, okB ? cB : nullptr, n, a.ncoef, lt, TL);
+    } else if (a.kind == TRIG_DCT1) {
+      for (int j = lt; j < n; j += TL)
+        buf[j] = {okA ? get_real_coef<T>(cA, j) : T(0), okB ? get_real_coef<T>(cB, j) : T(0)};
+    } else {
+      for (int j = lt; j < n; j += TL) {
+        const bool in = j > 0 && j < n - 1;
+        buf[j] = {okA && in ? get_real_coef<T>(cA, j - 1) : T(0), okB && in ? get_real_coef<T>(cB, j - 1) : T(0)};
       }
     }
-    __syncthreads();
-    line_dft<T>(buf, a.plan, lt, TL, false, false);
+  }
+  __syncthreads();
+  if (a.kind == TRIG_DCT1) {
+    for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];             // even extension
+  } else if (a.kind == TRIG_DST1) {
+    for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));   // odd extension
+  }
+  __syncthreads();
+  const bool cj = a.inverse && a.kind == TRIG_DFT;
+  line_dft<T, true>(buf, a.plan, lt, TL, cj, cj);
+
+  // ---- results
+  if (!a.inverse) {
     if (a.kind == TRIG_DFT) {
       const T half = T(0.5);
       for (int k = lt; k < a.ncoef; k += TL) {
@@ -562,34 +575,6 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
     }
     return;
   }
-
-  // inverse: coefficient rows -> physical rows (scaled)
-  if (a.kind == TRIG_DFT) {
-    load_packed_c2r<T>(buf, okA ? cA : nullptr, okB ? cB : nullptr, n, a.ncoef, lt, TL);
-  } else if (a.kind == TRIG_DCT1) {
-    for (int j = lt; j < L; j += TL) {
-      const int s = j < n ? j : L - j;
-      buf[j] = {okA ? get_real_coef<T>(cA, s) : T(0), okB ? get_real_coef<T>(cB, s) : T(0)};
-    }
-  } else {
-    for (int j = lt; j < L; j += TL) {
-      T va = T(0), vb = T(0);
-      int s = j;
-      T sg = T(1);
-      if (j > n - 1) {
-        s = L - j;
-        sg = T(-1);
-      }
-      if (s > 0 && s < n - 1) {
-        va = okA ? sg * get_real_coef<T>(cA, s - 1) : T(0);
-        vb = okB ? sg * get_real_coef<T>(cB, s - 1) : T(0);
-      }
-      buf[j] = {va, vb};
-    }
-  }
-  __syncthreads();
-  const bool inv = a.kind == TRIG_DFT;
-  line_dft<T>(buf, a.plan, lt, TL, inv, inv);
   for (int x = lt; x < n; x += TL) {
     double va, vb;
     if (a.kind == TRIG_DST1) {
@@ -609,25 +594,23 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
 // Symmetric extension of buf[0..n) to length L and transform.  Coefficients
 // (is_values = false) or values (true) of the complex line end up in buf[0..n).
 template <typename T>
-__device__ __forceinline__ void ppe_line_transform(cpx<T> *buf, const PpeColsArgs &a, int lt, int TL,
+__device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArgs &a, int lt, int TL,
                                                    bool is_values) {
   const int n = a.nline, L = a.plan.n;
   if (a.kind == TRIG_DCT1) {
     for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
-    __syncthreads();
-    line_dft<T>(buf, a.plan, lt, TL, false, false);
   } else if (a.kind == TRIG_DST1) {
     // odd extension: positions 0 and n-1 are zero, j > n-1 holds -buf[L-j]
     if (lt == 0) {
       buf[0] = {T(0), T(0)};
       buf[n - 1] = {T(0), T(0)};
     }
-    for (int j = n + lt; j < L; j += TL) {
-      const cpx<T> v = buf[L - j];
-      buf[j] = {-v.r, -v.i};
-    }
-    __syncthreads();
-    line_dft<T>(buf, a.plan, lt, TL, false, false);
+    for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));
+  }
+  __syncthreads();
+  const bool cj = a.kind == TRIG_DFT && is_values;
+  line_dft<T, true>(buf, a.plan, lt, TL, cj, cj);
+  if (a.kind == TRIG_DST1) {
     // the DST-I of the complex line is i Z
     for (int j = lt; j < n; j += TL) buf[j] = cpi(buf[j]);
     if (is_values && lt == 0) {
@@ -635,8 +618,6 @@ __device__ __forceinline__ void ppe_line_transform(cpx<T> *buf, const PpeColsArg
       buf[n - 1] = {T(0), T(0)};
     }
     __syncthreads();
-  } else {
-    line_dft<T>(buf, a.plan, lt, TL, is_values, is_values);
   }
 }
 
@@ -647,7 +628,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(PpeColsArgs a) {
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  cpx<T> *buf = smem + (size_t)g * a.ldsM;
+  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const int bid = xcd_panel(blockIdx.x, gridDim.x);
   const int o = bid / npanel;
@@ -664,39 +645,43 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(PpeColsArgs a) {
                      },
                      [&](int idx, cpx<T> v) {
                        const int l = idx % a.B, j = idx / a.B;
-                       smem[(size_t)l * a.ldsM + j] = v;
+                       Line<T>{smem + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j] = v;
                      });
   __syncthreads();
-  ppe_line_transform<T>(buf, a, lt, TL, a.solve == 2);
-  if (a.solve == 1) {
-    // divide by -(mu_inner + mu_line + mu_outer) in FP64; a vanishing sum
-    // (the constant mode) gives zero
-    const double mo = a.mu_outer ? a.mu_outer[o] : 0.0;
-    double mir = 0.0, mii = 0.0;
-    if (c < a.ninner) {
-      if (a.inner_packed) {
-        mir = a.mu_inner[2 * c];
-        mii = (2 * c + 1 < a.inner_nmodes) ? a.mu_inner[2 * c + 1] : 1.0;
-      } else {
-        mir = mii = a.mu_inner[c];
+  // solve == 0: forward only; 1: forward, divide, inverse; 2: inverse only
+  const int npass = a.solve == 1 ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    const bool values = a.solve == 2 || pass == 1;
+    ppe_line_transform<T>(buf, a, lt, TL, values);
+    if (a.solve == 1 && pass == 0) {
+      // divide by -(mu_inner + mu_line + mu_outer) in FP64; a vanishing sum
+      // (the constant mode) gives zero
+      const double mo = a.mu_outer ? a.mu_outer[o] : 0.0;
+      double mir = 0.0, mii = 0.0;
+      if (c < a.ninner) {
+        if (a.inner_packed) {
+          mir = a.mu_inner[2 * c];
+          mii = (2 * c + 1 < a.inner_nmodes) ? a.mu_inner[2 * c + 1] : 1.0;
+        } else {
+          mir = mii = a.mu_inner[c];
+        }
       }
+      for (int k = lt; k < n; k += TL) {
+        const bool valid = a.kind != TRIG_DST1 || (k >= 1 && k <= n - 2);
+        const double ml = valid ? a.mu_line[k] + mo : 0.0;
+        const double sr = mir + ml, si = mii + ml;
+        const cpx<T> v = buf[k];
+        const double vr = (valid && sr != 0.0) ? -(double)v.r / sr : 0.0;
+        const double vi = (valid && si != 0.0) ? -(double)v.i / si : 0.0;
+        buf[k] = to_cpx<T>(vr * a.scale, vi * a.scale);
+      }
+      __syncthreads();
     }
-    for (int k = lt; k < n; k += TL) {
-      const bool valid = a.kind != TRIG_DST1 || (k >= 1 && k <= n - 2);
-      const double ml = valid ? a.mu_line[k] + mo : 0.0;
-      const double sr = mir + ml, si = mii + ml;
-      const cpx<T> v = buf[k];
-      const double vr = (valid && sr != 0.0) ? -(double)v.r / sr : 0.0;
-      const double vi = (valid && si != 0.0) ? -(double)v.i / si : 0.0;
-      buf[k] = to_cpx<T>(vr * a.scale, vi * a.scale);
-    }
-    __syncthreads();
-    ppe_line_transform<T>(buf, a, lt, TL, true);
   }
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
     const int cc = c0 + l;
-    if (cc < a.ninner) data[(size_t)j * a.es + cc] = smem[(size_t)l * a.ldsM + j];
+    if (cc < a.ninner) data[(size_t)j * a.es + cc] = Line<T>{smem + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j];
   }
 }
 
