@@ -180,6 +180,44 @@ class Context:
             pass
 
 
+def make_desc(prob: "Problem"):
+    """The C descriptor of a Problem, with the FC map arrays it points into
+    (keep them alive while the descriptor is used)."""
+    tabs = fctables.load(prob.fc_d, prob.fc_C)
+    mdir = np.ascontiguousarray(tabs["dirichlet"], dtype=np.float64)
+    mneu = np.ascontiguousarray(tabs["neumann"], dtype=np.float64)
+    d = Desc()
+    d.ndim = prob.ndim
+    for a in range(prob.ndim):
+        d.n[a] = prob.n[a]
+        d.axis[a] = WALLED if prob.walled[a] else PERIODIC
+        if prob.walled[a]:
+            for s in range(2):
+                d.vel_bc[a][s] = _bc(prob.vel_bc[a][s])
+                d.prs_bc[a][s] = _bc(prob.prs_bc[a][s])
+    d.dx = prob.dx
+    d.fc_d, d.fc_C = prob.fc_d, prob.fc_C
+    d.fc_M_dir = mdir.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.fc_M_neu = mneu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.kernel = KERNEL_WENDLAND_C2
+    d.h_over_dx = prob.h_over_dx
+    d.prec = FP32_MIXED if prob.precision == "fp32" else FP64
+    d.ppe_domain = PPE_PHYSICAL
+    d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
+    d.rho = prob.rho
+    d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT}[prob.op_eval]
+    return d, mdir, mneu
+
+
+def workspace_bytes(prob: "Problem") -> int:
+    """Device workspace bytes a plan for prob needs (host-only query)."""
+    d, _m1, _m2 = make_desc(prob)
+    nbytes = ctypes.c_size_t()
+    _check(lib().fcsph_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), None,
+           "fcsph_plan_workspace_bytes")
+    return nbytes.value
+
+
 class Plan:
     """A plan for one lattice; owns its device workspace (a torch tensor)."""
 
@@ -187,30 +225,8 @@ class Plan:
         import torch
         L = lib()
         self.ctx, self.prob = ctx, prob
-        tabs = fctables.load(prob.fc_d, prob.fc_C)
-        self._mdir = np.ascontiguousarray(tabs["dirichlet"], dtype=np.float64)
-        self._mneu = np.ascontiguousarray(tabs["neumann"], dtype=np.float64)
-        d = Desc()
-        d.ndim = prob.ndim
-        for a in range(prob.ndim):
-            d.n[a] = prob.n[a]
-            d.axis[a] = WALLED if prob.walled[a] else PERIODIC
-            if prob.walled[a]:
-                for s in range(2):
-                    d.vel_bc[a][s] = _bc(prob.vel_bc[a][s])
-                    d.prs_bc[a][s] = _bc(prob.prs_bc[a][s])
-        d.dx = prob.dx
-        d.fc_d, d.fc_C = prob.fc_d, prob.fc_C
-        d.fc_M_dir = self._mdir.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        d.fc_M_neu = self._mneu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        d.kernel = KERNEL_WENDLAND_C2
-        d.h_over_dx = prob.h_over_dx
-        d.prec = FP32_MIXED if prob.precision == "fp32" else FP64
-        d.ppe_domain = PPE_PHYSICAL
-        d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
-        d.rho = prob.rho
-        d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT}[prob.op_eval]
-        self.desc = d
+        self.desc, self._mdir, self._mneu = make_desc(prob)
+        d = self.desc
         nbytes = ctypes.c_size_t()
         _check(L.fcsph_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)), None,
                "fcsph_plan_workspace_bytes")

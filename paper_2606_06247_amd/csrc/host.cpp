@@ -665,6 +665,8 @@ hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void
   a.spec[0] = spec0;
   a.spec[1] = spec1;
   a.spec_pitch = p->H;
+  a.rpp = p->n[1];
+  a.prow = p->nd == 3 ? p->E[1] : p->n[1];
   a.out[0] = out0;
   a.out[1] = out1;
   a.out_is_double = out_double ? 1 : 0;
@@ -682,6 +684,77 @@ WallInfo wall_info(fcsph_plan *p) {
     for (int s = 0; s < 2; ++s) w.dir[a][s] = p->walled[a] && p->d.vel_bc[a][s] == FCSPH_BC_DIRICHLET;
   }
   return w;
+}
+
+// ---- 3D (walls in y; x, z periodic): strided passes along y and z.
+// Spectrum arrays: x half spectra [nz][rows][H] with rows = ny (compact) or
+// E_y (y-extended, also used for the y-restricted results in place).
+ColsArgs y_pass_args(fcsph_plan *p, int mode, int fc) {
+  ColsArgs c{};
+  c.plan = p->op[1];
+  c.mode = mode;
+  c.ninner = p->H;
+  c.nouter = p->n[2];
+  c.es = p->H;
+  c.es_out = p->H;
+  if (mode == COLS_FWD) {
+    c.os_in = (long)p->n[1] * p->H;
+    c.nload = p->n[1];
+    c.nstore = p->E[1];
+  } else {
+    c.os_in = (long)p->E[1] * p->H;
+    c.nload = p->E[1];
+    c.nstore = p->n[1];
+  }
+  c.os_out = (long)p->E[1] * p->H;
+  c.fc = walls_for(p, 1, fc);
+  c.st = p->st;
+  c.line_axis = 1;
+  c.inner_axis = 0;
+  c.outer_axis = 2;
+  c.B = pick_B(c.plan, p->fp32, 4);
+  c.ldsM = padded_len(c.plan.M, c.plan.pad);
+  return c;
+}
+
+ColsArgs z_pass_args(fcsph_plan *p, int mode) {
+  ColsArgs c{};
+  c.plan = p->op[2];
+  c.mode = mode;
+  c.ninner = p->H;
+  c.nouter = p->E[1];
+  c.es = (long)p->E[1] * p->H;
+  c.es_out = c.es;
+  c.os_in = c.os_out = p->H;
+  c.nload = c.nstore = p->n[2];
+  c.fc = walls_for(p, 2, FCSPH_FIELD_VELOCITY);   // z is periodic: off
+  c.st = p->st;
+  c.line_axis = 2;
+  c.inner_axis = 0;
+  c.outer_axis = 1;
+  c.B = pick_B(c.plan, p->fp32, 4);
+  c.ldsM = padded_len(c.plan.M, c.plan.pad);
+  return c;
+}
+
+// y forward of nf spectra (FC along y with the field class's walls)
+hipError_t y_fwd(fcsph_plan *p, int nf, void *const *in, void *const *out, int fc) {
+  ColsArgs c = y_pass_args(p, COLS_FWD, fc);
+  for (int f = 0; f < nf; ++f) {
+    c.in[f] = in[f];
+    c.out[f][0] = out[f];
+  }
+  return cols_launch(p, c, nf, "cols_y_fwd");
+}
+
+// y inverse of nf spectra in place (y-extended layout), restricted to ny rows
+hipError_t y_inv(fcsph_plan *p, int nf, void *const *buf) {
+  ColsArgs c = y_pass_args(p, COLS_INV, FCSPH_FIELD_VELOCITY);
+  for (int f = 0; f < nf; ++f) {
+    c.in[f] = buf[f];
+    c.out[f][0] = buf[f];
+  }
+  return cols_launch(p, c, nf, "cols_y_inv");
 }
 
 DirectArgs direct_base(fcsph_plan *p, int fc) {
@@ -718,12 +791,94 @@ hipError_t direct_launch(fcsph_plan *p, const DirectArgs &a, int mode, const cha
   return launch_direct(a, mode, p->ctx->stream);
 }
 
+// 3D PPE (x, z periodic; y walled): DFT_x rows, then along y (forward),
+// along z (forward, FP64 divide, inverse, all inverse scales), along y
+// (inverse), and the inverse x DFT.
+fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
+  fcsph_status st = FCSPH_OK;
+  const bool f32 = p->fp32;
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  PpeRowsArgs r{};
+  r.plan = p->trig[0];
+  r.kind = p->trig_kind[0];
+  r.inverse = 0;
+  r.nrows = ny * nz;
+  r.nx = nx;
+  r.ncoef = p->ncoef[0];
+  r.cpitch = p->cpitch;
+  r.in_real = f32 ? nullptr : (const double *)rhs;
+  r.in_float = f32 ? (const float *)rhs : nullptr;
+  r.coef = p->coef;
+  r.B = pick_B(r.plan, f32, 4);
+  r.ldsM = padded_len(r.plan.M, r.plan.pad);
+  {
+    LaunchTimer t(p->ctx, "ppe_rows_fwd");
+    if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
+  }
+  PpeColsArgs cy{};
+  cy.plan = p->trig[1];
+  cy.kind = p->trig_kind[1];
+  cy.ninner = p->cpitch;
+  cy.nouter = nz;
+  cy.es = p->cpitch;
+  cy.os = (long)ny * p->cpitch;
+  cy.nline = ny;
+  cy.ncoef = p->ncoef[1];
+  cy.data = p->coef;
+  cy.B = pick_B(cy.plan, f32, 4);
+  cy.ldsM = padded_len(cy.plan.M, cy.plan.pad);
+  cy.solve = 0;
+  {
+    LaunchTimer t(p->ctx, "ppe_cols_y_fwd");
+    if (!chk(p, launch_ppe_cols(cy, f32, p->ctx->stream), "ppe y", st)) return st;
+  }
+  PpeColsArgs cz{};
+  cz.plan = p->trig[2];
+  cz.kind = p->trig_kind[2];
+  cz.ninner = p->cpitch;
+  cz.nouter = ny;
+  cz.es = (long)ny * p->cpitch;
+  cz.os = p->cpitch;
+  cz.nline = nz;
+  cz.ncoef = p->ncoef[2];
+  cz.solve = 1;
+  cz.mu_line = p->mu[2];
+  cz.mu_inner = p->mu[0];
+  cz.inner_packed = 0;
+  cz.inner_nmodes = p->ncoef[0];
+  cz.mu_outer = p->mu[1];
+  const double sy = p->trig_kind[1] == TRIG_DFT ? 1.0 / ny : 1.0 / (2.0 * (ny - 1));
+  cz.scale = sy / nz;
+  cz.data = p->coef;
+  cz.B = pick_B(cz.plan, f32, 4);
+  cz.ldsM = padded_len(cz.plan.M, cz.plan.pad);
+  {
+    LaunchTimer t(p->ctx, "ppe_cols_z_solve");
+    if (!chk(p, launch_ppe_cols(cz, f32, p->ctx->stream), "ppe z", st)) return st;
+  }
+  cy.solve = 2;
+  {
+    LaunchTimer t(p->ctx, "ppe_cols_y_inv");
+    if (!chk(p, launch_ppe_cols(cy, f32, p->ctx->stream), "ppe y inv", st)) return st;
+  }
+  r.inverse = 1;
+  r.in_real = nullptr;
+  r.in_float = nullptr;
+  r.out = phi;
+  r.scale = 1.0 / nx;
+  {
+    LaunchTimer t(p->ctx, "ppe_rows_inv");
+    if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows inverse", st)) return st;
+  }
+  return FCSPH_OK;
+}
+
 fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   fcsph_status st = FCSPH_OK;
-  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D PPE not built yet");
   for (int a = 0; a < p->nd; ++a)
     if (p->trig_kind[a] < 0)
       return fail(p->ctx, FCSPH_E_UNSUPPORTED, "mixed Dirichlet/Neumann pressure walls on one axis are not built");
+  if (p->nd == 3) return run_ppe3(p, rhs, phi);
   const bool f32 = p->fp32;
   // P1: rows forward
   PpeRowsArgs r{};
@@ -969,8 +1124,23 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
   if (!f || !g) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
   for (int a = 0; a < p->nd; ++a)
     if (!g[a]) return fail(p->ctx, FCSPH_E_INVALID, "null output");
-  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
   fcsph_status st = FCSPH_OK;
+  if (p->nd == 3) {
+    if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "grad x", st)) return st;
+    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc), "grad y", st)) return st;
+    ColsArgs c = z_pass_args(p, COLS_OP);
+    c.in[0] = p->Y[0];
+    for (int q = 0; q < 3; ++q) {
+      c.out[0][q] = p->O[q];
+      c.sym[q] = q;
+    }
+    c.nout = 3;
+    if (!chk(p, cols_launch(p, c, 1, "cols_z_op"), "grad z", st)) return st;
+    if (!chk(p, y_inv(p, 3, &p->O[0]), "grad y inv", st)) return st;
+    if (!chk(p, x_inv_store(p, p->O[0], p->O[1], g[0], g[1], !p->fp32, 1.0), "grad x inv", st)) return st;
+    if (!chk(p, x_inv_store(p, p->O[2], nullptr, g[2], nullptr, !p->fp32, 1.0), "grad x inv", st)) return st;
+    return FCSPH_OK;
+  }
   if (p->direct) {
     DirectArgs a = direct_base(p, fc);
     a.in[0] = f;
@@ -995,8 +1165,20 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
 fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *lap) {
   if (!p) return FCSPH_E_INVALID;
   if (!f || !lap) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
-  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
   fcsph_status st = FCSPH_OK;
+  if (p->nd == 3) {
+    if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
+    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc), "lap y", st)) return st;
+    ColsArgs c = z_pass_args(p, COLS_OP);
+    c.in[0] = p->Y[0];
+    c.out[0][0] = p->O[0];
+    c.sym[0] = SYM_LAP;
+    c.nout = 1;
+    if (!chk(p, cols_launch(p, c, 1, "cols_z_op"), "lap z", st)) return st;
+    if (!chk(p, y_inv(p, 1, &p->O[0]), "lap y inv", st)) return st;
+    if (!chk(p, x_inv_store(p, p->O[0], nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
+    return FCSPH_OK;
+  }
   if (p->direct) {
     DirectArgs a = direct_base(p, fc);
     a.in[0] = f;
@@ -1012,6 +1194,24 @@ fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *la
   c.sym[0] = SYM_LAP;
   if (!chk(p, cols_launch(p, c, 1, "cols_op"), "lap y", st)) return st;
   if (!chk(p, x_inv_store(p, p->O[0], nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
+  return FCSPH_OK;
+}
+
+static fcsph_status div3_impl(fcsph_plan *p, const double *const *u, void *out, bool out_double, double scale) {
+  fcsph_status st = FCSPH_OK;
+  if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
+  if (!chk(p, x_fwd_single(p, u[2], FCSPH_FIELD_VELOCITY, p->S[2]), "div x", st)) return st;
+  if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY), "div y", st)) return st;
+  ColsArgs c = z_pass_args(p, COLS_DIV);
+  for (int f = 0; f < 3; ++f) {
+    c.in[f] = p->Y[f];
+    c.sym[f] = f;
+  }
+  c.out[0][0] = p->O[0];
+  c.nout = 1;
+  if (!chk(p, cols_launch(p, c, 1, "cols_z_div"), "div z", st)) return st;
+  if (!chk(p, y_inv(p, 1, &p->O[0]), "div y inv", st)) return st;
+  if (!chk(p, x_inv_store(p, p->O[0], nullptr, out, nullptr, out_double, scale), "div x inv", st)) return st;
   return FCSPH_OK;
 }
 
@@ -1046,7 +1246,7 @@ fcsph_status fcsph_spectral_div(fcsph_plan *p, const double *const *u, void *div
   if (!u || !div) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
   for (int a = 0; a < p->nd; ++a)
     if (!u[a]) return fail(p->ctx, FCSPH_E_INVALID, "null input");
-  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D operators not built yet");
+  if (p->nd == 3) return div3_impl(p, u, div, !p->fp32, 1.0);
   return div_impl(p, u[0], u[1], div, !p->fp32, 1.0);
 }
 
@@ -1064,10 +1264,83 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     if (!u[a]) return fail(p->ctx, FCSPH_E_INVALID, "null velocity component");
   if (!(dt > 0.0) || !std::isfinite(dt) || !(nu >= 0.0) || !std::isfinite(nu))
     return fail(p->ctx, FCSPH_E_INVALID, "dt must be positive and nu non-negative");
-  if (p->nd != 2) return fail(p->ctx, FCSPH_E_UNSUPPORTED, "3D step not built yet");
   fcsph_status st = FCSPH_OK;
   hipStream_t s = p->ctx->stream;
   const bool f32 = p->fp32;
+  if (p->nd == 3) {
+    // A: 12 derivatives of (u, v, w), fused u*
+    if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "step3 A x", st)) return st;
+    if (!chk(p, x_fwd_single(p, u[2], FCSPH_FIELD_VELOCITY, p->S[2]), "step3 A x", st)) return st;
+    if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY), "step3 A y", st)) return st;
+    ColsArgs c = z_pass_args(p, COLS_OP);
+    for (int f = 0; f < 3; ++f) {
+      c.in[f] = p->Y[f];
+      for (int q = 0; q < 4; ++q) c.out[f][q] = p->O[4 * f + q];
+    }
+    c.nout = 4;
+    c.sym[0] = SYM_GX;
+    c.sym[1] = SYM_GY;
+    c.sym[2] = SYM_GZ;
+    c.sym[3] = SYM_LAP;
+    if (!chk(p, cols_launch(p, c, 3, "cols_z_op_step_a"), "step3 A z", st)) return st;
+    for (int g = 0; g < 4; ++g)
+      if (!chk(p, y_inv(p, 3, &p->O[3 * g]), "step3 A y inv", st)) return st;
+    RowsInvArgs r{};
+    r.plan = p->op[0];
+    r.nrows = p->n[1] * p->n[2];
+    r.nx = p->n[0];
+    r.E = p->E[0];
+    r.H = p->H;
+    r.B = 1;
+    r.ldsM = padded_len(r.plan.M, r.plan.pad);
+    const int order[12] = {0, 1, 2, 4, 5, 6, 8, 9, 10, 3, 7, 11};
+    for (int k = 0; k < 12; ++k) r.spec[k] = p->O[order[k]];
+    r.spec_pitch = p->H;
+    r.rpp = p->n[1];
+    r.prow = p->E[1];
+    for (int q = 0; q < 3; ++q) {
+      r.u[q] = u[q];
+      r.f[q] = force ? force[q] : nullptr;
+      r.wall[q] = wall_vel ? wall_vel[q] : nullptr;
+      r.ustar[q] = p->ustar[q];
+      r.unew[q] = u[q];
+    }
+    r.dt = dt;
+    r.nu = nu;
+    r.dt_over_rho = dt / p->d.rho;
+    r.wi = wall_info(p);
+    {
+      LaunchTimer t(p->ctx, "rows_inv_step_a3");
+      if (!chk(p, launch_rows_inv(r, EPI_STEP_A3, f32, s), "step3 A x inv", st)) return st;
+    }
+    // B, C
+    st = div3_impl(p, p->ustar, p->rhs, !f32, p->d.rho / dt);
+    if (st != FCSPH_OK) return st;
+    double *phi = p_out ? p_out : p->phi;
+    st = run_ppe(p, p->rhs, phi);
+    if (st != FCSPH_OK) return st;
+    // D
+    if (!chk(p, x_fwd_single(p, phi, FCSPH_FIELD_PRESSURE, p->S[0]), "step3 D x", st)) return st;
+    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], FCSPH_FIELD_PRESSURE), "step3 D y", st)) return st;
+    ColsArgs cd = z_pass_args(p, COLS_OP);
+    cd.in[0] = p->Y[0];
+    for (int q = 0; q < 3; ++q) {
+      cd.out[0][q] = p->O[q];
+      cd.sym[q] = q;
+    }
+    cd.nout = 3;
+    if (!chk(p, cols_launch(p, cd, 1, "cols_z_op_step_d"), "step3 D z", st)) return st;
+    if (!chk(p, y_inv(p, 3, &p->O[0]), "step3 D y inv", st)) return st;
+    RowsInvArgs rd = r;
+    rd.spec[0] = p->O[0];
+    rd.spec[1] = p->O[1];
+    rd.spec[2] = p->O[2];
+    {
+      LaunchTimer t(p->ctx, "rows_inv_step_d3");
+      if (!chk(p, launch_rows_inv(rd, EPI_STEP_D3, f32, s), "step3 D x inv", st)) return st;
+    }
+    return FCSPH_OK;
+  }
   if (p->direct) {
     DirectArgs a = direct_base(p, FCSPH_FIELD_VELOCITY);
     a.in[0] = u[0];
@@ -1128,6 +1401,8 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   r.spec[4] = p->O[2];
   r.spec[5] = p->O[5];
   r.spec_pitch = p->H;
+  r.rpp = p->n[1];
+  r.prow = p->n[1];
   r.u[0] = u[0];
   r.u[1] = u[1];
   r.f[0] = force ? force[0] : nullptr;

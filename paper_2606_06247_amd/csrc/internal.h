@@ -105,8 +105,12 @@ struct RowsInvArgs {
   int B;               // line groups per workgroup
   int ldsM;
   // EPI_STORE: line l packs rows (2l, 2l+1) of one output spectrum array
-  const void *spec[6]; // cpx<T> spectrum row arrays (row pitch H)
+  const void *spec[12]; // cpx<T> spectrum row arrays (row pitch H)
   long spec_pitch;     // complex elements per row
+  // row r of a spectrum array starts at ((r / rpp) * prow + r % rpp) * spec_pitch:
+  // rpp physical rows per plane, prow rows stored per plane (3D: y-extended
+  // arrays hold E_y rows per z plane; 2D: prow = rpp)
+  int rpp, prow;
   void *out[2];        // EPI_STORE outputs (row pitch nx)
   int out_is_double;
   double scale;

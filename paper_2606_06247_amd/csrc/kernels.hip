@@ -122,6 +122,10 @@ __device__ __forceinline__ void load_packed_c2r(Line<T> buf, const cpx<T> *A, co
                  });
 }
 
+__device__ __forceinline__ size_t spec_row(const RowsInvArgs &a, int r) {
+  return ((size_t)(r / a.rpp) * a.prow + (r % a.rpp)) * (size_t)a.spec_pitch;
+}
+
 template <typename T, int EPI>
 __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -140,8 +144,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
     int rA = pair ? line : 2 * line;
     int rB = pair ? line : 2 * line + 1;
     const bool okA = rA < a.nrows, okB = rB < a.nrows;
-    const cpx<T> *sA = okA ? static_cast<const cpx<T> *>(a.spec[0]) + (size_t)rA * P : nullptr;
-    const cpx<T> *sB = okB ? static_cast<const cpx<T> *>(pair ? a.spec[1] : a.spec[0]) + (size_t)rB * P : nullptr;
+    const cpx<T> *sA = okA ? static_cast<const cpx<T> *>(a.spec[0]) + spec_row(a, rA) : nullptr;
+    const cpx<T> *sB = okB ? static_cast<const cpx<T> *>(pair ? a.spec[1] : a.spec[0]) + spec_row(a, rB) : nullptr;
     load_packed_c2r<T>(buf, sA, sB, a.E, a.H, lt, TL);
     __syncthreads();
     line_dft<T>(buf, a.plan, lt, TL, true, true);
@@ -159,8 +163,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
   } else if constexpr (EPI == EPI_STEP_D2) {
     const int row = blockIdx.x * a.B + g;
     const bool ok = row < a.nrows;
-    const cpx<T> *sA = ok ? static_cast<const cpx<T> *>(a.spec[0]) + (size_t)row * P : nullptr;
-    const cpx<T> *sB = ok ? static_cast<const cpx<T> *>(a.spec[1]) + (size_t)row * P : nullptr;
+    const cpx<T> *sA = ok ? static_cast<const cpx<T> *>(a.spec[0]) + spec_row(a, row) : nullptr;
+    const cpx<T> *sB = ok ? static_cast<const cpx<T> *>(a.spec[1]) + spec_row(a, row) : nullptr;
     load_packed_c2r<T>(buf, sA, sB, a.E, a.H, lt, TL);
     __syncthreads();
     line_dft<T>(buf, a.plan, lt, TL, true, true);
@@ -182,28 +186,24 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
     // keeps the barriers).  Line buffers: NL consecutive slots of ldsM.
     //  A2: 0 (Gx u, Gy u) 1 (Gx v, Gy v) 2 (L u, L v)            from spec[2q], spec[2q+1]
     //  A3: 0 (Gx u, Gy u) 1 (Gz u, Gx v) 2 (Gy v, Gz v) 3 (Gx w, Gy w) 4 (Gz w, L u) 5 (L v, L w)
-    //      from spec[q] and the spectrum that follows it at nrows * spec_pitch
+    //      from spec[2q], spec[2q+1]
     //  D3: 0 (Gx p, Gy p) from spec[0], spec[1];  1 (Gz p, 0) from spec[2]
     constexpr int NL = EPI == EPI_STEP_A2 ? 3 : EPI == EPI_STEP_A3 ? 6 : 2;
     const int G = blockDim.x / TL;
     const int row = blockIdx.x;
-    const size_t plane = (size_t)a.nrows * P;
+    const size_t ro_s = spec_row(a, row);
     for (int r0 = 0; r0 < NL; r0 += G) {
       const int q = r0 + g;
       const bool act = q < NL;
       Line<T> lb{smem + (size_t)(act ? q : 0) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
       if (act) {
         const cpx<T> *sA, *sB;
-        if constexpr (EPI == EPI_STEP_A2) {
-          sA = static_cast<const cpx<T> *>(a.spec[2 * q]) + (size_t)row * P;
-          sB = static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + (size_t)row * P;
-        } else if constexpr (EPI == EPI_STEP_A3) {
-          const cpx<T> *base = static_cast<const cpx<T> *>(a.spec[q]);
-          sA = base + (size_t)row * P;
-          sB = base + plane + (size_t)row * P;
+        if constexpr (EPI == EPI_STEP_A2 || EPI == EPI_STEP_A3) {
+          sA = static_cast<const cpx<T> *>(a.spec[2 * q]) + ro_s;
+          sB = static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + ro_s;
         } else {
-          sA = static_cast<const cpx<T> *>(a.spec[q == 0 ? 0 : 2]) + (size_t)row * P;
-          sB = q == 0 ? static_cast<const cpx<T> *>(a.spec[1]) + (size_t)row * P : nullptr;
+          sA = static_cast<const cpx<T> *>(a.spec[q == 0 ? 0 : 2]) + ro_s;
+          sB = q == 0 ? static_cast<const cpx<T> *>(a.spec[1]) + ro_s : nullptr;
         }
         load_packed_c2r<T>(lb, sA, sB, a.E, a.H, lt, TL);
       }
@@ -400,7 +400,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(ColsArgs a) {
   const double2 *ph_line = a.st.ph[a.line_axis];
 
   if constexpr (MODE == COLS_FWD || MODE == COLS_INV) {
-    const cpx<T> *in = static_cast<const cpx<T> *>(a.in[0]);
+    const int f = blockIdx.y;
+    const cpx<T> *in = static_cast<const cpx<T> *>(a.in[f]);
     cols_load<T>(a, smem, in, c0, obase_in, a.nload);
     __syncthreads();
     if (MODE == COLS_FWD && a.fc.on) {
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(ColsArgs a) {
     }
     constexpr bool inv = MODE == COLS_INV;
     line_dft<T>(buf, a.plan, lt, TL, inv, inv);
-    cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[0][0]), c0, obase_out, a.nstore);
+    cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][0]), c0, obase_out, a.nstore);
   } else if constexpr (MODE == COLS_OP) {
     const int f = blockIdx.y;
     const cpx<T> *in = static_cast<const cpx<T> *>(a.in[f]);

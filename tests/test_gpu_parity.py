@@ -204,3 +204,96 @@ def test_decaying_flow_trajectory_20_steps(ctx, fc_tables, op_eval):
         tol = fft_tol(u[a], uf[a])
         assert rel_l2(to_np(ud[a]), u[a]) < tol, (rel_l2(to_np(ud[a]), u[a]), tol)
     assert rel_l2(to_np(pd), p) < fft_tol(p, pf)
+
+
+# ---------------------------------------------------------------- 3D channel
+# walls on y only (x, z periodic): the configuration of the 3D channel flow.
+CASES_3D = [
+    spec((32, 40, 24), (False, True, False)),                                   # Dirichlet u, Neumann p
+    spec((27, 33, 15), (False, True, False), vel=(None, ("D", "N"), None),
+         prs=(None, ("D", "D"), None)),                                         # odd row count, mixed u walls
+    spec((20, 36, 14), (False, True, False), vel=(None, ("N", "N"), None)),     # Neumann u, Dirichlet p
+]
+
+
+def channel_fields(s, seed):
+    flow = synth.ChannelFlow3D(s["n"], seed, seed + 1)
+    return [np.ascontiguousarray(c) for c in flow.u]
+
+
+@pytest.mark.parametrize("s", CASES_3D, ids=lambda s: f"{s['n']}-{s['vel'][1]}")
+def test_fc_extend_3d(ctx, fc_tables, s):
+    from paper_2606_06247_amd import api
+    plan = api.Plan(ctx, problem(s))
+    lat = lattice(s)
+    f = synth.random_field(tuple(reversed(s["n"])), 5)
+    class LD:
+        def M(self, bc):
+            return fc_tables.M(bc).astype(np.longdouble)
+    for fc_class, bcs in ((api.VELOCITY, lat.vel_bc), (api.PRESSURE, lat.prs_bc)):
+        got = to_np(plan.fc_extend(to_dev(f), fc_class))
+        ref = ofc.extend(f.astype(np.longdouble), lat.walled, bcs, LD())
+        assert got.shape == ref.shape
+        assert np.array_equal(got[tuple(slice(0, k) for k in f.shape)], f)
+        bound = fc_rounding_bound(f, lat, bcs, fc_tables)
+        err = np.abs(got - ref.astype(np.float64))
+        assert np.all(err <= bound), float(np.max(err / np.maximum(bound, 1e-300)))
+
+
+@pytest.mark.parametrize("s", CASES_3D, ids=lambda s: f"{s['n']}-{s['vel'][1]}")
+def test_operators_3d(ctx, fc_tables, s):
+    from paper_2606_06247_amd import api
+    plan = api.Plan(ctx, problem(s))
+    ops = operators.Operators(lattice(s), fc_tables)
+    opf = operators.Operators(lattice(s), fc_tables, mode="fft")
+    u = channel_fields(s, 30)
+    r = synth.random_field(tuple(reversed(s["n"])), 6)
+    for f in (u[0], r):
+        for fc_class, name in ((api.VELOCITY, "u"), (api.PRESSURE, "p")):
+            got = [to_np(t) for t in plan.spectral_grad(to_dev(f), fc_class)]
+            ref = ops.grad(f, name)
+            reff = opf.grad(f, name)
+            for a in range(3):
+                tol = fft_tol(ref[a], reff[a])
+                assert rel_l2(got[a], ref[a]) < tol, (name, a, rel_l2(got[a], ref[a]), tol)
+            lap = to_np(plan.spectral_lap(to_dev(f), fc_class))
+            ref = ops.lap(f, name)
+            tol = fft_tol(ref, opf.lap(f, name))
+            assert rel_l2(lap, ref) < tol, (rel_l2(lap, ref), tol)
+    div = to_np(plan.spectral_div([to_dev(c) for c in u]))
+    ref = ops.div(u)
+    tol = fft_tol(ref, opf.div(u))
+    assert rel_l2(div, ref) < tol, (rel_l2(div, ref), tol)
+
+
+@pytest.mark.parametrize("eig", ["spectral", "fd2"])
+@pytest.mark.parametrize("s", CASES_3D, ids=lambda s: f"{s['n']}-{s['prs'][1]}")
+def test_ppe_solve_3d(ctx, s, eig):
+    from paper_2606_06247_amd import api
+    plan = api.Plan(ctx, problem(s, eig=eig))
+    b = synth.random_field(tuple(reversed(s["n"])), 7)
+    got = to_np(plan.ppe_solve(to_dev(b)))
+    ref = ppe.solve(b, lattice(s), family=eig)
+    assert rel_l2(got, ref) < TOL, rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("s", CASES_3D, ids=lambda s: f"{s['n']}-{s['vel'][1]}-{s['prs'][1]}")
+def test_project_step_3d(ctx, fc_tables, s):
+    import torch
+    from paper_2606_06247_amd import api
+    plan = api.Plan(ctx, problem(s))
+    lat = lattice(s)
+    u = channel_fields(s, 40)
+    f = channel_fields(s, 42)
+    w = [c.copy() for c in u]
+    dt, nu = 1e-4, 1e-3
+    ud = [to_dev(c) for c in u]
+    pd = torch.empty_like(ud[0])
+    plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
+    ref_u, ref_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
+    fft_u, fft_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+    for a in range(3):
+        tol = fft_tol(ref_u[a], fft_u[a])
+        assert rel_l2(to_np(ud[a]), ref_u[a]) < tol, (a, rel_l2(to_np(ud[a]), ref_u[a]), tol)
+    tol = fft_tol(ref_p, fft_p)
+    assert rel_l2(to_np(pd), ref_p) < tol, (rel_l2(to_np(pd), ref_p), tol)

@@ -65,3 +65,26 @@ def test_zero_state_stays_zero(fc_tables):
     z = [np.zeros((16, 16)), np.zeros((16, 16))]
     un, p = step.project_step(lat, fc_tables, z)
     assert all(np.max(np.abs(c)) == 0 for c in un) and np.max(np.abs(p)) == 0
+
+
+def test_channel_3d_projection_walls_and_modes(fc_tables):
+    """The 3D channel lattice: P-PRJ1 in EXTENDED mode, Dirichlet walls and
+    the direct / FFT operator modes in PHYSICAL mode."""
+    n = (12, 17, 10)
+    lat = Lattice(n=n, walled=(False, True, False), dx=1.0 / 16, vel_bc=(None, ("D", "D"), None),
+                  prs_bc=(None, ("N", "N"), None))
+    u = synth.ChannelFlow3D(n, 1, 2).u
+    f = synth.ChannelFlow3D(n, 3, 4).u
+    w = [c + 0.25 for c in synth.ChannelFlow3D(n, 5, 6).u]
+    unew, phi, parts = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=1e-3, nu=1e-3,
+                                         mode="extended", return_parts=True)
+    S = parts["S"]
+    div_new = sum(S[a] * parts["uhat_new"][a] for a in range(3))
+    assert np.max(np.abs(div_new)) < 1e-13 * np.max(np.abs(parts["D"]))
+    a, pa = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=1e-4, nu=1e-3)
+    b, pb = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=1e-4, nu=1e-3, opmode="fft")
+    for c in range(3):
+        assert np.array_equal(a[c][:, 0, :], w[c][:, 0, :])
+        assert np.array_equal(a[c][:, -1, :], w[c][:, -1, :])
+        assert np.max(np.abs(a[c] - b[c])) < 1e-10 * np.max(np.abs(a[c]))
+    assert np.max(np.abs(pa - pb)) < 1e-10 * np.max(np.abs(pa))
