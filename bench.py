@@ -1,22 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the FC(Gram)-based spectral ISPH projection step on one MI355X.
 
-Workload: 2D 1024 x 1024 lattice on [0,1]^2 with walls on all four sides
-(Dirichlet velocity, homogeneous Neumann pressure), FC(Gram) d = 5, C = 25
-(extended 1049 x 1049), Wendland C2 kernel h = 1.3 dx, nu = 1e-3, rho = 1,
-first-order projection steps from a seeded manufactured decaying-vortex flow
-with its exact forcing and wall data.  All inputs are resident on the GPU
-before the timed region.  The manufactured trajectory is restarted from its
-initial condition every 25 steps (an on-device copy inside the timed region),
-so every timed step runs on a bounded state.
+Headline workload: 2D 1024 x 1024 lattice on [0,1]^2 with walls on all four
+sides (Dirichlet velocity, homogeneous Neumann pressure), FC(Gram) d = 5,
+C = 25 (extended 1049 x 1049), Wendland C2 kernel h = 1.3 dx, nu = 1e-3,
+rho = 1, first-order projection steps from a seeded manufactured
+decaying-vortex flow with its exact forcing and wall data, FP64.  All inputs
+are resident on the GPU before the timed region.  The manufactured trajectory
+is restarted from its initial condition every 25 steps (an on-device copy
+inside the timed region), so every timed step runs on a bounded state.
+
+Variants on the same JSON line: the other operator evaluations, the FP32-mixed
+form, and the 3D 256^3 channel (walls on y only, 20 steps from a manufactured
+divergence-free field, FP64 and FP32-mixed, with the FP32-vs-FP64 error after
+steps 1 and 20).
 
 Prints one JSON line (metric, value in Mpts/s = physical points x steps / s,
-roofline of the dominant kernel from live HIP-event timings, CPU oracle
-baseline on a bounded sample).
+roofline of the dominant kernel from live HIP-event timings on the library's
+stream, CPU oracle baseline on a bounded sample).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,30 +35,101 @@ sys.path.insert(0, ROOT)
 METRIC = "FC-spectral ISPH step Mpts/s + %HBM roofline; batched solves/s, p99 latency"
 HBM_PEAK_GBS = 8000.0
 CYCLE = 25
+C_FC = 25
 
 
-def algorithmic_bytes(n: int, C: int) -> dict:
-    """Compulsory HBM bytes of one launch of each kernel kind (every input read
-    once, every output written once) for the 2D n x n FP64 step."""
+# ------------------------------------------------------------------ bytes
+def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0) -> dict:
+    """Compulsory HBM bytes of one launch of each kernel kind of the 2D n x n
+    step (every input read once, every output written once).  State arrays are
+    FP64; spectra and derivative outputs are FP64 or FP32; L is the operator
+    transform length of the walled axes (n + C, or the window length)."""
     P = n * n
-    H = (n + C) // 2 + 1
-    S = n * H * 16                 # one x half-spectrum array, complex FP64
+    H = (L or n + C_FC) // 2 + 1
+    ce = 8 if fp32 else 16
+    te = 4 if fp32 else 8
+    S = n * H * ce                 # one x half-spectrum array
     R = P * 8                      # one real FP64 field
+    Rt = P * te                    # one derivative / rhs field
     return {
         "rows_fwd_pair": 2 * R + 2 * S,
         "cols_op_step_a": 2 * S + 6 * S,
         "rows_inv_step_a": 6 * S + 4 * R + 2 * R,
         "cols_div": 2 * S + S,
-        "rows_inv_store": S + R,
-        "ppe_rows_fwd": R + R,
-        "ppe_cols_solve": 2 * R,
-        "ppe_rows_inv": R + R,
+        "rows_inv_store": S + Rt,
+        "ppe_rows_fwd": Rt + P * ce // 2,
+        "ppe_cols_solve": P * ce,
+        "ppe_rows_inv": P * ce // 2 + R,
         "rows_fwd": R + S,
         "cols_op_step_d": S + 2 * S,
         "rows_inv_step_d": 2 * S + 2 * R + 2 * R,
+        "direct_step_a": 6 * R,
+        "direct_div": 2 * R + Rt,
+        "direct_step_d": 5 * R,
     }
 
 
+def algorithmic_bytes_3d(n: int, fp32: bool = False, L: int = 0, force: bool = False) -> dict:
+    """Same for the 3D n^3 channel (walls on y): x half spectra with n or
+    L rows per z plane (L = the y transform length)."""
+    P = n ** 3
+    H = n // 2 + 1
+    ce = 8 if fp32 else 16
+    te = 4 if fp32 else 8
+    Sx = n * n * H * ce
+    Sy = (L or n + C_FC) * n * H * ce
+    R = P * 8
+    Rt = P * te
+    out = {
+        "rows_fwd_pair": 2 * R + 2 * Sx,
+        "rows_fwd": R + Sx,
+        "cols_z_op_step_a": 3 * Sy + 12 * Sy,
+        "rows_inv_step_a3": 12 * Sx + 3 * R + (3 * R if force else 0) + 3 * R,
+        "cols_z_div": 3 * Sy + Sy,
+        "rows_inv_store": Sx + Rt,
+        "ppe_rows_fwd": Rt + P * ce // 2,
+        "ppe_cols_y_fwd": P * ce,
+        "ppe_cols_z_solve": P * ce,
+        "ppe_cols_y_inv": P * ce,
+        "ppe_rows_inv": P * ce // 2 + R,
+        "cols_z_op_step_d": Sy + 3 * Sy,
+        "rows_inv_step_d3": 3 * Sx + 3 * R + 3 * R,
+    }
+    for k in (1, 2, 3):
+        out[f"cols_y_fwd{k}"] = k * (Sx + Sy)
+        out[f"cols_y_inv{k}"] = k * (Sy + Sx)
+    return out
+
+
+def sources_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_06247_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary of `workload` (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    factor a plain copy of known size gives), or None if there is none or the
+    kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != sources_digest():
+        return None
+    k = rec.get("workloads", {}).get(workload, {}).get(kernel)
+    if not k:
+        return None
+    return round(1024 * (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]))
+
+
+# ------------------------------------------------------------------ CPU baseline
 def cpu_baseline(n: int, steps: int, budget_s: float) -> dict:
     """The oracle (direct tap sums, dense per-axis PPE) on the host cores."""
     import numpy as np
@@ -93,19 +170,65 @@ def cpu_baseline(n: int, steps: int, budget_s: float) -> dict:
                       f"restart cycle), {el:.1f} s of step time"}
 
 
-def algorithmic_bytes_direct(n: int) -> dict:
-    R = n * n * 8
-    return {"direct_step_a": 6 * R, "direct_div": 3 * R, "direct_step_d": 5 * R,
-            "ppe_rows_fwd": 2 * R, "ppe_cols_solve": 2 * R, "ppe_rows_inv": 2 * R}
+# ------------------------------------------------------------------ timing
+def timed(ctx, step, steps: int, warmup: int):
+    """Runs warmup + steps calls of step(k); returns wall seconds, event ms
+    and the per-kernel HIP-event record of the timed steps."""
+    import torch
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ctx.read_timing()
+    ctx.set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(steps):
+        step(k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    kern = ctx.read_timing()
+    return t1 - t0, e0.elapsed_time(e1), kern
 
 
-def run_gpu(op_eval: str, n: int, steps: int, warmup: int) -> dict:
-    """Time `steps` FOP steps of the n x n workload with one operator evaluation."""
+def summarise(kern: dict, ab: dict, gpu_ms: float, steps: int, ms_per_step: float, workload: str):
+    per_kernel = {}
+    for name, (cnt, tot) in sorted(kern.items(), key=lambda kv: -kv[1][1]):
+        avg_ms = tot / cnt
+        rec = {"launches": cnt, "avg_us": round(1e3 * avg_ms, 2), "share": round(tot / max(gpu_ms, 1e-9), 4)}
+        if name in ab:
+            rec["GBs"] = round(ab[name] / (avg_ms * 1e-3) / 1e9, 1)
+        per_kernel[name] = rec
+    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    dom_avg_s = kern[dom][1] / kern[dom][0] * 1e-3
+    achieved = ab[dom] / dom_avg_s / 1e9
+    step_bytes = sum(ab[k] * kern[k][0] for k in kern if k in ab) / steps
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counter_traffic(workload, dom),
+                "bytes_per_launch": ab[dom], "avg_launch_us": round(dom_avg_s * 1e6, 2),
+                "step_algorithmic_GB": round(step_bytes / 1e9, 4),
+                "step_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return roofline, per_kernel
+
+
+def rel_l2(a, b) -> float:
+    import torch
+    den = torch.linalg.vector_norm(b).item()
+    return torch.linalg.vector_norm(a - b).item() / (den if den > 0 else 1.0)
+
+
+# ------------------------------------------------------------------ 2D workload
+def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64") -> dict:
+    """Time `steps` FOP steps of the 2D n x n workload."""
     import torch
 
     from paper_2606_06247_amd import api, synth
 
-    C = 25
     nu, rho = 1e-3, 1.0
     dx = 1.0 / (n - 1)
     dt = min(0.2 * dx, 0.1 * dx * dx / nu)
@@ -125,7 +248,7 @@ def run_gpu(op_eval: str, n: int, steps: int, warmup: int) -> dict:
 
     ctx = api.Context(0)
     prob = api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
-                       prs_bc=(("N", "N"), ("N", "N")), rho=rho, op_eval=op_eval)
+                       prs_bc=(("N", "N"), ("N", "N")), rho=rho, op_eval=op_eval, precision=precision)
     plan = api.Plan(ctx, prob)
 
     def step(k):
@@ -135,47 +258,128 @@ def run_gpu(op_eval: str, n: int, steps: int, warmup: int) -> dict:
             u[1].copy_(u0[1])
         plan.project_step(u, dt, nu, p_out=p, force=forces[c], wall=walls[c])
 
-    for k in range(warmup):
-        step(k)
-    torch.cuda.synchronize()
-    ctx.read_timing()
-    ctx.set_timing(True)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for k in range(steps):
-        step(k)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.set_timing(False)
-    kern = ctx.read_timing()
-    gpu_ms = e0.elapsed_time(e1)
-    wall_s = t1 - t0
+    wall_s, gpu_ms, kern = timed(ctx, step, steps, warmup)
     ms_per_step = 1e3 * wall_s / steps
     finite = bool(all(torch.isfinite(c).all().item() for c in u))
-    ab = algorithmic_bytes(n, C) if op_eval == "fft" else algorithmic_bytes_direct(n)
-    per_kernel = {}
-    for name, (cnt, tot) in sorted(kern.items(), key=lambda kv: -kv[1][1]):
-        avg_ms = tot / cnt
-        rec = {"launches": cnt, "avg_us": round(1e3 * avg_ms, 2), "share": round(tot / max(gpu_ms, 1e-9), 4)}
-        if name in ab:
-            rec["GBs"] = round(ab[name] / (avg_ms * 1e-3) / 1e9, 1)
-        per_kernel[name] = rec
-    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
-    dom_avg_s = kern[dom][1] / kern[dom][0] * 1e-3
-    achieved = ab[dom] / dom_avg_s / 1e9
-    step_bytes = sum(ab[k] * kern[k][0] for k in kern if k in ab) / steps
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": ab[dom],
-                "step_algorithmic_GB": round(step_bytes / 1e9, 4),
-                "step_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ab = algorithmic_bytes_2d(n, precision == "fp32", plan.transform_lengths()[0])
+    roofline, per_kernel = summarise(kern, ab, gpu_ms, steps, ms_per_step,
+                                     f"2d_{n}_{precision}_{op_eval}")
     return {"value": round(n * n * steps / wall_s / 1e6, 2), "ms_per_step": round(ms_per_step, 4),
             "gpu_event_ms": round(gpu_ms, 3), "state_finite": finite, "roofline": roofline,
-            "kernels": per_kernel}
+            "kernels": per_kernel, "transform_lengths": plan.transform_lengths()}
+
+
+_INPUTS_2D = {}
+
+
+def inputs_2d(n: int, nsteps: int):
+    """Device-resident initial velocity, forcing and wall data of the first
+    nsteps steps of the 2D workload (built once per size)."""
+    import torch
+
+    from paper_2606_06247_amd import synth
+    key = (n, nsteps)
+    if key not in _INPUTS_2D:
+        nu = 1e-3
+        dx = 1.0 / (n - 1)
+        dt = min(0.2 * dx, 0.1 * dx * dx / nu)
+        flow = synth.DecayingVortexFlow(n, nu)
+        u0 = [torch.from_numpy(c).cuda() for c in flow.velocity(0.0)]
+        A, B = flow.force_parts()
+        A = [torch.from_numpy(c).cuda() for c in A]
+        B = [torch.from_numpy(c).cuda() for c in B]
+        f = [[math.exp(-(k + 0.5) * dt) * a + math.exp(-2 * (k + 0.5) * dt) * b for a, b in zip(A, B)]
+             for k in range(nsteps)]
+        w = [[math.exp(-(k + 1) * dt) * v for v in u0] for k in range(nsteps)]
+        _INPUTS_2D[key] = (dt, nu, u0, f, w)
+    return _INPUTS_2D[key]
+
+
+def fp32_error_2d(n: int, op_eval: str, nsteps: int = 20) -> dict:
+    """Relative L2 of the FP32-mixed form against the FP64 form after 1 and
+    nsteps steps of the 2D workload (same inputs)."""
+    import torch
+
+    from paper_2606_06247_amd import api
+    dt, nu, u0, forces, walls = inputs_2d(n, nsteps)
+    dx = 1.0 / (n - 1)
+    ctx = api.Context(0)
+    res = {}
+    states = {}
+    for prec in ("fp64", "fp32"):
+        prob = api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
+                           prs_bc=(("N", "N"), ("N", "N")), op_eval=op_eval, precision=prec)
+        plan = api.Plan(ctx, prob)
+        u = [c.clone() for c in u0]
+        p = torch.empty_like(u[0])
+        snaps = {}
+        for k in range(nsteps):
+            plan.project_step(u, dt, nu, p_out=p, force=forces[k], wall=walls[k])
+            if k + 1 in (1, nsteps):
+                snaps[k + 1] = [c.clone() for c in u] + [p.clone()]
+        states[prec] = snaps
+    for k in (1, nsteps):
+        res[f"step{k}"] = {name: float(f"{rel_l2(a, b):.3e}") for name, a, b in
+                           zip(("u", "v", "p"), states["fp32"][k], states["fp64"][k])}
+    return res
+
+
+# ------------------------------------------------------------------ 3D workload
+_CHANNEL = {}
+
+
+def run_3d(n: int, steps: int, warmup: int, precision: str, ref_states=None, op_eval: str = "fft") -> dict:
+    """Time `steps` FOP steps of the n^3 channel (walls on y, no forcing) from
+    the manufactured divergence-free field; the timed steps run from the
+    initial state (the warm-up steps run on a copy)."""
+    import torch
+
+    from paper_2606_06247_amd import api, synth
+    nu, rho = 1e-3, 1.0
+    dx = 1.0 / (n - 1)
+    dt = min(0.2 * dx, 0.1 * dx * dx / nu)
+    if n not in _CHANNEL:
+        _CHANNEL[n] = synth.ChannelFlow3D((n, n, n), 20, 21).u
+    u0 = [torch.from_numpy(c).cuda() for c in _CHANNEL[n]]
+    zero_wall = torch.zeros_like(u0[0])
+    walls = [zero_wall, zero_wall, zero_wall]
+    u = [c.clone() for c in u0]
+    p = torch.empty_like(u0[0])
+    ctx = api.Context(0)
+    prob = api.Problem(n=(n, n, n), walled=(False, True, False), dx=dx,
+                       vel_bc=(None, ("D", "D"), None), prs_bc=(None, ("N", "N"), None),
+                       rho=rho, precision=precision, op_eval=op_eval)
+    plan = api.Plan(ctx, prob)
+    snaps = {}
+
+    def step(k):
+        plan.project_step(u, dt, nu, p_out=p, force=None, wall=walls)
+
+    for k in range(warmup):
+        step(k)
+    for c, c0 in zip(u, u0):
+        c.copy_(c0)
+
+    def timed_step(k):
+        step(k)
+        if ref_states is not None and k + 1 in (1, steps):
+            snaps[k + 1] = [c.clone() for c in u] + [p.clone()]
+
+    wall_s, gpu_ms, kern = timed(ctx, timed_step, steps, 0)
+    ms_per_step = 1e3 * wall_s / steps
+    finite = bool(all(torch.isfinite(c).all().item() for c in u))
+    ab = algorithmic_bytes_3d(n, precision == "fp32", plan.transform_lengths()[1])
+    roofline, per_kernel = summarise(kern, ab, gpu_ms, steps, ms_per_step, f"3d_{n}_{precision}_{op_eval}")
+    out = {"value": round(n ** 3 * steps / wall_s / 1e6, 2), "ms_per_step": round(ms_per_step, 4),
+           "gpu_event_ms": round(gpu_ms, 3), "state_finite": finite, "roofline": roofline,
+           "kernels": per_kernel, "steps": steps, "transform_lengths": plan.transform_lengths()}
+    if ref_states is not None:
+        ref_states.update(snaps)
+    return out
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main() -> int:
@@ -184,12 +388,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--n3", type=int, default=256, help="3D channel lattice n^3")
+    ap.add_argument("--steps3", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--op-eval", choices=["fft", "direct"], default="fft")
+    ap.add_argument("--op-eval", choices=["fft", "fft_window", "direct"], default="fft")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip timing the other operator evaluation on the same workload")
+                    help="time only the headline workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -205,7 +411,9 @@ def main() -> int:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         return 2
     n = args.n
-    head = run_gpu(args.op_eval, n, args.steps, args.warmup)
+    log(f"headline 2d {n} fp64 {args.op_eval}")
+    head = run_2d(args.op_eval, n, args.steps, args.warmup)
+    log(f"  {head['value']} Mpts/s")
     out = {"metric": METRIC, "value": head["value"], "unit": "Mpts/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -218,10 +426,39 @@ def main() -> int:
                       "gpu_event_ms": head["gpu_event_ms"], "state_finite": head["state_finite"]},
            "roofline": head["roofline"], "kernels": head["kernels"]}
     if not args.no_variants:
-        other = "direct" if args.op_eval == "fft" else "fft"
-        v = run_gpu(other, n, args.steps, args.warmup)
-        out["variants"] = {f"op_eval={other}": {k: v[k] for k in ("value", "ms_per_step", "roofline", "kernels")}}
+        keep = ("value", "ms_per_step", "state_finite", "transform_lengths", "roofline", "kernels")
+        var = {}
+        for oe in ("fft", "fft_window", "direct"):
+            if oe != args.op_eval:
+                log(f"variant 2d {n} fp64 {oe}")
+                v = run_2d(oe, n, args.steps, args.warmup)
+                var[f"2d_{n}_fp64_{oe}"] = {k: v[k] for k in keep}
+        for oe in ("fft", "fft_window", "direct"):
+            log(f"variant 2d {n} fp32 {oe}")
+            v = run_2d(oe, n, args.steps, args.warmup, precision="fp32")
+            rec = {k: v[k] for k in keep}
+            rec["dtype"] = "f32 transforms, f64 FC/divide/state"
+            rec["fp32_vs_fp64_rel_l2"] = fp32_error_2d(n, oe)
+            var[f"2d_{n}_fp32_{oe}"] = rec
+        n3 = args.n3
+        for oe in ("fft", "fft_window"):
+            ref64, ref32 = {}, {}
+            for prec, ref in (("fp64", ref64), ("fp32", ref32)):
+                log(f"variant 3d {n3} {prec} {oe}")
+                v = run_3d(n3, args.steps3, 2, prec, ref, op_eval=oe)
+                rec = {k: v[k] for k in keep}
+                rec["steps"] = args.steps3
+                rec["workload"] = (f"3D {n3}^3 channel, walls on y (Dirichlet velocity, Neumann pressure), "
+                                   f"periodic x and z, extended {n3}x{n3 + 25}x{n3}, {args.steps3} steps "
+                                   "from a manufactured divergence-free field, no forcing")
+                var[f"3d_{n3}_{prec}_{oe}"] = rec
+            var[f"3d_{n3}_fp32_{oe}"]["fp32_vs_fp64_rel_l2"] = {
+                f"step{k}": {name: float(f"{rel_l2(a, b):.3e}") for name, a, b in
+                             zip(("u", "v", "w", "p"), ref32[k], ref64[k])} for k in sorted(ref64)}
+            del ref64, ref32
+        out["variants"] = var
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0

@@ -50,11 +50,20 @@ typedef enum { FCSPH_FP64 = 0, FCSPH_FP32_MIXED = 1 } fcsph_precision;
 typedef enum { FCSPH_PPE_PHYSICAL = 0, FCSPH_PPE_EXTENDED = 1 } fcsph_ppe_domain;
 typedef enum { FCSPH_EIG_SPECTRAL = 0, FCSPH_EIG_FD2 = 1, FCSPH_EIG_SPH = 2 } fcsph_eig;
 typedef enum { FCSPH_KERNEL_WENDLAND_C2 = 0 } fcsph_kernel;
-/* How the circular convolutions of the operators are evaluated: through the
- * DFT of the FC-extended field (the paper's convolution-theorem route) or as
- * direct tap sums over the compact kernel support (same result up to
- * rounding; every input read once). */
-typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1 } fcsph_op_eval;
+/* How the circular convolutions of the operators (period n + C on a walled
+ * axis) are evaluated; all three give the same result up to rounding:
+ *  FCSPH_OPS_FFT         DFT of the whole FC-extended line (length n + C,
+ *                        Bluestein where n + C has a large prime factor),
+ *                        symbol multiply, inverse DFT, restriction;
+ *  FCSPH_OPS_DIRECT      direct tap sums over the compact kernel support;
+ *  FCSPH_OPS_FFT_WINDOW  the convolution theorem on the window the physical
+ *                        outputs see: the n physical values, the first R and
+ *                        the last R continuation values (R = kernel reach in
+ *                        lattice points), zero padded to a smooth length
+ *                        L >= n + 2R.  A length-L cyclic convolution of that
+ *                        window equals the period-(n + C) convolution at every
+ *                        physical point, because no tap reaches farther. */
+typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2 } fcsph_op_eval;
 
 /*
  * Problem descriptor.  Axes are indexed 0 = x, 1 = y, 2 = z.
@@ -129,6 +138,10 @@ fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes);
 fcsph_status fcsph_plan_create(fcsph_ctx *c, const fcsph_desc *d, void *workspace,
                                size_t bytes, fcsph_plan **out);
 fcsph_status fcsph_plan_destroy(fcsph_plan *p);
+/* Operator transform length per axis (L[a] for a < ndim, 1 beyond): n + C on
+ * a walled axis, or the window length under FCSPH_OPS_FFT_WINDOW; n on a
+ * periodic axis.  For reporting; the layout of user buffers never depends on it. */
+fcsph_status fcsph_plan_transform_lengths(const fcsph_plan *p, int L[3]);
 
 /*
  * FC(Gram) extension (FC section, eq. eq:fc_extended and its 2D form

@@ -29,12 +29,13 @@ FP64, FP32_MIXED = 0, 1
 PPE_PHYSICAL, PPE_EXTENDED = 0, 1
 EIG_SPECTRAL, EIG_FD2, EIG_SPH = 0, 1, 2
 KERNEL_WENDLAND_C2 = 0
-OPS_FFT, OPS_DIRECT = 0, 1
+OPS_FFT, OPS_DIRECT, OPS_FFT_WINDOW = 0, 1, 2
 
 EXPORTS = [
     "fcsph_ctx_create", "fcsph_ctx_destroy", "fcsph_ctx_sync", "fcsph_status_string",
     "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
-    "fcsph_plan_destroy", "fcsph_fc_extend", "fcsph_spectral_grad", "fcsph_spectral_div",
+    "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
+    "fcsph_spectral_div",
     "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_ctx_set_timing",
     "fcsph_ctx_read_timing",
 ]
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_plan_workspace_bytes.argtypes = [P(Desc), P(ctypes.c_size_t)]
     L.fcsph_plan_create.argtypes = [vp, P(Desc), vp, ctypes.c_size_t, P(vp)]
     L.fcsph_plan_destroy.argtypes = [vp]
+    L.fcsph_plan_transform_lengths.argtypes = [vp, P(i)]
     L.fcsph_fc_extend.argtypes = [vp, i, vp, vp]
     L.fcsph_spectral_grad.argtypes = [vp, i, vp, P(vp)]
     L.fcsph_spectral_div.argtypes = [vp, P(vp), vp]
@@ -117,7 +119,7 @@ class Problem:
     precision: str = "fp64"       # 'fp64' | 'fp32'
     eig: str = "spectral"         # 'spectral' | 'fd2'
     rho: float = 1.0
-    op_eval: str = "fft"          # 'fft' | 'direct'
+    op_eval: str = "fft"          # 'fft' | 'fft_window' | 'direct'
     fc_d: int = 5
     fc_C: int = 25
 
@@ -205,7 +207,7 @@ def make_desc(prob: "Problem"):
     d.ppe_domain = PPE_PHYSICAL
     d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
     d.rho = prob.rho
-    d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT}[prob.op_eval]
+    d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT, "fft_window": OPS_FFT_WINDOW}[prob.op_eval]
     return d, mdir, mneu
 
 
@@ -273,6 +275,13 @@ class Plan:
         return arr
 
     # -- entry points (same names as the C ABI)
+    def transform_lengths(self) -> tuple:
+        """Operator transform length per lattice axis."""
+        arr = (ctypes.c_int * 3)()
+        _check(lib().fcsph_plan_transform_lengths(self.handle, arr), self.ctx.handle,
+               "fcsph_plan_transform_lengths")
+        return tuple(arr[a] for a in range(self.prob.ndim))
+
     def fc_extend(self, f, field: int = VELOCITY, out=None):
         import torch
         out = self._new(torch.float64, self.prob.ext_shape) if out is None else out

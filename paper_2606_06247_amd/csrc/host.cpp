@@ -119,6 +119,46 @@ int nb_max_host(int R) {
   return R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1;
 }
 
+// Transform length of a windowed walled axis: the cheapest L >= n + 2 R whose
+// factors are all radices with straight-line butterflies (2, 3, 4, 5, 7, 8).
+// Cost model per point: a fixed HBM term plus a per-stage butterfly term.
+// FCSPH_WINDOW_L=<L> overrides (used by the schedule tuner).
+int window_length(int n, int R) {
+  const int lo = n + 2 * R;
+  if (const char *e = getenv("FCSPH_WINDOW_L")) {
+    const int L = atoi(e);
+    std::vector<int> rad;
+    if (L >= lo && factor_direct(L, rad)) return L;
+  }
+  double best = 1e300;
+  int bestL = -1;
+  for (int L = lo; L <= 2 * lo + 8; ++L) {
+    std::vector<int> rad;
+    if (!factor_direct(L, rad)) continue;
+    double c = 4.0;
+    bool ok = true;
+    for (int r : rad) {
+      switch (r) {
+        case 1: break;
+        case 2: c += 1.0; break;
+        case 3: c += 1.35; break;
+        case 4: c += 1.1; break;
+        case 5: c += 1.7; break;
+        case 7: c += 2.4; break;
+        case 8: c += 1.4; break;
+        default: ok = false;
+      }
+    }
+    if (!ok) continue;
+    const double cost = c * L;
+    if (cost < best) {
+      best = cost;
+      bestL = L;
+    }
+  }
+  return bestL;
+}
+
 template <typename T>
 void put_cpx(std::vector<char> &v, size_t idx, LD re, LD im) {
   cpx<T> c = {static_cast<T>(re), static_cast<T>(im)};
@@ -316,17 +356,21 @@ struct fcsph_plan {
   bool fp32 = false;
   int nd = 2;
   int n[3] = {1, 1, 1};
-  int E[3] = {1, 1, 1};
+  int E[3] = {1, 1, 1};     // operator transform length per axis
+  int Efc[3] = {1, 1, 1};   // FC-extended period per axis (n + C on walled axes)
+  bool window = false;      // windowed operator transforms
   int walled[3] = {0, 0, 0};
   int H = 0;            // x half spectrum
   // FC maps (device)
   const double *M_dir = nullptr, *M_neu = nullptr;
   // line plans
   LinePlan op[3];       // operator DFT along each axis (length E[a])
+  LinePlan op64[3];     // FP32-mixed plans: FP64 twins for the PPE right-hand side
   LinePlan trig[3];     // PPE transform along each axis
   int trig_kind[3] = {0, 0, 0};
   int ncoef[3] = {0, 0, 0};
   const double *mu[3] = {nullptr, nullptr, nullptr};
+  const void *qtw[3] = {nullptr, nullptr, nullptr};   // quarter-wave pre-twiddles
   // symbols
   SymTables st{};
   // scratch
@@ -364,6 +408,12 @@ FcWalls walls_for(const fcsph_plan *p, int axis, int fc) {
   w.on = p->walled[axis];
   w.C = p->d.fc_C;
   w.d = p->d.fc_d;
+  w.head = w.C;
+  w.tail = 0;
+  if (w.on && p->window) {
+    w.head = p->reach;
+    w.tail = p->reach;
+  }
   if (w.on) {
     const int(*bc)[2] = fc == FCSPH_FIELD_VELOCITY ? p->d.vel_bc : p->d.prs_bc;
     w.Mlo = bc[axis][0] == FCSPH_BC_NEUMANN ? p->M_neu : p->M_dir;
@@ -382,7 +432,10 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
     return FCSPH_E_UNSUPPORTED;
   }
   if (d->prec != FCSPH_FP64 && d->prec != FCSPH_FP32_MIXED) { msg = "bad precision"; return FCSPH_E_INVALID; }
-  if (d->op_eval != FCSPH_OPS_FFT && d->op_eval != FCSPH_OPS_DIRECT) { msg = "bad op_eval"; return FCSPH_E_INVALID; }
+  if (d->op_eval != FCSPH_OPS_FFT && d->op_eval != FCSPH_OPS_DIRECT && d->op_eval != FCSPH_OPS_FFT_WINDOW) {
+    msg = "bad op_eval";
+    return FCSPH_E_INVALID;
+  }
   if (d->op_eval == FCSPH_OPS_DIRECT && d->ndim != 2) { msg = "direct evaluation is built for 2D"; return FCSPH_E_UNSUPPORTED; }
   if (d->ppe_domain != FCSPH_PPE_PHYSICAL) { msg = "only the physical-domain PPE is built"; return FCSPH_E_UNSUPPORTED; }
   if (d->eig != FCSPH_EIG_SPECTRAL && d->eig != FCSPH_EIG_FD2) { msg = "eigenvalue family not built"; return FCSPH_E_UNSUPPORTED; }
@@ -422,10 +475,20 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->d = *d;
   p->fp32 = d->prec == FCSPH_FP32_MIXED;
   p->nd = d->ndim;
+  p->window = d->op_eval == FCSPH_OPS_FFT_WINDOW;
+  {
+    std::vector<Tap> tl = wendland_tap_list(d->ndim, d->dx, d->h_over_dx, p->reach);
+  }
   for (int a = 0; a < 3; ++a) {
     p->n[a] = a < p->nd ? d->n[a] : 1;
     p->walled[a] = a < p->nd ? (d->axis[a] == FCSPH_AXIS_WALLED) : 0;
-    p->E[a] = p->n[a] + (p->walled[a] ? d->fc_C : 0);
+    p->Efc[a] = p->n[a] + (p->walled[a] ? d->fc_C : 0);
+    p->E[a] = p->Efc[a];
+    if (p->window && p->walled[a]) p->E[a] = window_length(p->n[a], p->reach);
+    if (p->E[a] <= 0) {
+      msg = "no transform length for the window of axis " + std::to_string(a);
+      return FCSPH_E_UNSUPPORTED;
+    }
   }
   p->H = p->E[0] / 2 + 1;
   const bool f32 = p->fp32;
@@ -448,7 +511,8 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   // operator line plans
   for (int a = 0; a < p->nd; ++a) {
     const int minTL = (a == 0) ? 64 : (p->E[a] + 7) / 8;   // cols kernels keep E/TL <= 8 values
-    if (!make_line_plan(p->E[a], f32, minTL, ws, up, p->op[a])) {
+    if (!make_line_plan(p->E[a], f32, minTL, ws, up, p->op[a]) ||
+        (f32 && !make_line_plan(p->E[a], false, minTL, ws, up, p->op64[a]))) {
       msg = "cannot plan a DFT of length " + std::to_string(p->E[a]);
       return FCSPH_E_UNSUPPORTED;
     }
@@ -508,14 +572,15 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       kind = TRIG_DFT;
       L = nn;
     } else if (d->prs_bc[a][0] != d->prs_bc[a][1]) {
-      p->trig_kind[a] = -1;     // quarter-wave transforms: not built
-      continue;
+      kind = d->prs_bc[a][0] == FCSPH_BC_DIRICHLET ? TRIG_QWS : TRIG_QWC;
+      L = 2 * (nn - 1);
     } else {
       kind = d->prs_bc[a][0] == FCSPH_BC_NEUMANN ? TRIG_DCT1 : TRIG_DST1;
       L = 2 * (nn - 1);
     }
     p->trig_kind[a] = kind;
-    p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : nn - 2);
+    const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
+    p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : qw ? nn - 1 : nn - 2);
     const int minTL = (a == 0) ? 64 : 64;
     if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
@@ -529,6 +594,8 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       if (kind == TRIG_DFT) {
         const int ks = (k <= nn / 2) ? k : k - nn;
         th = 2.0L * kPi * (LD)ks / (LD)nn;
+      } else if (qw) {
+        th = kPi * (LD)(2 * k + 1) / (LD)(2 * (nn - 1));   // quarter-wave mode k at position k
       } else if (kind == TRIG_DCT1 || a != 0) {
         th = kPi * (LD)k / (LD)(nn - 1);            // position = mode (lines, DCT rows)
       } else {
@@ -544,6 +611,20 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     u.dst = ws.take(u.data.size());
     p->mu[a] = (const double *)u.dst;
     up.push_back(std::move(u));
+    if (qw) {
+      // exp(-i pi j / 2N), j < 2N, N = n - 1
+      Upload q;
+      const size_t es = f32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+      q.data.resize((size_t)L * es);
+      for (int j = 0; j < L; ++j) {
+        const LD ang = -kPi * (LD)j / (LD)L;
+        if (f32) put_cpx<float>(q.data, j, cosl(ang), sinl(ang));
+        else put_cpx<double>(q.data, j, cosl(ang), sinl(ang));
+      }
+      q.dst = ws.take(q.data.size());
+      p->qtw[a] = q.dst;
+      up.push_back(std::move(q));
+    }
   }
   // scratch
   const size_t P = (size_t)p->n[0] * p->n[1] * p->n[2];
@@ -551,17 +632,18 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   size_t rows_ext = (size_t)p->E[1] * p->n[2];     // 3D y-extended rows
   p->spec_elems = std::max(rows, rows_ext) * p->H;
   const size_t sb = p->spec_elems * ce;
-  for (int i = 0; i < 3; ++i) p->S[i] = ws.take(sb);
+  const size_t sb64 = p->spec_elems * sizeof(cpx<double>);   // also holds the FP64 divergence pass
+  for (int i = 0; i < 3; ++i) p->S[i] = ws.take(sb64);
   const int nO = p->nd == 2 ? 6 : 12;
-  for (int i = 0; i < nO; ++i) p->O[i] = ws.take(sb);
+  for (int i = 0; i < nO; ++i) p->O[i] = ws.take(i == 0 ? sb64 : sb);
   if (p->nd == 3)
-    for (int i = 0; i < 3; ++i) p->Y[i] = ws.take(sb);
+    for (int i = 0; i < 3; ++i) p->Y[i] = ws.take(sb64);
   for (int a = 0; a < p->nd; ++a) p->ustar[a] = (double *)ws.take(P * sizeof(double));
   p->rhs = ws.take(P * te);
   p->phi = (double *)ws.take(P * sizeof(double));
   p->cpitch = p->trig_kind[0] == TRIG_DFT ? p->ncoef[0] : (std::max(p->ncoef[0], 1) + 1) / 2;
   p->coef = ws.take((size_t)p->cpitch * rows * ce);
-  p->ext_scratch = (double *)ws.take((size_t)p->E[0] * p->E[1] * p->E[2] * sizeof(double));
+  p->ext_scratch = (double *)ws.take((size_t)p->Efc[0] * p->Efc[1] * p->Efc[2] * sizeof(double));
   for (int i = 0; i < 3; ++i) {
     p->ghx[i] = (double *)ws.take((size_t)p->n[1] * p->n[2] * 2 * kSymR * sizeof(double));
     p->ghy[i] = (double *)ws.take((size_t)2 * kSymR * (p->n[0] + 2 * kSymR) * p->n[2] * sizeof(double));
@@ -571,6 +653,28 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
 }
 
 // ----------------------------------------------------------------- pipelines
+// Runs the operator passes of its scope in FP64 on an FP32-mixed plan (the
+// divergence of u* that forms the PPE right-hand side: the solenoidal part of
+// u* cancels in it, so FP32 transforms would round relative to |G u| instead
+// of |div u*|).  The plan's FP64 twin line plans and FP64-sized scratch
+// spectra make this possible; outside the scope the plan is unchanged.
+struct Fp64Passes {
+  fcsph_plan *p;
+  bool was;
+  explicit Fp64Passes(fcsph_plan *pl) : p(pl), was(pl->fp32) {
+    if (was) {
+      for (int a = 0; a < 3; ++a) std::swap(p->op[a], p->op64[a]);
+      p->fp32 = false;
+    }
+  }
+  ~Fp64Passes() {
+    if (was) {
+      for (int a = 0; a < 3; ++a) std::swap(p->op[a], p->op64[a]);
+      p->fp32 = true;
+    }
+  }
+};
+
 bool chk(fcsph_plan *p, hipError_t e, const char *where, fcsph_status &st) {
   if (e != hipSuccess) {
     st = hip_fail(p->ctx, e, where);
@@ -744,7 +848,8 @@ hipError_t y_fwd(fcsph_plan *p, int nf, void *const *in, void *const *out, int f
     c.in[f] = in[f];
     c.out[f][0] = out[f];
   }
-  return cols_launch(p, c, nf, "cols_y_fwd");
+  static const char *names[4] = {"cols_y_fwd", "cols_y_fwd1", "cols_y_fwd2", "cols_y_fwd3"};
+  return cols_launch(p, c, nf, names[nf < 4 ? nf : 0]);
 }
 
 // y inverse of nf spectra in place (y-extended layout), restricted to ny rows
@@ -754,7 +859,8 @@ hipError_t y_inv(fcsph_plan *p, int nf, void *const *buf) {
     c.in[f] = buf[f];
     c.out[f][0] = buf[f];
   }
-  return cols_launch(p, c, nf, "cols_y_inv");
+  static const char *names[4] = {"cols_y_inv", "cols_y_inv1", "cols_y_inv2", "cols_y_inv3"};
+  return cols_launch(p, c, nf, names[nf < 4 ? nf : 0]);
 }
 
 DirectArgs direct_base(fcsph_plan *p, int fc) {
@@ -809,6 +915,7 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_real = f32 ? nullptr : (const double *)rhs;
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
+  r.qtw = p->qtw[0];
   r.B = pick_B(r.plan, f32, 4);
   r.ldsM = padded_len(r.plan.M, r.plan.pad);
   {
@@ -825,6 +932,7 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   cy.nline = ny;
   cy.ncoef = p->ncoef[1];
   cy.data = p->coef;
+  cy.qtw = p->qtw[1];
   cy.B = pick_B(cy.plan, f32, 4);
   cy.ldsM = padded_len(cy.plan.M, cy.plan.pad);
   cy.solve = 0;
@@ -892,6 +1000,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_real = f32 ? nullptr : (const double *)rhs;
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
+  r.qtw = p->qtw[0];
   r.B = pick_B(r.plan, f32, 4);
   r.ldsM = padded_len(r.plan.M, r.plan.pad);
   {
@@ -916,6 +1025,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   c.mu_outer = nullptr;
   c.scale = p->trig_kind[1] == TRIG_DFT ? 1.0 / p->n[1] : 1.0 / (2.0 * (p->n[1] - 1));
   c.data = p->coef;
+  c.qtw = p->qtw[1];
   c.B = pick_B(c.plan, f32, 4);
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   {
@@ -1087,6 +1197,12 @@ fcsph_status fcsph_plan_create(fcsph_ctx *c, const fcsph_desc *d, void *workspac
 
 fcsph_status fcsph_plan_destroy(fcsph_plan *p) {
   delete p;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_plan_transform_lengths(const fcsph_plan *p, int L[3]) {
+  if (!p || !L) return FCSPH_E_INVALID;
+  for (int a = 0; a < 3; ++a) L[a] = p->E[a];
   return FCSPH_OK;
 }
 
@@ -1313,8 +1429,11 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
       LaunchTimer t(p->ctx, "rows_inv_step_a3");
       if (!chk(p, launch_rows_inv(r, EPI_STEP_A3, f32, s), "step3 A x inv", st)) return st;
     }
-    // B, C
-    st = div3_impl(p, p->ustar, p->rhs, !f32, p->d.rho / dt);
+    // B (FP64 transforms in both forms), C
+    {
+      Fp64Passes g64(p);
+      st = div3_impl(p, p->ustar, p->rhs, !f32, p->d.rho / dt);
+    }
     if (st != FCSPH_OK) return st;
     double *phi = p_out ? p_out : p->phi;
     st = run_ppe(p, p->rhs, phi);
@@ -1421,8 +1540,11 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     LaunchTimer t(p->ctx, "rows_inv_step_a");
     if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;
   }
-  // B: b = (rho/dt) div u*
-  st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
+  // B: b = (rho/dt) div u*, FP64 transforms in both forms
+  {
+    Fp64Passes g64(p);
+    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
+  }
   if (st != FCSPH_OK) return st;
   // C: PPE
   double *phi = p_out ? p_out : p->phi;

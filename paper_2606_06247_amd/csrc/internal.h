@@ -54,7 +54,21 @@ struct FcWalls {
   int C, d;
   const double *Mlo;   // map of the low wall (index 0)
   const double *Mhi;   // map of the high wall (index n-1)
+  // placement on a transform line of length L: positions n .. n+head-1 hold
+  // continuation values 0 .. head-1, positions L-tail .. L-1 hold the last
+  // `tail` continuation values, every other position beyond n is zero
+  // (whole extension: head = C, tail = 0, L = n + C)
+  int head, tail;
 };
+
+// Continuation index stored at line position j >= n of a length-L line, or -1
+// for a zero-padding position.
+__host__ __device__ inline int fc_slot(const FcWalls &fc, int n, int L, int j) {
+  const int r = j - n;
+  if (r < fc.head) return r;
+  const int t = L - j;
+  return t <= fc.tail ? fc.C - t : -1;
+}
 
 // Spectral symbol of one operator: dense tap weights (already scaled by
 // 1/prod(E_a)) on a kSymW^ndim cube, and per-axis phase tables
@@ -151,7 +165,20 @@ struct ColsArgs {
 };
 
 // ---------------------------------------------------------------- PPE passes
-enum TrigKind { TRIG_DFT = 0, TRIG_DCT1 = 1, TRIG_DST1 = 2 };
+// Per-axis PPE transform.  With N = n - 1 intervals between the walls:
+//  DCT1 (Neumann both walls) and DST1 (Dirichlet both walls): complex DFT of
+//    the even / odd extension, length 2N;
+//  QWS (Dirichlet at index 0, Neumann at n-1; basis sin(pi (2l+1) j / 2N),
+//    unknowns j = 1..N) and QWC (Neumann at 0, Dirichlet at n-1; basis
+//    cos(pi (2l+1) j / 2N), unknowns j = 0..N-1): the data extended to the
+//    length-4N sequence that is odd / even about 0, even / odd about N and
+//    anti-periodic with half period 2N has only odd frequencies 2l+1; those are
+//    a length-2N DFT of the first 2N samples times exp(-i pi j / 2N)
+//    (forward), and the inverse is the length-2N inverse DFT followed by
+//    exp(+i pi j / 2N).  Stored coefficients are 4 sum_j w_j x_j basis_l(j)
+//    (w = 1/2 at the Neumann end), so the synthesis scale is 1 / 2N as for
+//    DCT1 and DST1.
+enum TrigKind { TRIG_DFT = 0, TRIG_DCT1 = 1, TRIG_DST1 = 2, TRIG_QWS = 3, TRIG_QWC = 4 };
 
 struct PpeRowsArgs {
   LinePlan plan;       // complex FFT of the extended trig length
@@ -163,6 +190,7 @@ struct PpeRowsArgs {
   int jlo;             // first unknown index (DST1: 1)
   const double *in_real;   // forward input (double), or null when in_float used
   const float *in_float;
+  const void *qtw;     // QWS / QWC: cpx<T> exp(-i pi j / 2N), j < 2N
   void *coef;          // cpx<T> coefficient rows
   double *out;         // inverse output (physical rows)
   double scale;
@@ -184,6 +212,7 @@ struct PpeColsArgs {
   int inner_nmodes;
   const double *mu_outer;  // eigenvalues along the outer axis (or null)
   double scale;
+  const void *qtw;     // QWS / QWC line axis: cpx<T> exp(-i pi j / 2N), j < 2N
   void *data;          // cpx<T>, in place
   int B, ldsM;
 };

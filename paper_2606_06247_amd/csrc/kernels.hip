@@ -67,10 +67,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(RowsFwdArgs a) {
   batched<8, cpx<T>>(lt, a.nx, TL, [&](int j) { return to_cpx<T>(pa ? pa[j] : 0.0, pb ? pb[j] : 0.0); },
                      [&](int j, cpx<T> v) { buf[j] = v; });
   if (a.fc.on) {
-    for (int i = lt; i < a.fc.C; i += TL) {
-      double ra = pa ? fc_cont(a.fc, a.nx, i, [&](int j) { return pa[j]; }) : 0.0;
-      double rb = pb ? fc_cont(a.fc, a.nx, i, [&](int j) { return pb[j]; }) : 0.0;
-      buf[a.nx + i] = to_cpx<T>(ra, rb);
+    for (int j = a.nx + lt; j < a.E; j += TL) {
+      const int i = fc_slot(a.fc, a.nx, a.E, j);
+      double ra = (pa && i >= 0) ? fc_cont(a.fc, a.nx, i, [&](int q) { return pa[q]; }) : 0.0;
+      double rb = (pb && i >= 0) ? fc_cont(a.fc, a.nx, i, [&](int q) { return pb[q]; }) : 0.0;
+      buf[j] = to_cpx<T>(ra, rb);
     }
   }
   __syncthreads();
@@ -374,11 +375,15 @@ __device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem
 
 template <typename T>
 __device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, int TL) {
-  const int n = a.nload;
-  for (int i = lt; i < a.fc.C; i += TL) {
-    const double re = fc_cont(a.fc, n, i, [&](int j) { return (double)buf[j].r; });
-    const double im = fc_cont(a.fc, n, i, [&](int j) { return (double)buf[j].i; });
-    buf[n + i] = to_cpx<T>(re, im);
+  const int n = a.nload, L = a.plan.n;
+  for (int j = n + lt; j < L; j += TL) {
+    const int i = fc_slot(a.fc, n, L, j);
+    double re = 0.0, im = 0.0;
+    if (i >= 0) {
+      re = fc_cont(a.fc, n, i, [&](int q) { return (double)buf[q].r; });
+      im = fc_cont(a.fc, n, i, [&](int q) { return (double)buf[q].i; });
+    }
+    buf[j] = to_cpx<T>(re, im);
   }
 }
 
@@ -516,12 +521,17 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
   };
 
   // ---- line set-up: values (forward) or coefficients (inverse), extended
+  const bool qw = a.kind == TRIG_QWS || a.kind == TRIG_QWC;
+  const cpx<T> *qtw = static_cast<const cpx<T> *>(a.qtw);
   if (!a.inverse) {
-    if (a.kind == TRIG_DST1) {
-      // interior values 1..n-2; the odd extension is formed in LDS below
+    if (a.kind == TRIG_DST1 || qw) {
+      // unknowns only: DST1 1..n-2, QWS 1..n-1, QWC 0..n-2 (wall values are
+      // zero); the extension is formed in LDS below
+      const int jl = a.kind == TRIG_QWC ? 0 : 1;
+      const int jh = a.kind == TRIG_QWS ? n - 1 : n - 2;
       batched<8, cpx<T>>(lt, n, TL,
                          [&](int j) {
-                           const bool in = j > 0 && j < n - 1;
+                           const bool in = j >= jl && j <= jh;
                            return to_cpx<T>(okA && in ? val(rA, j) : 0.0, okB && in ? val(rB, j) : 0.0);
                          },
                          [&](int j, cpx<T> v) { buf[j] = v; });
@@ -535,6 +545,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
     } else if (a.kind == TRIG_DCT1) {
       for (int j = lt; j < n; j += TL)
         buf[j] = {okA ? get_real_coef<T>(cA, j) : T(0), okB ? get_real_coef<T>(cB, j) : T(0)};
+    } else if (qw) {
+      for (int j = lt; j < n - 1; j += TL)
+        buf[j] = {okA ? get_real_coef<T>(cA, j) : T(0), okB ? get_real_coef<T>(cB, j) : T(0)};
     } else {
       for (int j = lt; j < n; j += TL) {
         const bool in = j > 0 && j < n - 1;
@@ -547,9 +560,19 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
     for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];             // even extension
   } else if (a.kind == TRIG_DST1) {
     for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));   // odd extension
+  } else if (qw && !a.inverse) {
+    // samples N+1 .. 2N-1 of the quarter-wave extension: +x (QWS) / -x (QWC) at 2N - j
+    const T sg = a.kind == TRIG_QWS ? T(1) : T(-1);
+    for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], sg);
+    __syncthreads();
+    for (int j = lt; j < L; j += TL) buf[j] = cmul(buf[j], qtw[j]);
+  } else if (qw) {
+    // odd-frequency coefficients 2N-1-l mirror l: -F (QWS) / +F (QWC)
+    const T sg = a.kind == TRIG_QWS ? T(-1) : T(1);
+    for (int j = n - 1 + lt; j < L; j += TL) buf[j] = cscale(buf[L - 1 - j], sg);
   }
   __syncthreads();
-  const bool cj = a.inverse && a.kind == TRIG_DFT;
+  const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
   line_dft<T, true>(buf, a.plan, lt, TL, cj, cj);
 
   // ---- results
@@ -565,6 +588,20 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
       for (int k = lt; k < a.ncoef; k += TL) {
         if (okA) put_real_coef<T>(cA, k, buf[k].r);
         if (okB) put_real_coef<T>(cB, k, buf[k].i);
+      }
+    } else if (a.kind == TRIG_QWS) {
+      // W = -2i S_a + 2 S_b; stored 4 S
+      for (int k = lt; k < a.ncoef; k += TL) {
+        const cpx<T> z = buf[k];
+        if (okA) put_real_coef<T>(cA, k, T(-2) * z.i);
+        if (okB) put_real_coef<T>(cB, k, T(2) * z.r);
+      }
+    } else if (a.kind == TRIG_QWC) {
+      // W = 2 C_a + 2i C_b; stored 4 C
+      for (int k = lt; k < a.ncoef; k += TL) {
+        const cpx<T> z = buf[k];
+        if (okA) put_real_coef<T>(cA, k, T(2) * z.r);
+        if (okB) put_real_coef<T>(cB, k, T(2) * z.i);
       }
     } else {
       // Z = -i S_a + S_b: S_a = -Im Z, S_b = Re Z, modes 1..n-2 stored at m - 1
@@ -582,6 +619,12 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
       const bool wall = (x == 0 || x == n - 1);
       va = wall ? 0.0 : -(double)buf[x].i;
       vb = wall ? 0.0 : (double)buf[x].r;
+    } else if (qw) {
+      // R = exp(i pi x / 2N) IDFT: QWS R = 2i y_a - 2 y_b, QWC R = 2 y_a + 2i y_b
+      const cpx<T> R = cmul(buf[x], cconj(qtw[x]));
+      const bool wall = a.kind == TRIG_QWS ? x == 0 : x == n - 1;
+      va = wall ? 0.0 : 0.5 * (a.kind == TRIG_QWS ? (double)R.i : (double)R.r);
+      vb = wall ? 0.0 : 0.5 * (a.kind == TRIG_QWS ? -(double)R.r : (double)R.i);
     } else {
       va = (double)buf[x].r;
       vb = (double)buf[x].i;
@@ -598,6 +641,42 @@ template <typename T>
 __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArgs &a, int lt, int TL,
                                                    bool is_values) {
   const int n = a.nline, L = a.plan.n;
+  const bool qw = a.kind == TRIG_QWS || a.kind == TRIG_QWC;
+  if (qw) {
+    const cpx<T> *qtw = static_cast<const cpx<T> *>(a.qtw);
+    if (!is_values) {
+      // values at 0..N: zero the Dirichlet wall, extend, pre-twiddle
+      if (lt == 0) buf[a.kind == TRIG_QWS ? 0 : n - 1] = {T(0), T(0)};
+      const T sg = a.kind == TRIG_QWS ? T(1) : T(-1);
+      for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], sg);
+      __syncthreads();
+      for (int j = lt; j < L; j += TL) buf[j] = cmul(buf[j], qtw[j]);
+      __syncthreads();
+      line_dft<T, true>(buf, a.plan, lt, TL, false, false);
+      // F = 2i W (QWS), 2 W (QWC); position N holds no mode
+      for (int j = lt; j < n; j += TL) {
+        const cpx<T> w = buf[j];
+        buf[j] = j == n - 1 ? cpx<T>{T(0), T(0)}
+                            : (a.kind == TRIG_QWS ? cscale(cpi(w), T(2)) : cscale(w, T(2)));
+      }
+      __syncthreads();
+    } else {
+      // coefficients at 0..N-1: mirror to 2N-1-l, inverse DFT, post-twiddle
+      const T sg = a.kind == TRIG_QWS ? T(-1) : T(1);
+      for (int j = n - 1 + lt; j < L; j += TL) buf[j] = cscale(buf[L - 1 - j], sg);
+      __syncthreads();
+      line_dft<T, true>(buf, a.plan, lt, TL, true, true);
+      // y = -(i/2) R (QWS), R / 2 (QWC), R = exp(i pi j / 2N) IDFT; wall value 0
+      for (int j = lt; j < n; j += TL) {
+        const cpx<T> R = cmul(buf[j], cconj(qtw[j]));
+        const bool wall = a.kind == TRIG_QWS ? j == 0 : j == n - 1;
+        buf[j] = wall ? cpx<T>{T(0), T(0)}
+                      : (a.kind == TRIG_QWS ? cscale(cmi(R), T(0.5)) : cscale(R, T(0.5)));
+      }
+      __syncthreads();
+    }
+    return;
+  }
   if (a.kind == TRIG_DCT1) {
     for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
   } else if (a.kind == TRIG_DST1) {
@@ -668,7 +747,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(PpeColsArgs a) {
         }
       }
       for (int k = lt; k < n; k += TL) {
-        const bool valid = a.kind != TRIG_DST1 || (k >= 1 && k <= n - 2);
+        const bool valid = a.kind == TRIG_DST1 ? (k >= 1 && k <= n - 2)
+                           : (a.kind == TRIG_QWS || a.kind == TRIG_QWC) ? k < n - 1 : true;
         const double ml = valid ? a.mu_line[k] + mo : 0.0;
         const double sr = mir + ml, si = mii + ml;
         const cpx<T> v = buf[k];

@@ -158,8 +158,11 @@ class ChannelFlow3D:
         nx, ny, nz = self.n
         self.dx = dx = 1.0 / (ny - 1)
         Lx, Lz = nx * dx, nz * dx
-        x, y, z = grid(self.n, dx)
-        comps = [np.zeros_like(x) for _ in range(3)]
+        # separable factors broadcast over [z][y][x]
+        x = (np.arange(nx) * dx)[None, None, :]
+        y = (np.arange(ny) * dx)[None, :, None]
+        z = (np.arange(nz) * dx)[:, None, None]
+        comps = [np.zeros((nz, ny, nx)) for _ in range(3)]
         Y = y ** 2 * (1 - y) ** 2
         dY = 2 * y * (1 - y) ** 2 - 2 * y ** 2 * (1 - y)
         for q, seed in enumerate((seed1, seed2)):

@@ -64,6 +64,21 @@ def test_workspace_query_and_validation():
     d.fc_M_dir = None
     assert L.fcsph_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(nb)) == api.E_INVALID
     assert L.fcsph_status_string(api.E_HIP) == b"HIP error"
+    # operator evaluations: the three known values plan, others are rejected
+    for oe in (api.OPS_FFT, api.OPS_DIRECT, api.OPS_FFT_WINDOW):
+        assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(op_eval=oe)), ctypes.byref(nb)) == api.OK
+    assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(op_eval=3)), ctypes.byref(nb)) == api.E_INVALID
+    # 3D: walls on y only; the direct evaluation is 2D only
+    d3 = desc(ndim=3)
+    d3.n[2] = 32
+    d3.axis[0] = d3.axis[2] = api.PERIODIC
+    assert L.fcsph_plan_workspace_bytes(ctypes.byref(d3), ctypes.byref(nb)) == api.OK
+    d3.op_eval = api.OPS_DIRECT
+    assert L.fcsph_plan_workspace_bytes(ctypes.byref(d3), ctypes.byref(nb)) == api.E_UNSUPPORTED
+    d3 = desc(ndim=3)
+    d3.n[2] = 32
+    assert L.fcsph_plan_workspace_bytes(ctypes.byref(d3), ctypes.byref(nb)) == api.E_UNSUPPORTED
+    assert L.fcsph_plan_transform_lengths(None, (ctypes.c_int * 3)()) == api.E_INVALID
 
 
 def test_ctx_create_rejects_bad_device():
