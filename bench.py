@@ -223,7 +223,7 @@ def rel_l2(a, b) -> float:
 
 
 # ------------------------------------------------------------------ 2D workload
-def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64") -> dict:
+def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64", schedule=None) -> dict:
     """Time `steps` FOP steps of the 2D n x n workload."""
     import torch
 
@@ -249,6 +249,9 @@ def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64
     ctx = api.Context(0)
     prob = api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
                        prs_bc=(("N", "N"), ("N", "N")), rho=rho, op_eval=op_eval, precision=precision)
+    if schedule and op_eval == "fft_window":
+        prob.window_len = (schedule["window_len"],) * 2
+        prob.lines_per_group = schedule["lines_per_group"]
     plan = api.Plan(ctx, prob)
 
     def step(k):
@@ -378,6 +381,139 @@ def run_3d(n: int, steps: int, warmup: int, precision: str, ref_states=None, op_
     return out
 
 
+# ------------------------------------------------------------------ batched workload
+BATCH_SIZES = (64, 96, 128, 192, 256, 384, 512)
+
+
+def batch_instances(count: int, seed: int = 30) -> list:
+    """(n, velocity walls) per instance: n ~ U{64..512}, then each of the four
+    walls Dirichlet or Neumann, drawn in that order from one stream."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(BATCH_SIZES))
+        vel = tuple(tuple(str(rng.choice(["D", "N"])) for _ in range(2)) for _ in range(2))
+        out.append((n, vel))
+    return out
+
+
+def _complement(v):
+    return tuple(("N" if a == "D" else "D", "N" if b == "D" else "D") for a, b in v)
+
+
+def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None) -> dict:
+    """One FOP step of every instance per batch step: plain per-plan loop,
+    grouped launch, and grouped launch replayed from a HIP graph."""
+    import torch
+
+    from paper_2606_06247_amd import api, synth
+    dt, nu = 1e-4, 1e-3
+    inst = batch_instances(count)
+    ctx = api.Context(0)
+    plans, states, walls, pts = [], [], [], 0
+    for i, (n, vel) in enumerate(inst):
+        sch = schedules.get(n, {})
+        wl = sch.get("window_len", 0)
+        prob = api.Problem(n=(n, n), walled=(True, True), dx=1.0 / (n - 1), vel_bc=vel,
+                           prs_bc=_complement(vel), precision=precision, op_eval="fft_window",
+                           window_len=(wl, wl) if wl else (), lines_per_group=sch.get("lines_per_group", 0))
+        plans.append(api.Plan(ctx, prob))
+        u = [synth.poly_trig_2d(n, 1000 + 2 * i), synth.poly_trig_2d(n, 1001 + 2 * i)]
+        states.append([torch.from_numpy(c).cuda() for c in u])
+        walls.append([c.clone() for c in states[-1]])
+        pts += n * n
+    init = [[c.clone() for c in st] for st in states]
+    pbuf = [torch.empty_like(st[0]) for st in states]
+    # equality of one batched step with one plain step (copies of the state)
+    plain = [[c.clone() for c in st] for st in init]
+    for i in range(count):
+        plans[i].project_step(plain[i], dt, nu, p_out=pbuf[i], wall=walls[i])
+    b = api.Batch(ctx, count)
+    for i in range(count):
+        b.add_step(plans[i], states[i], dt, nu, p_out=pbuf[i], wall=walls[i])
+    b.launch()
+    torch.cuda.synchronize()
+    equal = all(torch.equal(states[i][a], plain[i][a]) for i in range(count) for a in range(2))
+    fp32_err = None
+    if ref_u is not None:
+        errs = sorted(max(rel_l2(states[i][a], ref_u[i][a]) for a in range(2)) for i in range(count))
+        fp32_err = {"max": float(f"{errs[-1]:.3e}"), "median": float(f"{errs[len(errs) // 2]:.3e}")}
+    first_step = [[c.clone() for c in st] for st in states] if precision == "fp64" else None
+    del plain
+
+    def clock(fn):
+        for st, st0 in zip(states, init):
+            for c, c0 in zip(st, st0):
+                c.copy_(c0)
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def plain_loop():
+        for i in range(count):
+            plans[i].project_step(states[i], dt, nu, p_out=pbuf[i], wall=walls[i])
+
+    t_plain = clock(plain_loop)
+    t_batch = clock(b.launch)
+    b.capture()
+    t_graph = clock(b.replay)
+    items, groups, launches = b.info()
+    # algorithmic bytes of one batch step (sum of the per-instance step models)
+    step_bytes = 0
+    for (n, _), pl in zip(inst, plans):
+        ab = algorithmic_bytes_2d(n, precision == "fp32", pl.transform_lengths()[0])
+        step_bytes += sum(ab[k] for k in ("rows_fwd_pair", "cols_op_step_a", "rows_inv_step_a", "cols_div",
+                                          "rows_inv_store", "ppe_rows_fwd", "ppe_cols_solve", "ppe_rows_inv",
+                                          "rows_fwd", "cols_op_step_d", "rows_inv_step_d"))
+        step_bytes -= 2 * n * n * 8        # no forcing arrays read
+    out = {"instances": count, "points": pts, "groups": groups, "grouped_launches": launches,
+           "batched_equals_plain_bitwise": bool(equal),
+           "solves_per_s": {"plain_loop": round(count / t_plain, 1), "batched": round(count / t_batch, 1),
+                            "batched_graph": round(count / t_graph, 1)},
+           "ms_per_batch_step": {"plain_loop": round(1e3 * t_plain, 3), "batched": round(1e3 * t_batch, 3),
+                                 "batched_graph": round(1e3 * t_graph, 3)},
+           "Mpts_per_s_graph": round(pts / t_graph / 1e6, 1),
+           "roofline": {"bound": "hbm", "achieved": round(step_bytes / t_graph / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(step_bytes / t_graph / 1e9 / HBM_PEAK_GBS, 4),
+                        "basis": "sum of the per-instance step byte models / graph-replay step time"}}
+    if fp32_err is not None:
+        out["fp32_vs_fp64_rel_l2_step1"] = fp32_err
+    del b
+    return out, first_step
+
+
+
+# ------------------------------------------------------------------ serving workload
+def run_serving(precision: str, lams, max_requests: int, window_s: float, plain_lams=()) -> dict:
+    """Poisson request streams at each rate: continuous batching against the
+    plain per-request path."""
+    from paper_2606_06247_amd import serve
+    out = {}
+    for lam in lams:
+        count = int(min(max_requests, max(50, lam * window_s)))
+        reqs = serve.make_requests(lam, count, seed=40)
+        shapes = sorted({(r.dims, r.n) for r in reqs})
+        srv = serve.Server(precision, hbm_budget=200e9, max_batch=64, lanes=2)
+        srv.warm(shapes)
+        warm = [serve.Request(i, 0.0, r.kind, r.dims, r.n, r.seed) for i, r in enumerate(reqs[:16])]
+        srv.run(warm, realtime=False)
+        st = srv.run(reqs, realtime=True)
+        rec = {"offered_req_per_s": lam, "served": st}
+        if lam in plain_lams:
+            reqs2 = serve.make_requests(lam, count, seed=40)
+            rec["plain_per_request"] = serve.run_plain(reqs2, precision, warm_shapes=shapes)
+        out[str(lam)] = rec
+        log(f"  lambda {lam}: {st['solves_per_s']} solves/s p50 {st['p50_ms']} ms p99 {st['p99_ms']} ms")
+        del srv
+    return out
+
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -390,10 +526,14 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--n3", type=int, default=256, help="3D channel lattice n^3")
     ap.add_argument("--steps3", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
+    ap.add_argument("--serve-requests", type=int, default=1200)
+    ap.add_argument("--serve-window", type=float, default=3.0)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--op-eval", choices=["fft", "fft_window", "direct"], default="fft")
+    ap.add_argument("--no-tune", action="store_true", help="library default schedules (no autotuning)")
+    ap.add_argument("--op-eval", choices=["fft", "fft_window", "direct"], default="fft_window")
     ap.add_argument("--no-variants", action="store_true",
                     help="time only the headline workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -411,8 +551,14 @@ def main() -> int:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         return 2
     n = args.n
+    from paper_2606_06247_amd import api as _api, tune
+    sched64 = sched32 = None
+    if not args.no_tune:
+        log(f"tuning {n} fp64 / fp32")
+        sched64 = tune.tune_2d(_api.Context(0), n, "fp64", lines=(1, 2, 4))
+        sched32 = tune.tune_2d(_api.Context(0), n, "fp32", lines=(1, 2, 4))
     log(f"headline 2d {n} fp64 {args.op_eval}")
-    head = run_2d(args.op_eval, n, args.steps, args.warmup)
+    head = run_2d(args.op_eval, n, args.steps, args.warmup, schedule=sched64)
     log(f"  {head['value']} Mpts/s")
     out = {"metric": METRIC, "value": head["value"], "unit": "Mpts/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -423,7 +569,9 @@ def main() -> int:
                                   f"FC(Gram) d=5 C=25 (extended {n + 25}x{n + 25}), Wendland C2 h=1.3dx, "
                                   "nu=1e-3, manufactured decaying-vortex flow, restart every 25 steps",
                       "n": n, "precision": "fp64", "op_eval": args.op_eval,
-                      "gpu_event_ms": head["gpu_event_ms"], "state_finite": head["state_finite"]},
+                      "gpu_event_ms": head["gpu_event_ms"], "state_finite": head["state_finite"],
+                      "transform_lengths": head["transform_lengths"],
+                      "schedule": sched64 if args.op_eval == "fft_window" else None},
            "roofline": head["roofline"], "kernels": head["kernels"]}
     if not args.no_variants:
         keep = ("value", "ms_per_step", "state_finite", "transform_lengths", "roofline", "kernels")
@@ -431,11 +579,11 @@ def main() -> int:
         for oe in ("fft", "fft_window", "direct"):
             if oe != args.op_eval:
                 log(f"variant 2d {n} fp64 {oe}")
-                v = run_2d(oe, n, args.steps, args.warmup)
+                v = run_2d(oe, n, args.steps, args.warmup, schedule=sched64)
                 var[f"2d_{n}_fp64_{oe}"] = {k: v[k] for k in keep}
         for oe in ("fft", "fft_window", "direct"):
             log(f"variant 2d {n} fp32 {oe}")
-            v = run_2d(oe, n, args.steps, args.warmup, precision="fp32")
+            v = run_2d(oe, n, args.steps, args.warmup, precision="fp32", schedule=sched32)
             rec = {k: v[k] for k in keep}
             rec["dtype"] = "f32 transforms, f64 FC/divide/state"
             rec["fp32_vs_fp64_rel_l2"] = fp32_error_2d(n, oe)
@@ -456,6 +604,34 @@ def main() -> int:
                 f"step{k}": {name: float(f"{rel_l2(a, b):.3e}") for name, a, b in
                              zip(("u", "v", "w", "p"), ref32[k], ref64[k])} for k in sorted(ref64)}
             del ref64, ref32
+        # batched solves (512 independent 2D lattices), schedules from the autotuner
+        tctx = _api.Context(0)
+        for prec in ("fp64", "fp32"):
+            sched = {}
+            for nb in BATCH_SIZES:
+                if not args.no_tune:
+                    log(f"tuning {nb} {prec}")
+                    sched[nb] = tune.tune_2d(tctx, nb, prec, lines=(1, 2, 4))
+            log(f"batch {args.batch} {prec}")
+            rec, first = run_batch(args.batch, prec, 5, sched, ref_u=ref_batch if prec == "fp32" else None)
+            if prec == "fp64":
+                ref_batch = first
+            rec["schedules"] = {str(k): v for k, v in sched.items()}
+            rec["workload"] = (f"{args.batch} independent 2D lattices, n ~ U{{64..512}} (seed 30), each wall "
+                               "Dirichlet or Neumann velocity (complementary pressure), manufactured fields, "
+                               "one FOP step per instance per batch step, windowed-FFT operators")
+            var[f"batch_{args.batch}_{prec}"] = rec
+        del ref_batch
+        # served requests (Poisson streams, continuous batching)
+        for prec in ("fp64", "fp32"):
+            log(f"serving {prec}")
+            var[f"serving_{prec}"] = {
+                "workload": "Poisson arrivals; 50% projection steps / 50% PPE solves; 75% 2D n ~ logU(64, 1024), "
+                            "25% 3D channel n ~ logU(64, 192), sizes in multiples of 16; HBM budget 200 GB; "
+                            f"at most {args.serve_requests} requests or {args.serve_window} s of arrivals per rate; "
+                            "2 lanes, up to 64 requests per batch",
+                "rates": run_serving(prec, (50, 100, 200, 500, 1000, 2000), args.serve_requests, args.serve_window,
+                                     plain_lams=(50, 500, 2000))}
         out["variants"] = var
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

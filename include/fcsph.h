@@ -82,6 +82,11 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *  prec        fcsph_precision;  ppe_domain  fcsph_ppe_domain;  eig  fcsph_eig
  *  rho         fluid density
  *  op_eval     fcsph_op_eval
+ *  window_len[a], lines_per_group   schedule hints (0 = the library's
+ *              choice): the transform length of a walled axis under
+ *              FCSPH_OPS_FFT_WINDOW (>= n + 2R, factors 2..13), and the upper
+ *              bound on lines per workgroup of the line kernels (1..16).  They
+ *              change speed, never the result beyond rounding.
  */
 typedef struct {
   int ndim;
@@ -100,6 +105,8 @@ typedef struct {
   int eig;
   double rho;
   int op_eval;
+  int window_len[3];
+  int lines_per_group;
 } fcsph_desc;
 
 typedef struct fcsph_ctx fcsph_ctx;
@@ -191,6 +198,44 @@ fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi);
 fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out,
                                 const double *const *force, const double *const *wall_vel,
                                 double dt, double nu);
+
+/*
+ * Batches: the projection steps and PPE solves of many independent plans
+ * (different sizes, wall types, precisions and operator evaluations) issued
+ * together.  Each added call is validated and its launch sequence recorded
+ * (nothing runs); fcsph_batch_launch groups the items whose sequences have the
+ * same kernels and launch shapes and issues every launch of a group once for
+ * all its items (the group index is the third grid dimension), groups on
+ * separate streams.  Results are bitwise those of the plain calls.
+ * The argument arrays live in a caller-owned device workspace of
+ * fcsph_batch_workspace_bytes(max_items) bytes (256-byte aligned); the batch
+ * also holds a pinned host staging copy and its own HIP streams.
+ * A plan may appear once per batch (items of one plan would share its
+ * scratch); its buffers are read when the batch runs, not when added.
+ * The batch stream waits for the context stream before it starts, and the
+ * context stream waits for the batch to finish.
+ */
+typedef struct fcsph_batch fcsph_batch;
+fcsph_status fcsph_batch_workspace_bytes(int max_items, size_t *bytes);
+fcsph_status fcsph_batch_create(fcsph_ctx *c, int max_items, void *workspace, size_t bytes,
+                                fcsph_batch **out);
+fcsph_status fcsph_batch_destroy(fcsph_batch *b);
+/* Removes every item (the captured graph, if any, stays valid until the next launch). */
+fcsph_status fcsph_batch_clear(fcsph_batch *b);
+/* Adds one fcsph_project_step / fcsph_ppe_solve call (same arguments). */
+fcsph_status fcsph_batch_add_step(fcsph_batch *b, fcsph_plan *p, double *const *u, double *p_out,
+                                  const double *const *force, const double *const *wall_vel,
+                                  double dt, double nu);
+fcsph_status fcsph_batch_add_ppe(fcsph_batch *b, fcsph_plan *p, const void *rhs, double *phi);
+/* Uploads the argument arrays and issues the grouped launches (asynchronous). */
+fcsph_status fcsph_batch_launch(fcsph_batch *b);
+/* Captures the launches of the last fcsph_batch_launch (without the upload)
+ * into a HIP graph; fcsph_batch_replay runs it again on the same buffers
+ * (for steps: the next step of every item). */
+fcsph_status fcsph_batch_capture(fcsph_batch *b);
+fcsph_status fcsph_batch_replay(fcsph_batch *b);
+/* Items, groups and grouped launches of the last launch. */
+fcsph_status fcsph_batch_info(const fcsph_batch *b, int *items, int *groups, int *launches);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,9 @@ EXPORTS = [
     "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
     "fcsph_spectral_div",
     "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_ctx_set_timing",
-    "fcsph_ctx_read_timing",
+    "fcsph_ctx_read_timing", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
+    "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_ppe", "fcsph_batch_launch",
+    "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
 ]
 
 
@@ -49,7 +51,7 @@ class Desc(ctypes.Structure):
         ("fc_M_dir", ctypes.POINTER(ctypes.c_double)), ("fc_M_neu", ctypes.POINTER(ctypes.c_double)),
         ("kernel", ctypes.c_int), ("h_over_dx", ctypes.c_double), ("prec", ctypes.c_int),
         ("ppe_domain", ctypes.c_int), ("eig", ctypes.c_int), ("rho", ctypes.c_double),
-        ("op_eval", ctypes.c_int),
+        ("op_eval", ctypes.c_int), ("window_len", ctypes.c_int * 3), ("lines_per_group", ctypes.c_int),
     ]
 
 
@@ -85,6 +87,16 @@ def lib() -> ctypes.CDLL:
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
     L.fcsph_ctx_set_timing.argtypes = [vp, i]
     L.fcsph_ctx_read_timing.argtypes = [vp, i, ctypes.c_char_p, P(i), P(d), P(i)]
+    L.fcsph_batch_workspace_bytes.argtypes = [i, P(ctypes.c_size_t)]
+    L.fcsph_batch_create.argtypes = [vp, i, vp, ctypes.c_size_t, P(vp)]
+    L.fcsph_batch_destroy.argtypes = [vp]
+    L.fcsph_batch_clear.argtypes = [vp]
+    L.fcsph_batch_add_step.argtypes = [vp, vp, P(vp), vp, P(vp), P(vp), d, d]
+    L.fcsph_batch_add_ppe.argtypes = [vp, vp, vp, vp]
+    L.fcsph_batch_launch.argtypes = [vp]
+    L.fcsph_batch_capture.argtypes = [vp]
+    L.fcsph_batch_replay.argtypes = [vp]
+    L.fcsph_batch_info.argtypes = [vp, P(i), P(i), P(i)]
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:
@@ -122,6 +134,8 @@ class Problem:
     op_eval: str = "fft"          # 'fft' | 'fft_window' | 'direct'
     fc_d: int = 5
     fc_C: int = 25
+    window_len: tuple = ()        # schedule hint per axis (0 = library choice)
+    lines_per_group: int = 0      # schedule hint (0 = library choice)
 
     @property
     def ndim(self):
@@ -208,6 +222,9 @@ def make_desc(prob: "Problem"):
     d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
     d.rho = prob.rho
     d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT, "fft_window": OPS_FFT_WINDOW}[prob.op_eval]
+    for a, L in enumerate(prob.window_len):
+        d.window_len[a] = int(L)
+    d.lines_per_group = int(prob.lines_per_group)
     return d, mdir, mneu
 
 
@@ -327,6 +344,73 @@ class Plan:
         _check(lib().fcsph_project_step(self.handle, up, pp, fp, wp, float(dt), float(nu)),
                self.ctx.handle, "fcsph_project_step")
         return u, p_out
+
+
+class Batch:
+    """Many plans' steps / PPE solves issued as grouped launches (fcsph_batch_*).
+
+    add_step / add_ppe record a call (buffers are read when the batch runs;
+    the batch keeps references to the tensors until clear()); launch() runs
+    every recorded call; capture() / replay() turn the last launch into a HIP
+    graph and run it again on the same buffers."""
+
+    def __init__(self, ctx: Context, max_items: int):
+        import torch
+        L = lib()
+        self.ctx = ctx
+        nb = ctypes.c_size_t()
+        _check(L.fcsph_batch_workspace_bytes(int(max_items), ctypes.byref(nb)), None,
+               "fcsph_batch_workspace_bytes")
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _check(L.fcsph_batch_create(ctx.handle, int(max_items), ctypes.c_void_p(base + off), nb.value,
+                                    ctypes.byref(h)), ctx.handle, "fcsph_batch_create")
+        self.handle = h
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.fcsph_batch_destroy(h)
+            self.handle = None
+
+    def add_step(self, plan: "Plan", u, dt: float, nu: float, p_out=None, force=None, wall=None):
+        up = plan._ptrs([plan._phys(c).value for c in u])
+        fp = plan._ptrs([plan._phys(c).value for c in force]) if force is not None else None
+        wp = plan._ptrs([plan._phys(c).value for c in wall]) if wall is not None else None
+        pp = plan._phys(p_out) if p_out is not None else None
+        _check(lib().fcsph_batch_add_step(self.handle, plan.handle, up, pp, fp, wp, float(dt), float(nu)),
+               self.ctx.handle, "fcsph_batch_add_step")
+        self._keep.append((plan, u, p_out, force, wall))
+
+    def add_ppe(self, plan: "Plan", rhs, out=None):
+        out = plan._new() if out is None else out
+        _check(lib().fcsph_batch_add_ppe(self.handle, plan.handle, plan._phys(rhs, plan.out_dtype),
+                                         plan._phys(out)), self.ctx.handle, "fcsph_batch_add_ppe")
+        self._keep.append((plan, rhs, out))
+        return out
+
+    def launch(self):
+        _check(lib().fcsph_batch_launch(self.handle), self.ctx.handle, "fcsph_batch_launch")
+
+    def capture(self):
+        _check(lib().fcsph_batch_capture(self.handle), self.ctx.handle, "fcsph_batch_capture")
+
+    def replay(self):
+        _check(lib().fcsph_batch_replay(self.handle), self.ctx.handle, "fcsph_batch_replay")
+
+    def clear(self):
+        _check(lib().fcsph_batch_clear(self.handle), self.ctx.handle, "fcsph_batch_clear")
+        self._keep = []
+
+    def info(self) -> tuple:
+        """(items, groups, grouped launches) of the last launch."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().fcsph_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               self.ctx.handle, "fcsph_batch_info")
+        return a.value, b.value, c.value
 
 
 # module-level aliases with the C ABI names

@@ -92,7 +92,9 @@ __device__ __forceinline__ int ghost_slot(int g, int n, int R) { return g < 0 ? 
 
 // One thread per ghost value: x ghosts of every row, then y ghosts of every
 // column of the x-extended lattice (corners: y continuation of x ghosts).
-__global__ void k_ghost2d(DirectArgs a) {
+template <bool G>
+__global__ void k_ghost2d(KArg<DirectArgs, G> ka) {
+  const DirectArgs &a = ka.get();
   const int fi = blockIdx.y;
   const double *f = a.in[fi];
   const int nx = a.n[0], ny = a.n[1], R = a.R;
@@ -151,8 +153,9 @@ __device__ __forceinline__ bool dirichlet_pt(const WallInfo &w, int x, int y, in
 constexpr int RPT = 4;                    // output rows per thread
 constexpr int TYD = RPT * (NT / TX);      // tile height: 16 rows
 
-template <int MODE, int R>
-__global__ void __launch_bounds__(NT) k_direct2d(DirectArgs a) {
+template <int MODE, int R, bool G>
+__global__ void __launch_bounds__(NT) k_direct2d(KArg<DirectArgs, G> ka) {
+  const DirectArgs &a = ka.get();
   constexpr int NF = (MODE == DIR_DIV || MODE == DIR_STEP_A) ? 2 : 1;
   constexpr int W = TX + 2 * R, Hh = TYD + 2 * R;
   constexpr int SW = kSymW;
@@ -289,8 +292,7 @@ __global__ void __launch_bounds__(NT) k_direct2d(DirectArgs a) {
 template <int MODE, int R>
 hipError_t launch2d(const DirectArgs &a, hipStream_t s) {
   const dim3 grid((a.n[0] + TX - 1) / TX, (a.n[1] + TYD - 1) / TYD), block(NT);
-  hipLaunchKernelGGL((k_direct2d<MODE, R>), grid, block, 0, s, a);
-  return hipGetLastError();
+  return issue(k_direct2d<MODE, R, false>, k_direct2d<MODE, R, true>, a, grid, block, 0, s);
 }
 
 template <int MODE>
@@ -310,8 +312,7 @@ hipError_t launch_ghost2d(const DirectArgs &a, int nfields, hipStream_t s) {
   const int total = (a.walled[0] ? a.n[1] * 2 * R : 0) + (a.walled[1] ? 2 * R * (a.n[0] + 2 * R) : 0);
   if (total == 0) return hipSuccess;
   const dim3 grid((total + 255) / 256, nfields), block(256);
-  hipLaunchKernelGGL(k_ghost2d, grid, block, 0, s, a);
-  return hipGetLastError();
+  return issue(k_ghost2d<false>, k_ghost2d<true>, a, grid, block, 0, s);
 }
 
 hipError_t launch_direct(const DirectArgs &a, int mode, hipStream_t s) {

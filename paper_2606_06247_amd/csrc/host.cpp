@@ -49,7 +49,7 @@ struct LaunchTimer {
   const char *name;
   hipEvent_t a = nullptr, b = nullptr;
   LaunchTimer(fcsph_ctx *ctx, const char *n) : c(ctx), name(n) {
-    if (c && c->timing) {
+    if (c && c->timing && !active_recorder()) {
       a = pool_event(c);
       b = pool_event(c);
       if (a) hipEventRecord(a, c->stream);
@@ -359,6 +359,7 @@ struct fcsph_plan {
   int E[3] = {1, 1, 1};     // operator transform length per axis
   int Efc[3] = {1, 1, 1};   // FC-extended period per axis (n + C on walled axes)
   bool window = false;      // windowed operator transforms
+  int want_B = 4;           // lines per workgroup of the line kernels (upper bound)
   int walled[3] = {0, 0, 0};
   int H = 0;            // x half spectrum
   // FC maps (device)
@@ -440,6 +441,7 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
   if (d->ppe_domain != FCSPH_PPE_PHYSICAL) { msg = "only the physical-domain PPE is built"; return FCSPH_E_UNSUPPORTED; }
   if (d->eig != FCSPH_EIG_SPECTRAL && d->eig != FCSPH_EIG_FD2) { msg = "eigenvalue family not built"; return FCSPH_E_UNSUPPORTED; }
   if (!(d->rho > 0.0)) { msg = "rho must be positive"; return FCSPH_E_INVALID; }
+  if (d->lines_per_group < 0 || d->lines_per_group > 16) { msg = "lines_per_group must be in 0..16"; return FCSPH_E_INVALID; }
   bool any_wall = false;
   for (int a = 0; a < d->ndim; ++a) {
     if (d->n[a] < 2) { msg = "n must be >= 2"; return FCSPH_E_INVALID; }
@@ -476,6 +478,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->fp32 = d->prec == FCSPH_FP32_MIXED;
   p->nd = d->ndim;
   p->window = d->op_eval == FCSPH_OPS_FFT_WINDOW;
+  p->want_B = d->lines_per_group > 0 ? d->lines_per_group : 4;
   {
     std::vector<Tap> tl = wendland_tap_list(d->ndim, d->dx, d->h_over_dx, p->reach);
   }
@@ -484,7 +487,17 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     p->walled[a] = a < p->nd ? (d->axis[a] == FCSPH_AXIS_WALLED) : 0;
     p->Efc[a] = p->n[a] + (p->walled[a] ? d->fc_C : 0);
     p->E[a] = p->Efc[a];
-    if (p->window && p->walled[a]) p->E[a] = window_length(p->n[a], p->reach);
+    if (p->window && p->walled[a]) {
+      p->E[a] = window_length(p->n[a], p->reach);
+      if (d->window_len[a] > 0) {
+        std::vector<int> rad;
+        if (d->window_len[a] < p->n[a] + 2 * p->reach || !factor_direct(d->window_len[a], rad)) {
+          msg = "window_len must be >= n + 2 R with radices 2..13";
+          return FCSPH_E_INVALID;
+        }
+        p->E[a] = d->window_len[a];
+      }
+    }
     if (p->E[a] <= 0) {
       msg = "no transform length for the window of axis " + std::to_string(a);
       return FCSPH_E_UNSUPPORTED;
@@ -700,7 +713,7 @@ hipError_t x_fwd_single(fcsph_plan *p, const double *f, int fc, void *S) {
   a.outA = S;
   a.outB = (char *)S + (size_t)p->H * (p->fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
   a.ostrideA = a.ostrideB = 2L * p->H;
-  a.B = pick_B(a.plan, p->fp32, 4);
+  a.B = pick_B(a.plan, p->fp32, p->want_B);
   a.ldsM = padded_len(a.plan.M, a.plan.pad);
   LaunchTimer t(p->ctx, "rows_fwd");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
@@ -723,7 +736,7 @@ hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc,
   a.outA = S0;
   a.outB = S1;
   a.ostrideA = a.ostrideB = p->H;
-  a.B = pick_B(a.plan, p->fp32, 4);
+  a.B = pick_B(a.plan, p->fp32, p->want_B);
   a.ldsM = padded_len(a.plan.M, a.plan.pad);
   LaunchTimer t(p->ctx, "rows_fwd_pair");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
@@ -746,7 +759,7 @@ ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
   c.line_axis = 1;
   c.inner_axis = 0;
   c.outer_axis = -1;
-  c.B = pick_B(c.plan, p->fp32, 4);
+  c.B = pick_B(c.plan, p->fp32, p->want_B);
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }
@@ -764,7 +777,7 @@ hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void
   a.nx = p->n[0];
   a.E = p->E[0];
   a.H = p->H;
-  a.B = pick_B(a.plan, p->fp32, 4);
+  a.B = pick_B(a.plan, p->fp32, p->want_B);
   a.ldsM = padded_len(a.plan.M, a.plan.pad);
   a.spec[0] = spec0;
   a.spec[1] = spec1;
@@ -816,7 +829,7 @@ ColsArgs y_pass_args(fcsph_plan *p, int mode, int fc) {
   c.line_axis = 1;
   c.inner_axis = 0;
   c.outer_axis = 2;
-  c.B = pick_B(c.plan, p->fp32, 4);
+  c.B = pick_B(c.plan, p->fp32, p->want_B);
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }
@@ -836,7 +849,7 @@ ColsArgs z_pass_args(fcsph_plan *p, int mode) {
   c.line_axis = 2;
   c.inner_axis = 0;
   c.outer_axis = 1;
-  c.B = pick_B(c.plan, p->fp32, 4);
+  c.B = pick_B(c.plan, p->fp32, p->want_B);
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }
@@ -916,7 +929,7 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.qtw = p->qtw[0];
-  r.B = pick_B(r.plan, f32, 4);
+  r.B = pick_B(r.plan, f32, p->want_B);
   r.ldsM = padded_len(r.plan.M, r.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_rows_fwd");
@@ -933,7 +946,7 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   cy.ncoef = p->ncoef[1];
   cy.data = p->coef;
   cy.qtw = p->qtw[1];
-  cy.B = pick_B(cy.plan, f32, 4);
+  cy.B = pick_B(cy.plan, f32, p->want_B);
   cy.ldsM = padded_len(cy.plan.M, cy.plan.pad);
   cy.solve = 0;
   {
@@ -958,7 +971,7 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   const double sy = p->trig_kind[1] == TRIG_DFT ? 1.0 / ny : 1.0 / (2.0 * (ny - 1));
   cz.scale = sy / nz;
   cz.data = p->coef;
-  cz.B = pick_B(cz.plan, f32, 4);
+  cz.B = pick_B(cz.plan, f32, p->want_B);
   cz.ldsM = padded_len(cz.plan.M, cz.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_cols_z_solve");
@@ -1001,7 +1014,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.qtw = p->qtw[0];
-  r.B = pick_B(r.plan, f32, 4);
+  r.B = pick_B(r.plan, f32, p->want_B);
   r.ldsM = padded_len(r.plan.M, r.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_rows_fwd");
@@ -1026,7 +1039,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   c.scale = p->trig_kind[1] == TRIG_DFT ? 1.0 / p->n[1] : 1.0 / (2.0 * (p->n[1] - 1));
   c.data = p->coef;
   c.qtw = p->qtw[1];
-  c.B = pick_B(c.plan, f32, 4);
+  c.B = pick_B(c.plan, f32, p->want_B);
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_cols_solve");
@@ -1563,13 +1576,316 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   RowsInvArgs rd = r;
   rd.spec[0] = p->O[0];
   rd.spec[1] = p->O[1];
-  rd.B = pick_B(rd.plan, f32, 4);
+  rd.B = pick_B(rd.plan, f32, p->want_B);
   rd.unew[0] = u[0];
   rd.unew[1] = u[1];
   {
     LaunchTimer t(p->ctx, "rows_inv_step_d");
     if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, f32, s), "step D x inv", st)) return st;
   }
+  return FCSPH_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== batches
+// A batch runs the projection steps / PPE solves of many plans with grouped
+// launches: each item's launch sequence is recorded (not issued), items whose
+// sequences have the same kernels and launch shapes form a group, and every
+// launch of a group is issued once with gridDim.z = group size, each
+// workgroup reading its item's argument struct from the batch workspace.
+// Groups run on their own streams (fork / join around the batch stream) so
+// groups of different shapes overlap on the device.
+namespace {
+constexpr int kBatchStreams = 8;
+enum { BATCH_STEP = 0, BATCH_PPE = 1 };
+}  // namespace
+
+struct fcsph_batch {
+  fcsph_ctx *ctx = nullptr;
+  int max_items = 0;
+  unsigned char *dev = nullptr;      // workspace (argument arrays)
+  size_t dev_bytes = 0;
+  unsigned char *host = nullptr;     // pinned staging of the argument arrays
+  size_t host_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  hipStream_t stream = nullptr;      // the batch's own stream (capturable)
+  hipStream_t gs[kBatchStreams] = {};
+  hipEvent_t fork = nullptr, join[kBatchStreams] = {}, done = nullptr;
+  struct Item {
+    fcsph_plan *p;
+    int kind;
+    Recorder rec;
+  };
+  std::vector<Item> items;
+  struct Issue {
+    const void *gfunc;
+    dim3 grid, block;
+    size_t lds;
+    const void *args;                // device pointer of the group's argument array
+    int stream;                      // group stream index
+  };
+  std::vector<Issue> issues;         // launch list of the last batch_launch
+  int nstreams_used = 0;
+  int ngroups = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+fcsph_status batch_fail(fcsph_batch *b, fcsph_status s, const std::string &m) { return fail(b->ctx, s, m); }
+
+hipError_t batch_issue_all(fcsph_batch *b, hipStream_t s) {
+  // fork: every used group stream waits for the batch stream
+  hipError_t e = hipEventRecord(b->fork, s);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < b->nstreams_used; ++k)
+    if ((e = hipStreamWaitEvent(b->gs[k], b->fork, 0)) != hipSuccess) return e;
+  for (const fcsph_batch::Issue &is : b->issues) {
+    void *arg = const_cast<void *>(is.args);
+    void *params[1] = {&arg};
+    e = hipLaunchKernel(is.gfunc, is.grid, is.block, params, is.lds, b->gs[is.stream]);
+    if (e != hipSuccess) return e;
+  }
+  for (int k = 0; k < b->nstreams_used; ++k) {
+    if ((e = hipEventRecord(b->join[k], b->gs[k])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, b->join[k], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void batch_drop_graph(fcsph_batch *b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+}  // namespace
+
+extern "C" {
+
+// Per item: at most kBatchMaxLaunches launches of at most kBatchMaxArgs bytes,
+// plus the 256-byte alignment of each group's array.
+constexpr int kBatchMaxLaunches = 32;
+constexpr size_t kBatchMaxArgs = 2048;
+static_assert(sizeof(RowsFwdArgs) <= kBatchMaxArgs && sizeof(RowsInvArgs) <= kBatchMaxArgs &&
+                  sizeof(ColsArgs) <= kBatchMaxArgs && sizeof(PpeRowsArgs) <= kBatchMaxArgs &&
+                  sizeof(PpeColsArgs) <= kBatchMaxArgs && sizeof(DirectArgs) <= kBatchMaxArgs,
+              "kernel argument struct larger than the batch slot");
+
+fcsph_status fcsph_batch_workspace_bytes(int max_items, size_t *bytes) {
+  if (max_items < 1 || !bytes) return FCSPH_E_INVALID;
+  *bytes = (size_t)max_items * kBatchMaxLaunches * (kBatchMaxArgs + 256);
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_create(fcsph_ctx *c, int max_items, void *workspace, size_t bytes, fcsph_batch **out) {
+  if (!c || !out || max_items < 1 || !workspace) return c ? fail(c, FCSPH_E_INVALID, "bad batch arguments") : FCSPH_E_INVALID;
+  *out = nullptr;
+  size_t need = 0;
+  fcsph_batch_workspace_bytes(max_items, &need);
+  if (bytes < need || ((uintptr_t)workspace & 255)) return fail(c, FCSPH_E_WORKSPACE, "batch workspace too small or misaligned");
+  fcsph_batch *b = new (std::nothrow) fcsph_batch;
+  if (!b) return FCSPH_E_INVALID;
+  b->ctx = c;
+  b->max_items = max_items;
+  b->dev = (unsigned char *)workspace;
+  b->dev_bytes = bytes;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&b->gs[k], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming);
+  for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+  if (e == hipSuccess) {
+    b->host_bytes = bytes;
+    e = hipHostMalloc((void **)&b->host, bytes, hipHostMallocDefault);
+  }
+  if (e != hipSuccess) {
+    fcsph_batch_destroy(b);
+    return hip_fail(c, e, "batch create");
+  }
+  *out = b;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_destroy(fcsph_batch *b) {
+  if (!b) return FCSPH_OK;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  for (int k = 0; k < kBatchStreams; ++k) {
+    if (b->gs[k]) hipStreamDestroy(b->gs[k]);
+    if (b->join[k]) hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) hipEventDestroy(b->fork);
+  if (b->done) hipEventDestroy(b->done);
+  if (b->upload_done) {
+    hipEventSynchronize(b->upload_done);
+    hipEventDestroy(b->upload_done);
+  }
+  if (b->stream) hipStreamDestroy(b->stream);
+  if (b->host) hipHostFree(b->host);
+  delete b;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_clear(fcsph_batch *b) {
+  if (!b) return FCSPH_E_INVALID;
+  b->items.clear();
+  return FCSPH_OK;
+}
+
+static fcsph_status batch_add(fcsph_batch *b, fcsph_plan *p, int kind) {
+  if ((int)b->items.size() >= b->max_items) return batch_fail(b, FCSPH_E_INVALID, "batch is full");
+  for (const fcsph_batch::Item &it : b->items)
+    if (it.p == p) return batch_fail(b, FCSPH_E_INVALID, "a plan may appear once per batch (its scratch is shared)");
+  b->items.push_back({p, kind, Recorder{}});
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_add_step(fcsph_batch *b, fcsph_plan *p, double *const *u, double *p_out,
+                                  const double *const *force, const double *const *wall_vel, double dt,
+                                  double nu) {
+  if (!b || !p) return b ? batch_fail(b, FCSPH_E_INVALID, "null plan") : FCSPH_E_INVALID;
+  fcsph_status st = batch_add(b, p, BATCH_STEP);
+  if (st != FCSPH_OK) return st;
+  Recorder *&r = active_recorder();
+  r = &b->items.back().rec;
+  st = fcsph_project_step(p, u, p_out, force, wall_vel, dt, nu);
+  r = nullptr;
+  if (st == FCSPH_OK && b->items.back().rec.recs.size() > (size_t)kBatchMaxLaunches)
+    st = fail(p->ctx, FCSPH_E_UNSUPPORTED, "too many launches for a batch item");
+  if (st != FCSPH_OK) {
+    b->items.pop_back();
+    return fail(b->ctx, st, std::string("batch step: ") + fcsph_ctx_last_error(p->ctx));
+  }
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_add_ppe(fcsph_batch *b, fcsph_plan *p, const void *rhs, double *phi) {
+  if (!b || !p) return b ? batch_fail(b, FCSPH_E_INVALID, "null plan") : FCSPH_E_INVALID;
+  fcsph_status st = batch_add(b, p, BATCH_PPE);
+  if (st != FCSPH_OK) return st;
+  Recorder *&r = active_recorder();
+  r = &b->items.back().rec;
+  st = fcsph_ppe_solve(p, rhs, phi);
+  r = nullptr;
+  if (st == FCSPH_OK && b->items.back().rec.recs.size() > (size_t)kBatchMaxLaunches)
+    st = fail(p->ctx, FCSPH_E_UNSUPPORTED, "too many launches for a batch item");
+  if (st != FCSPH_OK) {
+    b->items.pop_back();
+    return fail(b->ctx, st, std::string("batch ppe: ") + fcsph_ctx_last_error(p->ctx));
+  }
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_launch(fcsph_batch *b) {
+  if (!b) return FCSPH_E_INVALID;
+  fcsph_ctx *c = b->ctx;
+  batch_drop_graph(b);
+  b->issues.clear();
+  if (b->items.empty()) return FCSPH_OK;
+  // group items by launch signature
+  std::vector<std::string> sig(b->items.size());
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    std::string &k = sig[i];
+    for (const LaunchRecord &r : b->items[i].rec.recs) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "%p/%u.%u.%u/%u/%zu/%zu;", r.gfunc, r.grid.x, r.grid.y, r.grid.z, r.block.x,
+                    r.lds, r.args.size());
+      k += buf;
+    }
+  }
+  std::vector<std::vector<int>> groups;
+  std::vector<std::string> gsig;
+  for (size_t i = 0; i < sig.size(); ++i) {
+    size_t g = 0;
+    while (g < gsig.size() && gsig[g] != sig[i]) ++g;
+    if (g == gsig.size()) {
+      gsig.push_back(sig[i]);
+      groups.emplace_back();
+    }
+    groups[g].push_back((int)i);
+  }
+  // lay out the argument arrays: group by group, launch by launch
+  if (hipEventSynchronize(b->upload_done) != hipSuccess) return hip_fail(c, hipGetLastError(), "batch upload wait");
+  size_t off = 0;
+  b->nstreams_used = std::min<int>((int)groups.size(), kBatchStreams);
+  b->ngroups = (int)groups.size();
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const std::vector<int> &m = groups[g];
+    const Recorder &r0 = b->items[m[0]].rec;
+    for (size_t k = 0; k < r0.recs.size(); ++k) {
+      const size_t asz = r0.recs[k].args.size();
+      off = (off + 255) & ~size_t(255);
+      if (off + asz * m.size() > b->dev_bytes) return fail(c, FCSPH_E_WORKSPACE, "batch argument arrays exceed the workspace");
+      for (size_t q = 0; q < m.size(); ++q)
+        std::memcpy(b->host + off + q * asz, b->items[m[q]].rec.recs[k].args.data(), asz);
+      fcsph_batch::Issue is;
+      is.gfunc = r0.recs[k].gfunc;
+      is.grid = dim3(r0.recs[k].grid.x, r0.recs[k].grid.y, (unsigned)m.size());
+      is.block = r0.recs[k].block;
+      is.lds = r0.recs[k].lds;
+      is.args = b->dev + off;
+      is.stream = (int)(g % kBatchStreams);
+      b->issues.push_back(is);
+      off += asz * m.size();
+    }
+  }
+  hipError_t e = hipSetDevice(c->device);
+  // the batch stream follows the context stream, uploads, runs the groups
+  if (e == hipSuccess) e = hipEventRecord(b->done, c->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->done, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->dev, b->host, off, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->upload_done, b->stream);
+  if (e == hipSuccess) e = batch_issue_all(b, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, b->done, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "batch launch");
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_capture(fcsph_batch *b) {
+  if (!b) return FCSPH_E_INVALID;
+  fcsph_ctx *c = b->ctx;
+  if (b->issues.empty()) return fail(c, FCSPH_E_INVALID, "nothing launched to capture");
+  batch_drop_graph(b);
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(c, e, "batch capture begin");
+  hipError_t e2 = batch_issue_all(b, b->stream);
+  e = hipStreamEndCapture(b->stream, &b->graph);
+  if (e2 != hipSuccess || e != hipSuccess) {
+    batch_drop_graph(b);
+    return hip_fail(c, e2 != hipSuccess ? e2 : e, "batch capture");
+  }
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    batch_drop_graph(b);
+    return hip_fail(c, e, "batch graph instantiate");
+  }
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_replay(fcsph_batch *b) {
+  if (!b) return FCSPH_E_INVALID;
+  fcsph_ctx *c = b->ctx;
+  if (!b->exec) return fail(c, FCSPH_E_INVALID, "no captured graph");
+  hipError_t e = hipEventRecord(b->done, c->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->done, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, b->done, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "batch replay");
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_batch_info(const fcsph_batch *b, int *items, int *groups, int *launches) {
+  if (!b) return FCSPH_E_INVALID;
+  if (items) *items = (int)b->items.size();
+  if (groups) *groups = b->ngroups;
+  if (launches) *launches = (int)b->issues.size();
   return FCSPH_OK;
 }
 

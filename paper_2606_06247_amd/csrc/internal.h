@@ -4,6 +4,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <cstring>
+#include <vector>
+
 namespace fcsph {
 
 constexpr int kMaxStages = 16;
@@ -273,6 +276,66 @@ struct FcExtArgs {
   long total_in_per_line_stride;
   FcWalls fc;
 };
+
+// ---------------------------------------------------------------- launch plumbing
+// Kernel argument: the argument struct itself (one problem per launch), or a
+// device array of them indexed by blockIdx.z (grouped launch: many problems
+// with the same launch shape in one dispatch).
+template <typename A, bool G>
+struct KArg;
+template <typename A>
+struct KArg<A, false> {
+  A a;
+  __device__ __forceinline__ const A &get() const { return a; }
+};
+template <typename A>
+struct KArg<A, true> {
+  const A *__restrict__ arr;
+  __device__ __forceinline__ const A &get() const { return arr[blockIdx.z]; }
+};
+
+// One launch captured instead of issued: the grouped kernel, its per-problem
+// launch shape and the bytes of its argument struct.
+struct LaunchRecord {
+  const void *gfunc;
+  dim3 grid, block;
+  size_t lds;
+  std::vector<unsigned char> args;
+};
+struct Recorder {
+  std::vector<LaunchRecord> recs;
+};
+// While non-null (per host thread), launchers append to it and issue nothing.
+Recorder *&active_recorder();
+
+template <typename K>
+inline hipError_t set_kernel_lds(K kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Issue kernel `ks` on stream s, or record its grouped twin `kg`.
+template <typename A, typename KS, typename KG>
+inline hipError_t issue(KS ks, KG kg, const A &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  if (Recorder *r = active_recorder()) {
+    if (grid.z != 1) return hipErrorInvalidValue;
+    hipError_t e = set_kernel_lds(kg, lds);
+    if (e != hipSuccess) return e;
+    LaunchRecord rec;
+    rec.gfunc = reinterpret_cast<const void *>(kg);
+    rec.grid = grid;
+    rec.block = block;
+    rec.lds = lds;
+    rec.args.resize(sizeof(A));
+    std::memcpy(rec.args.data(), &a, sizeof(A));
+    r->recs.push_back(std::move(rec));
+    return hipSuccess;
+  }
+  hipError_t e = set_kernel_lds(ks, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ks, grid, block, lds, s, KArg<A, false>{a});
+  return hipGetLastError();
+}
 
 // launchers (kernels.hip); return hipError_t
 hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s);

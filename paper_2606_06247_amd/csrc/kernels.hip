@@ -52,8 +52,9 @@ __device__ __forceinline__ double fc_cont(const FcWalls &fc, int n, int i, Get g
 }
 
 // ============================================================= rows forward
-template <typename T>
-__global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(RowsFwdArgs a) {
+template <typename T, bool G>
+__global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(KArg<RowsFwdArgs, G> ka) {
+  const RowsFwdArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
   const int TL = a.plan.TL;
@@ -127,8 +128,9 @@ __device__ __forceinline__ size_t spec_row(const RowsInvArgs &a, int r) {
   return ((size_t)(r / a.rpp) * a.prow + (r % a.rpp)) * (size_t)a.spec_pitch;
 }
 
-template <typename T, int EPI>
-__global__ void __launch_bounds__(kMaxThreads) k_rows_inv(RowsInvArgs a) {
+template <typename T, int EPI, bool GR>
+__global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> ka) {
+  const RowsInvArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
   const int TL = a.plan.TL;
@@ -387,8 +389,9 @@ __device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, 
   }
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kMaxThreads) k_cols(ColsArgs a) {
+template <typename T, int MODE, bool G>
+__global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
+  const ColsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
   const int TL = a.plan.TL;
@@ -501,8 +504,9 @@ __device__ __forceinline__ T get_real_coef(const cpx<T> *row, int m) {
   return p[m & 1];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
+template <typename T, bool G>
+__global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> ka) {
+  const PpeRowsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
   const int TL = a.plan.TL;
@@ -611,6 +615,13 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(PpeRowsArgs a) {
         if (okB) put_real_coef<T>(cB, k, z.r);
       }
     }
+    // an odd coefficient count leaves the last real slot of the packed row
+    // unused: write zero, since the column transforms round the two slots of
+    // a complex element together
+    if (a.kind != TRIG_DFT && (a.ncoef & 1) && lt == 0) {
+      if (okA) put_real_coef<T>(cA, a.ncoef, T(0));
+      if (okB) put_real_coef<T>(cB, a.ncoef, T(0));
+    }
     return;
   }
   for (int x = lt; x < n; x += TL) {
@@ -701,8 +712,9 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(PpeColsArgs a) {
+template <typename T, bool G>
+__global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> ka) {
+  const PpeColsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
   const int TL = a.plan.TL;
@@ -789,36 +801,25 @@ __global__ void k_fc_extend(const double *in, double *out, long outer, int len, 
 }
 
 // ============================================================= launchers
-static size_t lds_bytes(int B, int ldsM, bool fp32) {
-  return (size_t)B * ldsM * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
+Recorder *&active_recorder() {
+  static thread_local Recorder *r = nullptr;
+  return r;
 }
 
-template <typename K>
-static hipError_t set_lds(K kern, size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+static size_t lds_bytes(int B, int ldsM, bool fp32) {
+  return (size_t)B * ldsM * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
 }
 
 hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s) {
   const dim3 grid((a.nlines + a.B - 1) / a.B), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
-  hipError_t e;
-  if (fp32) {
-    if ((e = set_lds(k_rows_fwd<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_fwd<float>, grid, block, lds, s, a);
-  } else {
-    if ((e = set_lds(k_rows_fwd<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_fwd<double>, grid, block, lds, s, a);
-  }
-  return hipGetLastError();
+  if (fp32) return issue(k_rows_fwd<float, false>, k_rows_fwd<float, true>, a, grid, block, lds, s);
+  return issue(k_rows_fwd<double, false>, k_rows_fwd<double, true>, a, grid, block, lds, s);
 }
 
 template <typename T, int EPI>
 static hipError_t rows_inv_t(const RowsInvArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-  hipError_t e = set_lds(k_rows_inv<T, EPI>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_rows_inv<T, EPI>), grid, block, lds, s, a);
-  return hipGetLastError();
+  return issue(k_rows_inv<T, EPI, false>, k_rows_inv<T, EPI, true>, a, grid, block, lds, s);
 }
 
 template <typename T>
@@ -863,10 +864,7 @@ hipError_t launch_rows_inv(const RowsInvArgs &a, int epi, bool fp32, hipStream_t
 
 template <typename T, int MODE>
 static hipError_t cols_t(const ColsArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-  hipError_t e = set_lds(k_cols<T, MODE>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cols<T, MODE>), grid, block, lds, s, a);
-  return hipGetLastError();
+  return issue(k_cols<T, MODE, false>, k_cols<T, MODE, true>, a, grid, block, lds, s);
 }
 
 template <typename T>
@@ -891,30 +889,16 @@ hipError_t launch_ppe_rows(const PpeRowsArgs &a, bool fp32, hipStream_t s) {
   const int nl = (a.nrows + 1) / 2;
   const dim3 grid((nl + a.B - 1) / a.B), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
-  hipError_t e;
-  if (fp32) {
-    if ((e = set_lds(k_ppe_rows<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ppe_rows<float>, grid, block, lds, s, a);
-  } else {
-    if ((e = set_lds(k_ppe_rows<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ppe_rows<double>, grid, block, lds, s, a);
-  }
-  return hipGetLastError();
+  if (fp32) return issue(k_ppe_rows<float, false>, k_ppe_rows<float, true>, a, grid, block, lds, s);
+  return issue(k_ppe_rows<double, false>, k_ppe_rows<double, true>, a, grid, block, lds, s);
 }
 
 hipError_t launch_ppe_cols(const PpeColsArgs &a, bool fp32, hipStream_t s) {
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const dim3 grid(npanel * a.nouter), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
-  hipError_t e;
-  if (fp32) {
-    if ((e = set_lds(k_ppe_cols<float>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ppe_cols<float>, grid, block, lds, s, a);
-  } else {
-    if ((e = set_lds(k_ppe_cols<double>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ppe_cols<double>, grid, block, lds, s, a);
-  }
-  return hipGetLastError();
+  if (fp32) return issue(k_ppe_cols<float, false>, k_ppe_cols<float, true>, a, grid, block, lds, s);
+  return issue(k_ppe_cols<double, false>, k_ppe_cols<double, true>, a, grid, block, lds, s);
 }
 
 hipError_t launch_fc_extend_axis(const double *in, double *out, int ndim, const int *shape_in,

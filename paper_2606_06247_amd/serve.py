@@ -1,0 +1,263 @@
+"""Serving loop: continuous batching of projection-step and PPE-solve requests.
+
+Requests arrive over time (a Poisson stream, or any list of arrival times).
+The server keeps plans and their device workspaces resident, one pool of plan
+instances per (kind, shape, precision), and admits work against a fixed HBM
+budget: a request is admitted when a plan instance of its shape is idle (or a
+new one fits in the budget) and its buffers fit.  Admitted requests are packed
+into a batch (grouped launches, `api.Batch`) on one of several lanes (each
+lane: its own context stream and batch object), so requests that arrive while
+other batches run are issued as soon as a lane is free and their work
+overlaps on the device with the batches already in flight.  Completion is
+observed by polling an event per batch; latency = completion - arrival.
+
+Every result equals the plain call on the same plan bitwise (the batch
+launches the same kernels on the same data), so a request gives the same
+output alone and in the mix.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import api, synth
+
+
+@dataclass
+class Request:
+    rid: int
+    t_arrival: float          # seconds from the start of the stream
+    kind: str                 # 'step' | 'ppe'
+    dims: int                 # 2 | 3
+    n: int                    # lattice points per axis
+    seed: int
+    t_done: float = math.nan
+    out: list = field(default_factory=list)
+
+
+def make_requests(lam: float, count: int, seed: int = 40, p_step: float = 0.5, p_2d: float = 0.75,
+                  n2=(64, 1024), n3=(64, 192), quantum2: int = 16, quantum3: int = 16) -> list:
+    """Poisson arrivals at rate lam; per request (in this order): inter-arrival
+    gap ~ Exp(lam), kind step w.p. p_step, 2D w.p. p_2d, size log-uniform over
+    the range rounded to a multiple of the quantum (a finite set of shapes
+    keeps the plan cache finite)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / lam)
+        kind = "step" if rng.random() < p_step else "ppe"
+        dims = 2 if rng.random() < p_2d else 3
+        lo, hi = n2 if dims == 2 else n3
+        q = quantum2 if dims == 2 else quantum3
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))) / q) * q)
+        n = min(max(n, lo), hi)
+        out.append(Request(i, t, kind, dims, n, int(rng.integers(1 << 30))))
+    return out
+
+
+def problem_for(dims: int, n: int, precision: str, op_eval: str = "fft_window") -> api.Problem:
+    """2D: walls on all four sides, Dirichlet velocity and pressure; 3D: the
+    channel (walls on y, Dirichlet velocity, Neumann pressure)."""
+    if dims == 2:
+        return api.Problem(n=(n, n), walled=(True, True), dx=1.0 / (n - 1),
+                           vel_bc=(("D", "D"), ("D", "D")), prs_bc=(("D", "D"), ("D", "D")),
+                           precision=precision, op_eval=op_eval)
+    return api.Problem(n=(n, n, n), walled=(False, True, False), dx=1.0 / (n - 1),
+                       vel_bc=(None, ("D", "D"), None), prs_bc=(None, ("N", "N"), None),
+                       precision=precision, op_eval=op_eval)
+
+
+class Server:
+    def __init__(self, precision: str = "fp64", hbm_budget: float = 200e9, max_batch: int = 64,
+                 lanes: int = 2, op_eval: str = "fft_window", dt: float = 1e-4, nu: float = 1e-3):
+        import torch
+        self.precision, self.op_eval = precision, op_eval
+        self.budget = hbm_budget
+        self.max_batch = max_batch
+        self.dt, self.nu = dt, nu
+        self.streams = [torch.cuda.Stream() for _ in range(lanes)]
+        self.ctxs = [api.Context(0, s.cuda_stream) for s in self.streams]
+        self.batches = [api.Batch(c, max_batch) for c in self.ctxs]
+        self.inflight = [None] * lanes          # (event, [(request, plan instance, bufs)])
+        self.pool: dict = {}                    # shape key -> idle plans
+        self.busy_plans = 0
+        self.used = 0.0                         # bytes: plan workspaces + request buffers in flight
+        self.templates: dict = {}
+        self.plan_ctx = api.Context(0)
+        self.stats = {"plans_created": 0, "admitted": 0, "max_queue": 0, "batches": 0}
+
+    # ---- resident state
+    def _key(self, r: Request):
+        return (r.dims, r.n)
+
+    def _template(self, dims, n):
+        import torch
+        k = (dims, n)
+        if k not in self.templates:
+            if dims == 2:
+                f = [synth.poly_trig_2d(n, 2 * n), synth.poly_trig_2d(n, 2 * n + 1)]
+            else:
+                f = list(synth.ChannelFlow3D((n, n, n), 20, 21).u)
+            self.templates[k] = [torch.from_numpy(c).cuda() for c in f]
+        return self.templates[k]
+
+    def _new_plan(self, dims, n):
+        plan = api.Plan(self.plan_ctx, problem_for(dims, n, self.precision, self.op_eval))
+        self.plan_ctx.sync()           # tables resident before any lane stream uses the plan
+        self.used += plan.workspace.numel()
+        self.stats["plans_created"] += 1
+        return plan
+
+    def warm(self, shapes):
+        """Create one resident plan and the input template per shape."""
+        for dims, n in shapes:
+            self._template(dims, n)
+            self.pool.setdefault((dims, n), []).append(self._new_plan(dims, n))
+
+    def _request_bytes(self, r: Request) -> int:
+        pts = r.n ** r.dims
+        return pts * 8 * (2 * r.dims + 1 if r.kind == "step" else 2)
+
+    def _acquire(self, r: Request):
+        idle = self.pool.setdefault(self._key(r), [])
+        need = self._request_bytes(r)
+        if idle:
+            if self.used + need > self.budget:
+                return None
+            return idle.pop()
+        ws = api.workspace_bytes(problem_for(r.dims, r.n, self.precision, self.op_eval))
+        if self.used + ws + need > self.budget:
+            return None
+        return self._new_plan(r.dims, r.n)
+
+    def _inputs(self, r: Request):
+        import torch
+        tpl = self._template(r.dims, r.n)
+        s = 1.0 + (r.seed % 97) / 97.0
+        if r.kind == "step":
+            u = [(c * s).contiguous() for c in tpl]
+            wall = [c.clone() for c in u]
+            p = torch.empty_like(u[0])
+            return {"u": u, "wall": wall, "p": p}
+        rhs = (tpl[0] * s).contiguous()
+        if self.precision == "fp32":
+            rhs = rhs.float()
+        return {"rhs": rhs, "phi": torch.empty_like(tpl[0])}
+
+    # ---- the loop
+    def _poll(self, now_fn):
+        done = 0
+        for k, fl in enumerate(self.inflight):
+            if fl is None or not fl[0].query():
+                continue
+            t = now_fn()
+            for r, plan, bufs in fl[1]:
+                r.t_done = t
+                r.out = [bufs["u"], bufs["p"]] if r.kind == "step" else [bufs["phi"]]
+                self.pool[self._key(r)].append(plan)
+                self.used -= self._request_bytes(r)
+                done += 1
+            self.inflight[k] = None
+        return done
+
+    def _launch(self, lane: int, work):
+        b = self.batches[lane]
+        b.clear()
+        for r, plan, bufs in work:
+            if r.kind == "step":
+                b.add_step(plan, bufs["u"], self.dt, self.nu, p_out=bufs["p"], wall=bufs["wall"])
+            else:
+                b.add_ppe(plan, bufs["rhs"], bufs["phi"])
+        b.launch()
+        ev = self.streams[lane].record_event()
+        self.inflight[lane] = (ev, work)
+        self.stats["batches"] += 1
+
+    def run(self, requests: list, realtime: bool = True, keep_outputs: bool = False) -> dict:
+        """Serve the requests (arrival times relative to the start); returns
+        throughput and latency statistics."""
+        import torch
+        torch.cuda.synchronize()
+        pending = deque(sorted(requests, key=lambda r: r.t_arrival))
+        queue: deque = deque()
+        if not realtime:                     # burst: every request arrives at once
+            for r in pending:
+                r.t_arrival = 0.0
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+        remaining = len(requests)
+        while remaining:
+            t = now()
+            while pending and pending[0].t_arrival <= t:
+                queue.append(pending.popleft())
+            self.stats["max_queue"] = max(self.stats["max_queue"], len(queue))
+            remaining -= self._poll(now)
+            free = [k for k, fl in enumerate(self.inflight) if fl is None]
+            if free and queue:
+                lane = free[0]
+                work, skipped = [], deque()
+                with torch.cuda.stream(self.streams[lane]):     # inputs ordered before the lane's batch
+                    while queue and len(work) < self.max_batch:
+                        r = queue.popleft()
+                        plan = self._acquire(r)
+                        if plan is None:
+                            skipped.append(r)
+                            continue
+                        self.used += self._request_bytes(r)
+                        work.append((r, plan, self._inputs(r)))
+                        self.stats["admitted"] += 1
+                queue.extendleft(reversed(skipped))
+                if work:
+                    self._launch(lane, work)
+                    continue
+            if not free or not queue:
+                time.sleep(0.0002)
+        wall = now()
+        lat = np.array([r.t_done - r.t_arrival for r in requests])
+        if not keep_outputs:
+            for r in requests:
+                r.out = []
+        return {"requests": len(requests), "wall_s": round(wall, 3),
+                "solves_per_s": round(len(requests) / wall, 1),
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                "plans_created": self.stats["plans_created"], "batches": self.stats["batches"],
+                "max_queue": self.stats["max_queue"], "hbm_used_GB": round(self.used / 1e9, 2)}
+
+
+def run_plain(requests: list, precision: str = "fp64", op_eval: str = "fft_window", realtime: bool = True,
+              dt: float = 1e-4, nu: float = 1e-3, warm_shapes=()) -> dict:
+    """The plain per-request path at the same arrival times: one request at a
+    time on resident plans, each call synchronised before the next."""
+    import torch
+    srv = Server(precision, op_eval=op_eval, lanes=1, max_batch=1, dt=dt, nu=nu)
+    srv.warm(warm_shapes)
+    pending = deque(sorted(requests, key=lambda r: r.t_arrival))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in pending:
+        if realtime:
+            while time.perf_counter() - t0 < r.t_arrival:
+                time.sleep(0.0002)
+        plan = srv._acquire(r)
+        bufs = srv._inputs(r)
+        if r.kind == "step":
+            plan.project_step(bufs["u"], dt, nu, p_out=bufs["p"], wall=bufs["wall"])
+        else:
+            plan.ppe_solve(bufs["rhs"], bufs["phi"])
+        torch.cuda.synchronize()
+        r.t_done = time.perf_counter() - t0
+        srv.pool[srv._key(r)].append(plan)
+    wall = time.perf_counter() - t0
+    lat = np.array([r.t_done - r.t_arrival for r in requests])
+    return {"requests": len(requests), "wall_s": round(wall, 3),
+            "solves_per_s": round(len(requests) / wall, 1),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)}

@@ -33,9 +33,10 @@ def poly_trig_2d(n, seed: int, dx: float | None = None) -> np.ndarray:
     """
     nx, ny = (n, n) if np.isscalar(n) else n
     dx = 1.0 / (nx - 1) if dx is None else dx
-    x, y = grid((nx, ny), dx)
+    x = (np.arange(nx) * dx)[None, :]        # separable factors, broadcast over [y][x]
+    y = (np.arange(ny) * dx)[:, None]
     rng = np.random.default_rng(seed)
-    f = np.zeros_like(x)
+    f = np.zeros((ny, nx))
     for a in range(4):
         for b in range(4 - a):
             f += rng.standard_normal() * x ** a * y ** b

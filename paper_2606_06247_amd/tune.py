@@ -1,0 +1,123 @@
+"""Schedule autotuner: picks the transform length of the windowed operator
+evaluation and the number of lines per workgroup of the line kernels for one
+lattice shape by timing whole projection steps on the device.
+
+The candidates only change speed: every schedule computes the same
+convolutions and PPE (the window length is any smooth L >= n + 2R, the lines
+per workgroup only regroup independent lines), so the tuner is free to pick
+the fastest.  Results are cached per (shape, precision) in memory and, when a
+path is given, in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import api
+
+RADIX_COST = {2: 1.0, 3: 1.35, 4: 1.1, 5: 1.7, 7: 2.4, 8: 1.4}
+
+
+def _factor(L: int):
+    """Radix list of L over {8, 4, 2, 3, 5, 7} (as the library factors it), or None."""
+    rad, m = [], L
+    while m % 8 == 0:
+        rad.append(8)
+        m //= 8
+    while m % 4 == 0:
+        rad.append(4)
+        m //= 4
+    while m % 2 == 0:
+        rad.append(2)
+        m //= 2
+    for p in (3, 5, 7):
+        while m % p == 0:
+            rad.append(p)
+            m //= p
+    return rad if m == 1 else None
+
+
+def window_candidates(n: int, reach: int = 2, count: int = 5, span: float = 1.35) -> list:
+    """The `count` cheapest smooth window lengths in [n + 2R, span (n + 2R)]
+    under a per-point cost model (HBM term + butterfly stages)."""
+    lo = n + 2 * reach
+    scored = []
+    for L in range(lo, int(math.ceil(span * lo)) + 1):
+        rad = _factor(L)
+        if rad is None:
+            continue
+        scored.append(((4.0 + sum(RADIX_COST[r] for r in rad)) * L, L))
+    scored.sort()
+    return [L for _, L in scored[:count]]
+
+
+def _problem_2d(n, precision, window_len=0, lines=0):
+    dx = 1.0 / (n - 1)
+    wl = (window_len, window_len) if window_len else ()
+    return api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
+                       prs_bc=(("N", "N"), ("N", "N")), precision=precision, op_eval="fft_window",
+                       window_len=wl, lines_per_group=lines)
+
+
+def time_step(ctx, prob, steps: int = 8, warmup: int = 2) -> float:
+    """Median milliseconds of one projection step of `prob` (synthetic state)."""
+    import torch
+    plan = api.Plan(ctx, prob)
+    shape = prob.shape
+    g = torch.Generator(device="cpu").manual_seed(0)
+    u = [torch.randn(shape, generator=g, dtype=torch.float64).cuda() * 1e-3 for _ in range(prob.ndim)]
+    p = torch.empty_like(u[0])
+    for _ in range(warmup):
+        plan.project_step(u, 1e-6, 1e-3, p_out=p)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.project_step(u, 1e-6, 1e-3, p_out=p)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+_CACHE: dict = {}
+
+
+def tune_2d(ctx, n: int, precision: str = "fp64", lines=(1, 2, 4, 8), cache_path: str | None = None,
+            log=None) -> dict:
+    """Best (window_len, lines_per_group) for the 2D n x n walled lattice."""
+    key = f"2d:{n}:{precision}"
+    if key in _CACHE:
+        return _CACHE[key]
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            disk = json.load(fh)
+        if key in disk:
+            _CACHE[key] = disk[key]
+            return disk[key]
+    best = None
+    trials = []
+    for L in window_candidates(n):
+        for b in lines:
+            ms = time_step(ctx, _problem_2d(n, precision, L, b))
+            trials.append((L, b, ms))
+            if best is None or ms < best[2]:
+                best = (L, b, ms)
+    default_ms = time_step(ctx, _problem_2d(n, precision))
+    rec = {"window_len": best[0], "lines_per_group": best[1], "ms": round(best[2], 4),
+           "default_ms": round(default_ms, 4), "trials": len(trials)}
+    if log:
+        log(f"tuned {key}: {rec}")
+    _CACHE[key] = rec
+    if cache_path:
+        disk = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                disk = json.load(fh)
+        disk[key] = rec
+        with open(cache_path, "w") as fh:
+            json.dump(disk, fh, indent=1, sort_keys=True)
+    return rec
