@@ -434,7 +434,9 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
         b.add_step(plans[i], states[i], dt, nu, p_out=pbuf[i], wall=walls[i])
     b.launch()
     torch.cuda.synchronize()
-    equal = all(torch.equal(states[i][a], plain[i][a]) for i in range(count) for a in range(2))
+    mism = [i for i in range(count) if not all(torch.equal(states[i][a], plain[i][a]) for a in range(2))]
+    equal = not mism
+    max_diff = max([float((states[i][a] - plain[i][a]).abs().max()) for i in mism for a in range(2)] + [0.0])
     fp32_err = None
     if ref_u is not None:
         errs = sorted(max(rel_l2(states[i][a], ref_u[i][a]) for a in range(2)) for i in range(count))
@@ -473,6 +475,7 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
         step_bytes -= 2 * n * n * 8        # no forcing arrays read
     out = {"instances": count, "points": pts, "groups": groups, "grouped_launches": launches,
            "batched_equals_plain_bitwise": bool(equal),
+           "instances_differing_from_plain": len(mism), "max_abs_diff_vs_plain": max_diff,
            "solves_per_s": {"plain_loop": round(count / t_plain, 1), "batched": round(count / t_batch, 1),
                             "batched_graph": round(count / t_graph, 1)},
            "ms_per_batch_step": {"plain_loop": round(1e3 * t_plain, 3), "batched": round(1e3 * t_batch, 3),
@@ -490,28 +493,31 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
 
 # ------------------------------------------------------------------ serving workload
 def run_serving(precision: str, lams, max_requests: int, window_s: float, plain_lams=()) -> dict:
-    """Poisson request streams at each rate: continuous batching against the
-    plain per-request path."""
+    """Poisson request streams at each rate on one server (plans and input
+    templates resident across rates): continuous batching, and the plain
+    per-request path on the same resident plans."""
     from paper_2606_06247_amd import serve
-    out = {}
+    streams = {}
     for lam in lams:
         count = int(min(max_requests, max(50, lam * window_s)))
-        reqs = serve.make_requests(lam, count, seed=40)
-        shapes = sorted({(r.dims, r.n) for r in reqs})
-        srv = serve.Server(precision, hbm_budget=200e9, max_batch=64, lanes=2)
-        srv.warm(shapes)
-        warm = [serve.Request(i, 0.0, r.kind, r.dims, r.n, r.seed) for i, r in enumerate(reqs[:16])]
-        srv.run(warm, realtime=False)
-        st = srv.run(reqs, realtime=True)
-        rec = {"offered_req_per_s": lam, "served": st}
+        streams[lam] = serve.make_requests(lam, count, seed=40)
+    shapes = sorted({(r.dims, r.n) for rs in streams.values() for r in rs})
+    srv = serve.Server(precision, hbm_budget=200e9, max_batch=64, lanes=2)
+    srv.warm(shapes)
+    warm = [serve.Request(i, 0.0, r.kind, r.dims, r.n, r.seed) for i, r in enumerate(streams[lams[0]][:32])]
+    srv.run(warm, realtime=False)
+    out = {"resident_plans_created": srv.stats["plans_created"], "shapes": len(shapes)}
+    for lam in lams:
+        st = srv.run(streams[lam], realtime=True)
+        rec = {"served": st}
         if lam in plain_lams:
-            reqs2 = serve.make_requests(lam, count, seed=40)
-            rec["plain_per_request"] = serve.run_plain(reqs2, precision, warm_shapes=shapes)
+            reqs2 = serve.make_requests(lam, len(streams[lam]), seed=40)
+            rec["plain_per_request"] = serve.run_plain(reqs2, srv)
         out[str(lam)] = rec
-        log(f"  lambda {lam}: {st['solves_per_s']} solves/s p50 {st['p50_ms']} ms p99 {st['p99_ms']} ms")
-        del srv
+        log(f"  lambda {lam}: {st['solves_per_s']} solves/s p50 {st['p50_ms']} ms p99 {st['p99_ms']} ms"
+            + (f"; plain p99 {rec['plain_per_request']['p99_ms']} ms" if lam in plain_lams else ""))
+    del srv
     return out
-
 
 
 def log(msg: str):

@@ -322,42 +322,52 @@ __device__ __forceinline__ void line_dft(Line<T> buf, const LinePlan &p, int lt,
   if (!active) {
     lt = 1 << 30;           // every index loop below starts past its bound
   }
+  // one Stockham call site (two passes for Bluestein) keeps the inlined code
+  // and its registers at those of a single transform
+  const int len = p.blue ? p.M : p.n;
+  const cpx<T> *chirp = static_cast<const cpx<T> *>(p.chirp);
+  const cpx<T> *filt = static_cast<const cpx<T> *>(p.filt);
   if (!p.blue) {
     if (conj_in) {
       for (int j = lt; j < p.n; j += TL) buf[j].i = -buf[j].i;
       __syncthreads();
     }
-    fft_stockham<T, BIG>(buf, p, p.n, lt, TL, active);
+  } else {
+    // a_j = x_j w_j (zero padded to M)
+    for (int j = lt; j < p.M; j += TL) {
+      cpx<T> v = {T(0), T(0)};
+      if (j < p.n) {
+        v = buf[j];
+        if (conj_in) v.i = -v.i;
+        v = cmul(v, chirp[j]);
+      }
+      buf[j] = v;
+    }
+    __syncthreads();
+  }
+  const int npass = p.blue ? 2 : 1;
+#pragma unroll 1
+  for (int pass = 0; pass < npass; ++pass) {
+    fft_stockham<T, BIG>(buf, p, len, lt, TL, active);
+    if (pass == 0 && p.blue) {
+      // pointwise product with the filter spectrum; conjugate for the inverse FFT
+      for (int j = lt; j < p.M; j += TL) buf[j] = cconj(cmul(buf[j], filt[j]));
+      __syncthreads();
+    }
+  }
+  if (!p.blue) {
     if (conj_out) {
       for (int j = lt; j < p.n; j += TL) buf[j].i = -buf[j].i;
       __syncthreads();
     }
-    return;
-  }
-  const cpx<T> *chirp = static_cast<const cpx<T> *>(p.chirp);
-  const cpx<T> *filt = static_cast<const cpx<T> *>(p.filt);
-  // a_j = x_j w_j (zero padded to M)
-  for (int j = lt; j < p.M; j += TL) {
-    cpx<T> v = {T(0), T(0)};
-    if (j < p.n) {
-      v = buf[j];
-      if (conj_in) v.i = -v.i;
-      v = cmul(v, chirp[j]);
+  } else {
+    for (int k = lt; k < p.n; k += TL) {
+      cpx<T> v = cmul(cconj(buf[k]), chirp[k]);
+      if (conj_out) v.i = -v.i;
+      buf[k] = v;
     }
-    buf[j] = v;
+    __syncthreads();
   }
-  __syncthreads();
-  fft_stockham<T, BIG>(buf, p, p.M, lt, TL, active);
-  // pointwise product with the filter spectrum; conjugate for the inverse FFT
-  for (int j = lt; j < p.M; j += TL) buf[j] = cconj(cmul(buf[j], filt[j]));
-  __syncthreads();
-  fft_stockham<T, BIG>(buf, p, p.M, lt, TL, active);
-  for (int k = lt; k < p.n; k += TL) {
-    cpx<T> v = cmul(cconj(buf[k]), chirp[k]);
-    if (conj_out) v.i = -v.i;
-    buf[k] = v;
-  }
-  __syncthreads();
 }
 
 }  // namespace fcsph

@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -248,27 +250,46 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
         bi[M - m] = -ci[m];
       }
     }
-    std::vector<LD> twr(M), twi(M);
-    for (int t = 0; t < M; ++t) {
-      const LD a = -2.0L * kPi * (LD)t / (LD)M;
-      twr[t] = cosl(a);
-      twi[t] = sinl(a);
+    // the O(M^2) long-double DFT of the filter is cached per (n, M): plans of
+    // the same line length (batches, served requests) reuse it
+    static std::mutex filt_mu;
+    static std::map<std::pair<int, int>, std::vector<LD>> filt_cache;
+    std::vector<LD> spec;
+    {
+      std::lock_guard<std::mutex> lock(filt_mu);
+      auto it = filt_cache.find({n, M});
+      if (it != filt_cache.end()) spec = it->second;
+    }
+    if (spec.empty()) {
+      std::vector<LD> twr(M), twi(M);
+      for (int t = 0; t < M; ++t) {
+        const LD a = -2.0L * kPi * (LD)t / (LD)M;
+        twr[t] = cosl(a);
+        twi[t] = sinl(a);
+      }
+      spec.assign(2 * (size_t)M, 0.0L);
+      for (int k = 0; k < M; ++k) {
+        LD sr = 0.0L, si = 0.0L;
+        long long idx = 0;
+        for (int m = 0; m < M; ++m) {
+          if (br[m] != 0.0L || bi[m] != 0.0L) {
+            sr += br[m] * twr[idx] - bi[m] * twi[idx];
+            si += br[m] * twi[idx] + bi[m] * twr[idx];
+          }
+          idx += k;
+          if (idx >= M) idx -= M;
+        }
+        spec[2 * (size_t)k] = sr / M;
+        spec[2 * (size_t)k + 1] = si / M;
+      }
+      std::lock_guard<std::mutex> lock(filt_mu);
+      filt_cache[{n, M}] = spec;
     }
     Upload uf;
     uf.data.resize((size_t)M * es);
     for (int k = 0; k < M; ++k) {
-      LD sr = 0.0L, si = 0.0L;
-      long long idx = 0;
-      for (int m = 0; m < M; ++m) {
-        if (br[m] != 0.0L || bi[m] != 0.0L) {
-          sr += br[m] * twr[idx] - bi[m] * twi[idx];
-          si += br[m] * twi[idx] + bi[m] * twr[idx];
-        }
-        idx += k;
-        if (idx >= M) idx -= M;
-      }
-      if (fp32) put_cpx<float>(uf.data, k, sr / M, si / M);
-      else put_cpx<double>(uf.data, k, sr / M, si / M);
+      if (fp32) put_cpx<float>(uf.data, k, spec[2 * (size_t)k], spec[2 * (size_t)k + 1]);
+      else put_cpx<double>(uf.data, k, spec[2 * (size_t)k], spec[2 * (size_t)k + 1]);
     }
     uf.dst = ws.take(uf.data.size());
     p.filt = uf.dst;
@@ -278,10 +299,10 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
 }
 
 // Workgroup line count for a plan and per-line buffer size.
-int pick_B(const LinePlan &p, bool fp32, int want) {
+int pick_B(const LinePlan &p, bool fp32, int want, int nbuf = 1) {
   const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
   int B = want;
-  while (B > 1 && ((size_t)B * padded_len(p.M, p.pad) * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
+  while (B > 1 && ((size_t)B * nbuf * padded_len(p.M, p.pad) * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
   return B;
 }
 
@@ -523,7 +544,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   }
   // operator line plans
   for (int a = 0; a < p->nd; ++a) {
-    const int minTL = (a == 0) ? 64 : (p->E[a] + 7) / 8;   // cols kernels keep E/TL <= 8 values
+    const int minTL = 64;
     if (!make_line_plan(p->E[a], f32, minTL, ws, up, p->op[a]) ||
         (f32 && !make_line_plan(p->E[a], false, minTL, ws, up, p->op64[a]))) {
       msg = "cannot plan a DFT of length " + std::to_string(p->E[a]);
@@ -759,7 +780,7 @@ ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
   c.line_axis = 1;
   c.inner_axis = 0;
   c.outer_axis = -1;
-  c.B = pick_B(c.plan, p->fp32, p->want_B);
+  c.B = pick_B(c.plan, p->fp32, p->want_B, cols_lines_per_column(mode));
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }
@@ -829,7 +850,7 @@ ColsArgs y_pass_args(fcsph_plan *p, int mode, int fc) {
   c.line_axis = 1;
   c.inner_axis = 0;
   c.outer_axis = 2;
-  c.B = pick_B(c.plan, p->fp32, p->want_B);
+  c.B = pick_B(c.plan, p->fp32, p->want_B, cols_lines_per_column(mode));
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }
@@ -849,7 +870,7 @@ ColsArgs z_pass_args(fcsph_plan *p, int mode) {
   c.line_axis = 2;
   c.inner_axis = 0;
   c.outer_axis = 1;
-  c.B = pick_B(c.plan, p->fp32, p->want_B);
+  c.B = pick_B(c.plan, p->fp32, p->want_B, cols_lines_per_column(mode));
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;
 }

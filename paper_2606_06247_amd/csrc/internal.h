@@ -286,7 +286,13 @@ struct KArg;
 template <typename A>
 struct KArg<A, false> {
   A a;
-  __device__ __forceinline__ const A &get() const { return a; }
+  // Read the fields through the kernel-argument segment pointer (this struct
+  // is the kernel's only argument, at offset 0), as the grouped variant reads
+  // its array: field loads then stay where they are used instead of the whole
+  // struct being held in registers (which made the line kernels spill).
+  __device__ __forceinline__ const A &get() const {
+    return *(const A *)__builtin_amdgcn_kernarg_segment_ptr();
+  }
 };
 template <typename A>
 struct KArg<A, true> {
@@ -336,6 +342,10 @@ inline hipError_t issue(KS ks, KG kg, const A &a, dim3 grid, dim3 block, size_t 
   hipLaunchKernelGGL(ks, grid, block, lds, s, KArg<A, false>{a});
   return hipGetLastError();
 }
+
+// LDS lines per column of the strided pass: OP and DIV keep a second line
+// (the forward spectrum / the divergence accumulator).
+inline int cols_lines_per_column(int mode) { return (mode == COLS_OP || mode == COLS_DIV) ? 2 : 1; }
 
 // launchers (kernels.hip); return hipError_t
 hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s);

@@ -297,11 +297,14 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 //   S(k) = sum_s R[s] exp(-2 pi i k_line s / E_line).
 __device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
   const double *W = a.st.W[q];
+#pragma unroll
   for (int s = 0; s < kSymW; ++s) R[s] = make_double2(0.0, 0.0);
   if (a.st.ndim == 2) {
     // W[(sy + R) * kSymW + (sx + R)]; line axis y, inner axis x
+#pragma unroll
     for (int sl = -kSymR; sl <= kSymR; ++sl) {
       double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 1
       for (int si = -kSymR; si <= kSymR; ++si) {
         const int li = (a.line_axis == 1) ? (sl + kSymR) * kSymW + (si + kSymR)
                                           : (si + kSymR) * kSymW + (sl + kSymR);
@@ -314,17 +317,19 @@ __device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int ki
       R[sl + kSymR] = acc;
     }
   } else {
-    // W[(sz + R) * kSymW^2 + (sy + R) * kSymW + (sx + R)]
-    int off[3];
+    // W[(sz + R) * kSymW^2 + (sy + R) * kSymW + (sx + R)]: index strides per axis
+    const int stl = a.line_axis == 0 ? 1 : a.line_axis == 1 ? kSymW : kSymW * kSymW;
+    const int sti = a.inner_axis == 0 ? 1 : a.inner_axis == 1 ? kSymW : kSymW * kSymW;
+    const int sto = a.outer_axis == 0 ? 1 : a.outer_axis == 1 ? kSymW : kSymW * kSymW;
+#pragma unroll
     for (int sl = -kSymR; sl <= kSymR; ++sl) {
       double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 1
       for (int si = -kSymR; si <= kSymR; ++si) {
         const double2 pi_ = phase(a.st.ph[a.inner_axis], kin, si);
+#pragma unroll 1
         for (int so = -kSymR; so <= kSymR; ++so) {
-          off[a.line_axis] = sl;
-          off[a.inner_axis] = si;
-          off[a.outer_axis] = so;
-          const double w = W[(off[2] + kSymR) * kSymW * kSymW + (off[1] + kSymR) * kSymW + (off[0] + kSymR)];
+          const double w = W[(sl + kSymR) * stl + (si + kSymR) * sti + (so + kSymR) * sto];
           if (w == 0.0) continue;
           const double2 p = zmul(pi_, phase(a.st.ph[a.outer_axis], kout, so));
           acc.x += w * p.x;
@@ -348,7 +353,6 @@ __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_
   return acc;
 }
 
-constexpr int kXMax = 8;   // spectrum values kept in registers per thread
 
 template <typename T>
 __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const cpx<T> *in,
@@ -420,71 +424,66 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
     line_dft<T>(buf, a.plan, lt, TL, inv, inv);
     cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][0]), c0, obase_out, a.nstore);
   } else if constexpr (MODE == COLS_OP) {
+    // pass 0: FC + forward DFT, kept in a second LDS line (xb); pass q + 1:
+    // symbol q times xb, inverse DFT, store.  One transform call site keeps
+    // the kernel's register footprint at that of a single transform.
+    Line<T> xb{smem + (size_t)(a.B + g) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
     const int f = blockIdx.y;
-    const cpx<T> *in = static_cast<const cpx<T> *>(a.in[f]);
-    cols_load<T>(a, smem, in, c0, obase_in, a.nload);
-    __syncthreads();
-    if (a.fc.on) {
-      cols_fc<T>(a, buf, lt, TL);
-      __syncthreads();
-    }
-    line_dft<T>(buf, a.plan, lt, TL, false, false);
-    cpx<T> X[kXMax];
-#pragma unroll
-    for (int m = 0; m < kXMax; ++m) {
-      const int k = lt + m * TL;
-      X[m] = k < E ? buf[k] : cpx<T>{T(0), T(0)};
-    }
-    for (int q = 0; q < a.nout; ++q) {
-      double2 R[kSymW];
-      sym_line_coeffs(a, a.sym[q], c < a.ninner ? c : 0, o, R);
-      __syncthreads();   // the previous output's store has finished reading buf
-#pragma unroll
-      for (int m = 0; m < kXMax; ++m) {
-        const int k = lt + m * TL;
-        if (k < E) {
-          const double2 sv = sym_eval(R, ph_line, k);
-          buf[k] = cmul(to_cpx<T>(sv.x, sv.y), X[m]);
+    for (int pass = 0; pass <= a.nout; ++pass) {
+      if (pass == 0) {
+        cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[f]), c0, obase_in, a.nload);
+        __syncthreads();
+        if (a.fc.on) {
+          cols_fc<T>(a, buf, lt, TL);
+          __syncthreads();
         }
-      }
-      __syncthreads();
-      line_dft<T>(buf, a.plan, lt, TL, true, true);
-      cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][q]), c0, obase_out, a.nstore);
-    }
-  } else {
-    // COLS_DIV: out = sum_f S_f DFT(FC(in_f)), one output
-    cpx<T> acc[kXMax];
-#pragma unroll
-    for (int m = 0; m < kXMax; ++m) acc[m] = {T(0), T(0)};
-    const int nin = a.st.ndim;
-    for (int f = 0; f < nin; ++f) {
-      __syncthreads();
-      cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[f]), c0, obase_in, a.nload);
-      __syncthreads();
-      if (a.fc.on) {
-        cols_fc<T>(a, buf, lt, TL);
+      } else {
+        double2 R[kSymW];
+        sym_line_coeffs(a, a.sym[pass - 1], c < a.ninner ? c : 0, o, R);
+        __syncthreads();   // the previous output's store has finished reading buf
+        for (int k = lt; k < E; k += TL) {
+          const double2 sv = sym_eval(R, ph_line, k);
+          buf[k] = cmul(to_cpx<T>(sv.x, sv.y), xb[k]);
+        }
         __syncthreads();
       }
-      line_dft<T>(buf, a.plan, lt, TL, false, false);
-      double2 R[kSymW];
-      sym_line_coeffs(a, a.sym[f], c < a.ninner ? c : 0, o, R);
-#pragma unroll
-      for (int m = 0; m < kXMax; ++m) {
-        const int k = lt + m * TL;
-        if (k < E) {
+      line_dft<T>(buf, a.plan, lt, TL, pass > 0, pass > 0);
+      if (pass == 0) {
+        for (int k = lt; k < E; k += TL) xb[k] = buf[k];
+      } else {
+        cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][pass - 1]), c0, obase_out, a.nstore);
+      }
+    }
+  } else {
+    // COLS_DIV: out = sum_f S_f DFT(FC(in_f)), one output; passes 0..nin-1
+    // transform input f and accumulate in a second LDS line (each thread owns
+    // its positions), the last pass inverts the sum
+    Line<T> acc{smem + (size_t)(a.B + g) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+    for (int k = lt; k < E; k += TL) acc[k] = {T(0), T(0)};
+    const int nin = a.st.ndim;
+    for (int pass = 0; pass <= nin; ++pass) {
+      __syncthreads();
+      if (pass < nin) {
+        cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[pass]), c0, obase_in, a.nload);
+        __syncthreads();
+        if (a.fc.on) {
+          cols_fc<T>(a, buf, lt, TL);
+          __syncthreads();
+        }
+      } else {
+        for (int k = lt; k < E; k += TL) buf[k] = acc[k];
+        __syncthreads();
+      }
+      line_dft<T>(buf, a.plan, lt, TL, pass == nin, pass == nin);
+      if (pass < nin) {
+        double2 R[kSymW];
+        sym_line_coeffs(a, a.sym[pass], c < a.ninner ? c : 0, o, R);
+        for (int k = lt; k < E; k += TL) {
           const double2 sv = sym_eval(R, ph_line, k);
-          acc[m] = cadd(acc[m], cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
+          acc[k] = cadd(acc[k], cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
         }
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kXMax; ++m) {
-      const int k = lt + m * TL;
-      if (k < E) buf[k] = acc[m];
-    }
-    __syncthreads();
-    line_dft<T>(buf, a.plan, lt, TL, true, true);
     cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[0][0]), c0, obase_out, a.nstore);
   }
 }
@@ -577,7 +576,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   }
   __syncthreads();
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
-  line_dft<T, true>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T>(buf, a.plan, lt, TL, cj, cj);
 
   // ---- results
   if (!a.inverse) {
@@ -651,44 +650,23 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
 template <typename T>
 __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArgs &a, int lt, int TL,
                                                    bool is_values) {
+  // extension / twiddle before, one transform, mode extraction after
   const int n = a.nline, L = a.plan.n;
   const bool qw = a.kind == TRIG_QWS || a.kind == TRIG_QWC;
-  if (qw) {
-    const cpx<T> *qtw = static_cast<const cpx<T> *>(a.qtw);
-    if (!is_values) {
-      // values at 0..N: zero the Dirichlet wall, extend, pre-twiddle
-      if (lt == 0) buf[a.kind == TRIG_QWS ? 0 : n - 1] = {T(0), T(0)};
-      const T sg = a.kind == TRIG_QWS ? T(1) : T(-1);
-      for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], sg);
-      __syncthreads();
-      for (int j = lt; j < L; j += TL) buf[j] = cmul(buf[j], qtw[j]);
-      __syncthreads();
-      line_dft<T, true>(buf, a.plan, lt, TL, false, false);
-      // F = 2i W (QWS), 2 W (QWC); position N holds no mode
-      for (int j = lt; j < n; j += TL) {
-        const cpx<T> w = buf[j];
-        buf[j] = j == n - 1 ? cpx<T>{T(0), T(0)}
-                            : (a.kind == TRIG_QWS ? cscale(cpi(w), T(2)) : cscale(w, T(2)));
-      }
-      __syncthreads();
-    } else {
-      // coefficients at 0..N-1: mirror to 2N-1-l, inverse DFT, post-twiddle
-      const T sg = a.kind == TRIG_QWS ? T(-1) : T(1);
-      for (int j = n - 1 + lt; j < L; j += TL) buf[j] = cscale(buf[L - 1 - j], sg);
-      __syncthreads();
-      line_dft<T, true>(buf, a.plan, lt, TL, true, true);
-      // y = -(i/2) R (QWS), R / 2 (QWC), R = exp(i pi j / 2N) IDFT; wall value 0
-      for (int j = lt; j < n; j += TL) {
-        const cpx<T> R = cmul(buf[j], cconj(qtw[j]));
-        const bool wall = a.kind == TRIG_QWS ? j == 0 : j == n - 1;
-        buf[j] = wall ? cpx<T>{T(0), T(0)}
-                      : (a.kind == TRIG_QWS ? cscale(cmi(R), T(0.5)) : cscale(R, T(0.5)));
-      }
-      __syncthreads();
-    }
-    return;
-  }
-  if (a.kind == TRIG_DCT1) {
+  const bool qws = a.kind == TRIG_QWS;
+  const cpx<T> *qtw = static_cast<const cpx<T> *>(a.qtw);
+  if (qw && !is_values) {
+    // values at 0..N: zero the Dirichlet wall, extend, pre-twiddle
+    if (lt == 0) buf[qws ? 0 : n - 1] = {T(0), T(0)};
+    const T sg = qws ? T(1) : T(-1);
+    for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], sg);
+    __syncthreads();
+    for (int j = lt; j < L; j += TL) buf[j] = cmul(buf[j], qtw[j]);
+  } else if (qw) {
+    // coefficients at 0..N-1: mirror to 2N-1-l
+    const T sg = qws ? T(-1) : T(1);
+    for (int j = n - 1 + lt; j < L; j += TL) buf[j] = cscale(buf[L - 1 - j], sg);
+  } else if (a.kind == TRIG_DCT1) {
     for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
   } else if (a.kind == TRIG_DST1) {
     // odd extension: positions 0 and n-1 are zero, j > n-1 holds -buf[L-j]
@@ -699,9 +677,24 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
     for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));
   }
   __syncthreads();
-  const bool cj = a.kind == TRIG_DFT && is_values;
-  line_dft<T, true>(buf, a.plan, lt, TL, cj, cj);
-  if (a.kind == TRIG_DST1) {
+  const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
+  line_dft<T>(buf, a.plan, lt, TL, cj, cj);
+  if (qw && !is_values) {
+    // F = 2i W (QWS), 2 W (QWC); position N holds no mode
+    for (int j = lt; j < n; j += TL) {
+      const cpx<T> w = buf[j];
+      buf[j] = j == n - 1 ? cpx<T>{T(0), T(0)} : (qws ? cscale(cpi(w), T(2)) : cscale(w, T(2)));
+    }
+    __syncthreads();
+  } else if (qw) {
+    // y = -(i/2) R (QWS), R / 2 (QWC), R = exp(i pi j / 2N) IDFT; wall value 0
+    for (int j = lt; j < n; j += TL) {
+      const cpx<T> R = cmul(buf[j], cconj(qtw[j]));
+      const bool wall = qws ? j == 0 : j == n - 1;
+      buf[j] = wall ? cpx<T>{T(0), T(0)} : (qws ? cscale(cmi(R), T(0.5)) : cscale(R, T(0.5)));
+    }
+    __syncthreads();
+  } else if (a.kind == TRIG_DST1) {
     // the DST-I of the complex line is i Z
     for (int j = lt; j < n; j += TL) buf[j] = cpi(buf[j]);
     if (is_values && lt == 0) {
@@ -881,7 +874,8 @@ static hipError_t cols_dispatch(const ColsArgs &a, dim3 grid, dim3 block, size_t
 hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s) {
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const dim3 grid(npanel * a.nouter, ngrid_y), block(a.B * a.plan.TL);
-  const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
+  const size_t lds = lds_bytes(a.B * cols_lines_per_column(a.mode), a.ldsM, fp32);
+  if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
   return fp32 ? cols_dispatch<float>(a, grid, block, lds, s) : cols_dispatch<double>(a, grid, block, lds, s);
 }
 

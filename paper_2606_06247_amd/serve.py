@@ -81,11 +81,11 @@ class Server:
         self.max_batch = max_batch
         self.dt, self.nu = dt, nu
         self.streams = [torch.cuda.Stream() for _ in range(lanes)]
-        self.ctxs = [api.Context(0, s.cuda_stream) for s in self.streams]
+        self.ctxs = [api.Context(0, s) for s in self.streams]
         self.batches = [api.Batch(c, max_batch) for c in self.ctxs]
         self.inflight = [None] * lanes          # (event, [(request, plan instance, bufs)])
         self.pool: dict = {}                    # shape key -> idle plans
-        self.busy_plans = 0
+        self.count: dict = {}                   # shape key -> plan instances
         self.used = 0.0                         # bytes: plan workspaces + request buffers in flight
         self.templates: dict = {}
         self.plan_ctx = api.Context(0)
@@ -114,10 +114,12 @@ class Server:
         return plan
 
     def warm(self, shapes):
-        """Create one resident plan and the input template per shape."""
+        """Create the resident plans (one per lane) and the input template per shape."""
         for dims, n in shapes:
             self._template(dims, n)
-            self.pool.setdefault((dims, n), []).append(self._new_plan(dims, n))
+            for _ in range(len(self.streams)):
+                self.pool.setdefault((dims, n), []).append(self._new_plan(dims, n))
+            self.count[(dims, n)] = len(self.streams)
 
     def _request_bytes(self, r: Request) -> int:
         pts = r.n ** r.dims
@@ -130,9 +132,14 @@ class Server:
             if self.used + need > self.budget:
                 return None
             return idle.pop()
+        # a new instance only while a shape has fewer than one per lane
+        # (otherwise the request waits for an instance to return)
+        if self.count.get(self._key(r), 0) >= len(self.streams):
+            return None
         ws = api.workspace_bytes(problem_for(r.dims, r.n, self.precision, self.op_eval))
         if self.used + ws + need > self.budget:
             return None
+        self.count[self._key(r)] = self.count.get(self._key(r), 0) + 1
         return self._new_plan(r.dims, r.n)
 
     def _inputs(self, r: Request):
@@ -183,6 +190,7 @@ class Server:
         throughput and latency statistics."""
         import torch
         torch.cuda.synchronize()
+        self.stats.update(admitted=0, max_queue=0, batches=0)
         pending = deque(sorted(requests, key=lambda r: r.t_arrival))
         queue: deque = deque()
         if not realtime:                     # burst: every request arrives at once
@@ -232,13 +240,12 @@ class Server:
                 "max_queue": self.stats["max_queue"], "hbm_used_GB": round(self.used / 1e9, 2)}
 
 
-def run_plain(requests: list, precision: str = "fp64", op_eval: str = "fft_window", realtime: bool = True,
-              dt: float = 1e-4, nu: float = 1e-3, warm_shapes=()) -> dict:
-    """The plain per-request path at the same arrival times: one request at a
-    time on resident plans, each call synchronised before the next."""
+def run_plain(requests: list, srv: Server, realtime: bool = True) -> dict:
+    """The plain per-request path at the same arrival times on the server's
+    resident plans: one request at a time, each call synchronised before the
+    next."""
     import torch
-    srv = Server(precision, op_eval=op_eval, lanes=1, max_batch=1, dt=dt, nu=nu)
-    srv.warm(warm_shapes)
+    dt, nu = srv.dt, srv.nu
     pending = deque(sorted(requests, key=lambda r: r.t_arrival))
     torch.cuda.synchronize()
     t0 = time.perf_counter()

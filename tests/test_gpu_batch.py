@@ -157,3 +157,35 @@ def test_batch_rejects_repeated_plan(ctx):
     b.add_ppe(plan, rhs)
     with pytest.raises(api.FcsphError):
         b.add_ppe(plan, rhs)
+
+
+def test_batch_tuned_schedules_bitwise(ctx):
+    """Larger lattices, random walls, explicit window lengths and one line per
+    workgroup (the schedules the tuner picks): batched == plain bitwise."""
+    import torch
+    from paper_2606_06247_amd import api
+    rng = np.random.default_rng(31)
+    plans, plain, batched, walls = [], [], [], []
+    for i, (n, L, lines) in enumerate([(192, 200, 1), (192, 200, 1), (256, 270, 2), (384, 392, 1), (256, 0, 0)]):
+        s = spec((n, n), (True, True), vel=random_walls(rng))
+        prob = problem(s, op_eval="fft_window")
+        prob.window_len = (L, L) if L else ()
+        prob.lines_per_group = lines
+        plans.append(api.Plan(ctx, prob))
+        u = make_inputs(s, 500 + 2 * i)
+        plain.append([to_dev(c) for c in u])
+        batched.append([to_dev(c) for c in u])
+        walls.append([to_dev(c) for c in u])
+    pp = [torch.empty_like(x[0]) for x in plain]
+    pb = [torch.empty_like(x[0]) for x in plain]
+    for i, plan in enumerate(plans):
+        plan.project_step(plain[i], 1e-4, 1e-3, p_out=pp[i], wall=walls[i])
+    b = api.Batch(ctx, len(plans))
+    for i, plan in enumerate(plans):
+        b.add_step(plan, batched[i], 1e-4, 1e-3, p_out=pb[i], wall=walls[i])
+    b.launch()
+    torch.cuda.synchronize()
+    for i in range(len(plans)):
+        for a in range(2):
+            assert torch.equal(plain[i][a], batched[i][a]), (i, a, float((plain[i][a] - batched[i][a]).abs().max()))
+        assert torch.equal(pp[i], pb[i]), i
