@@ -695,12 +695,10 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
     }
     __syncthreads();
   } else if (a.kind == TRIG_DST1) {
-    // the DST-I of the complex line is i Z
-    for (int j = lt; j < n; j += TL) buf[j] = cpi(buf[j]);
-    if (is_values && lt == 0) {
-      buf[0] = {T(0), T(0)};
-      buf[n - 1] = {T(0), T(0)};
-    }
+    // the DST-I of the complex line is i Z; wall values are zero (each
+    // position written by the thread that owns it)
+    for (int j = lt; j < n; j += TL)
+      buf[j] = (is_values && (j == 0 || j == n - 1)) ? cpx<T>{T(0), T(0)} : cpi(buf[j]);
     __syncthreads();
   }
 }
