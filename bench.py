@@ -502,7 +502,7 @@ def run_serving(precision: str, lams, max_requests: int, window_s: float, plain_
         count = int(min(max_requests, max(50, lam * window_s)))
         streams[lam] = serve.make_requests(lam, count, seed=40)
     shapes = sorted({(r.dims, r.n) for rs in streams.values() for r in rs})
-    srv = serve.Server(precision, hbm_budget=200e9, max_batch=64, lanes=2)
+    srv = serve.Server(precision, hbm_budget=200e9, max_batch=16, lanes=4)
     srv.warm(shapes)
     warm = [serve.Request(i, 0.0, r.kind, r.dims, r.n, r.seed) for i, r in enumerate(streams[lams[0]][:32])]
     srv.run(warm, realtime=False)
@@ -635,7 +635,7 @@ def main() -> int:
                 "workload": "Poisson arrivals; 50% projection steps / 50% PPE solves; 75% 2D n ~ logU(64, 1024), "
                             "25% 3D channel n ~ logU(64, 192), sizes in multiples of 16; HBM budget 200 GB; "
                             f"at most {args.serve_requests} requests or {args.serve_window} s of arrivals per rate; "
-                            "2 lanes, up to 64 requests per batch",
+                            "4 lanes, batches of one class: up to 16 2D or 2 3D requests",
                 "rates": run_serving(prec, (50, 100, 200, 500, 1000, 2000), args.serve_requests, args.serve_window,
                                      plain_lams=(50, 500, 2000))}
         out["variants"] = var

@@ -73,12 +73,14 @@ def problem_for(dims: int, n: int, precision: str, op_eval: str = "fft_window") 
 
 
 class Server:
-    def __init__(self, precision: str = "fp64", hbm_budget: float = 200e9, max_batch: int = 64,
-                 lanes: int = 2, op_eval: str = "fft_window", dt: float = 1e-4, nu: float = 1e-3):
+    def __init__(self, precision: str = "fp64", hbm_budget: float = 200e9, max_batch: int = 16,
+                 lanes: int = 4, op_eval: str = "fft_window", dt: float = 1e-4, nu: float = 1e-3,
+                 max_batch_3d: int = 2):
         import torch
         self.precision, self.op_eval = precision, op_eval
         self.budget = hbm_budget
         self.max_batch = max_batch
+        self.max_batch_3d = max(1, min(max_batch_3d, max_batch))
         self.dt, self.nu = dt, nu
         self.streams = [torch.cuda.Stream() for _ in range(lanes)]
         self.ctxs = [api.Context(0, s) for s in self.streams]
@@ -211,9 +213,14 @@ class Server:
             if free and queue:
                 lane = free[0]
                 work, skipped = [], deque()
-                with torch.cuda.stream(self.streams[lane]):     # inputs ordered before the lane's batch
-                    while queue and len(work) < self.max_batch:
+                cls = queue[0].dims                             # batches of one class (2D or 3D): a
+                limit = self.max_batch if cls == 2 else self.max_batch_3d   # large 3D solve does not
+                with torch.cuda.stream(self.streams[lane]):     # hold small ones
+                    while queue and len(work) < limit:
                         r = queue.popleft()
+                        if r.dims != cls:
+                            skipped.append(r)
+                            continue
                         plan = self._acquire(r)
                         if plan is None:
                             skipped.append(r)
