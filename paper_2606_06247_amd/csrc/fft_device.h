@@ -238,9 +238,10 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
     if (active && j < NR) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NR];
-      // radix <= 4: one twiddle per butterfly, loaded before the barrier, its
-      // powers formed by multiplication; larger radices load each twiddle
-      if constexpr (R <= 4) w1[b] = tw[(j % Ns) * tstride];
+      // radix <= 8: one twiddle per butterfly, loaded before the barrier (its
+      // latency hides behind the barrier), its powers formed by products of
+      // depth <= 3; larger radices load each twiddle
+      if constexpr (R <= 8) w1[b] = tw[(j % Ns) * tstride];
     }
   }
   __syncthreads();
@@ -258,6 +259,19 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
             t = cmul(t, w1[b]);
             v[b][r] = cmul(v[b][r], t);
           }
+        } else if constexpr (R <= 8) {
+          // w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, w^{4+q} = w^4 w^q
+          const cpx<T> t1 = w1[b];
+          const cpx<T> t2 = cmul(t1, t1);
+          const cpx<T> t3 = cmul(t2, t1);
+          const cpx<T> t4 = cmul(t2, t2);
+          v[b][1] = cmul(v[b][1], t1);
+          v[b][2] = cmul(v[b][2], t2);
+          v[b][3] = cmul(v[b][3], t3);
+          v[b][4] = cmul(v[b][4], t4);
+          if constexpr (R > 5) v[b][5] = cmul(v[b][5], cmul(t4, t1));
+          if constexpr (R > 6) v[b][6] = cmul(v[b][6], cmul(t4, t2));
+          if constexpr (R > 7) v[b][7] = cmul(v[b][7], cmul(t4, t3));
         } else {
 #pragma unroll
           for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * tstride]);
