@@ -204,9 +204,10 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
   tl = (tl + 63) / 64 * 64;
   if (tl > kMaxThreads) return false;
   p.TL = tl;
-  // LDS padding: measured to halve the bank conflicts of power-of-two work
-  // lengths and to double them for the mixed-radix Bluestein lengths
-  p.pad = (M & (M - 1)) == 0 ? 4 : 0;
+  // LDS padding (one slot every 16 elements): a sweep of 0..5 on the 1024^2
+  // step put 3..5 ahead of none by 2-4 % (power-of-two Bluestein lengths gain
+  // most), so it is on for every length
+  p.pad = 4;
   if (const char *e = getenv("FCSPH_LDS_PAD")) p.pad = atoi(e) == 0 ? 0 : (atoi(e) < 0 ? p.pad : atoi(e));
   const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
   // twiddles exp(-2 pi i t / M)

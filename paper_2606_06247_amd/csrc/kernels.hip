@@ -296,23 +296,28 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 // operator q at fixed wavenumbers of the transverse axes:
 //   S(k) = sum_s R[s] exp(-2 pi i k_line s / E_line).
 __device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
+  // R[sl + kSymR] = sum over the other offsets of the tap weight times the
+  // phases of the other axes' wavenumbers.  All loads are independent and
+  // issued up front (no branches on loaded values): the phases of the inner
+  // (and outer) wavenumber once, the tap weights (uniform across the
+  // workgroup) as one batch.
   const double *W = a.st.W[q];
+  double2 pin[kSymR + 1];
 #pragma unroll
-  for (int s = 0; s < kSymW; ++s) R[s] = make_double2(0.0, 0.0);
+  for (int s = 0; s <= kSymR; ++s) pin[s] = a.st.ph[a.inner_axis][(size_t)kin * (kSymR + 1) + s];
   if (a.st.ndim == 2) {
-    // W[(sy + R) * kSymW + (sx + R)]; line axis y, inner axis x
+    // W[(sy + R) * kSymW + (sx + R)]; line axis y, inner axis x (or the reverse)
+    const int stl = a.line_axis == 1 ? kSymW : 1;
+    const int sti = a.line_axis == 1 ? 1 : kSymW;
 #pragma unroll
     for (int sl = -kSymR; sl <= kSymR; ++sl) {
       double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 1
+#pragma unroll
       for (int si = -kSymR; si <= kSymR; ++si) {
-        const int li = (a.line_axis == 1) ? (sl + kSymR) * kSymW + (si + kSymR)
-                                          : (si + kSymR) * kSymW + (sl + kSymR);
-        const double w = W[li];
-        if (w == 0.0) continue;
-        const double2 p = phase(a.st.ph[a.inner_axis], kin, si);
+        const double w = W[(sl + kSymR) * stl + (si + kSymR) * sti];
+        const double2 p = pin[si < 0 ? -si : si];
         acc.x += w * p.x;
-        acc.y += w * p.y;
+        acc.y += w * (si < 0 ? -p.y : p.y);
       }
       R[sl + kSymR] = acc;
     }
@@ -322,33 +327,42 @@ __device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int ki
     const int sti = a.inner_axis == 0 ? 1 : a.inner_axis == 1 ? kSymW : kSymW * kSymW;
     const int sto = a.outer_axis == 0 ? 1 : a.outer_axis == 1 ? kSymW : kSymW * kSymW;
 #pragma unroll
-    for (int sl = -kSymR; sl <= kSymR; ++sl) {
-      double2 acc = make_double2(0.0, 0.0);
+    for (int s = 0; s < kSymW; ++s) R[s] = make_double2(0.0, 0.0);
+    const double2 *pho = a.st.ph[a.outer_axis] + (size_t)kout * (kSymR + 1);
 #pragma unroll 1
+    for (int so = -kSymR; so <= kSymR; ++so) {
+      double2 po = pho[so < 0 ? -so : so];
+      if (so < 0) po.y = -po.y;
+      const double *Wo = W + (so + kSymR) * sto;
+#pragma unroll
       for (int si = -kSymR; si <= kSymR; ++si) {
-        const double2 pi_ = phase(a.st.ph[a.inner_axis], kin, si);
-#pragma unroll 1
-        for (int so = -kSymR; so <= kSymR; ++so) {
-          const double w = W[(sl + kSymR) * stl + (si + kSymR) * sti + (so + kSymR) * sto];
-          if (w == 0.0) continue;
-          const double2 p = zmul(pi_, phase(a.st.ph[a.outer_axis], kout, so));
-          acc.x += w * p.x;
-          acc.y += w * p.y;
+        double2 pi_ = pin[si < 0 ? -si : si];
+        if (si < 0) pi_.y = -pi_.y;
+        const double2 p = zmul(pi_, po);
+#pragma unroll
+        for (int sl = -kSymR; sl <= kSymR; ++sl) {
+          const double w = Wo[(sl + kSymR) * stl + (si + kSymR) * sti];
+          R[sl + kSymR].x += w * p.x;
+          R[sl + kSymR].y += w * p.y;
         }
       }
-      R[sl + kSymR] = acc;
     }
   }
 }
 
 __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
+  // exp(-2 pi i k s / E) for s = 1 from the table, s = 2, 3 by products
+  double2 p[kSymR + 1];
+  p[1] = ph_line[(size_t)k * (kSymR + 1) + 1];
+#pragma unroll
+  for (int s = 2; s <= kSymR; ++s) p[s] = zmul(p[s - 1], p[1]);
   double2 acc = R[kSymR];
+#pragma unroll
   for (int s = 1; s <= kSymR; ++s) {
-    const double2 p = ph_line[(size_t)k * (kSymR + 1) + s];   // exp(-2 pi i k s / E)
     const double2 rp = R[kSymR + s], rm = R[kSymR - s];
     // rp * p + rm * conj(p)
-    acc.x += (rp.x + rm.x) * p.x - (rp.y - rm.y) * p.y;
-    acc.y += (rp.x - rm.x) * p.y + (rp.y + rm.y) * p.x;
+    acc.x += (rp.x + rm.x) * p[s].x - (rp.y - rm.y) * p[s].y;
+    acc.y += (rp.x - rm.x) * p[s].y + (rp.y + rm.y) * p[s].x;
   }
   return acc;
 }
