@@ -407,6 +407,7 @@ struct fcsph_plan {
   void *coef = nullptr;         // PPE coefficient rows
   int cpitch = 0;
   double *ext_scratch = nullptr;  // intermediate of a multi-axis FC extension
+  void *edge[3] = {nullptr, nullptr, nullptr};   // FP32 plans: FP64 boundary-row x spectra per field
   bool direct = false;            // operators as direct tap sums
   double wd2[3][kSymW * kSymW] = {};   // 2D dense tap weights (grad x, grad y, lap)
   double *ghx[3] = {}, *ghy[3] = {};    // FC ghost values of up to 3 direct-pass inputs
@@ -670,7 +671,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   const size_t sb64 = p->spec_elems * sizeof(cpx<double>);   // also holds the FP64 divergence pass
   for (int i = 0; i < 3; ++i) p->S[i] = ws.take(sb64);
   const int nO = p->nd == 2 ? 6 : 12;
-  for (int i = 0; i < nO; ++i) p->O[i] = ws.take(i == 0 ? sb64 : sb);
+  for (int i = 0; i < nO; ++i) p->O[i] = ws.take(i < 3 ? sb64 : sb);
   if (p->nd == 3)
     for (int i = 0; i < 3; ++i) p->Y[i] = ws.take(sb64);
   for (int a = 0; a < p->nd; ++a) p->ustar[a] = (double *)ws.take(P * sizeof(double));
@@ -679,6 +680,9 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->cpitch = p->trig_kind[0] == TRIG_DFT ? p->ncoef[0] : (std::max(p->ncoef[0], 1) + 1) / 2;
   p->coef = ws.take((size_t)p->cpitch * rows * ce);
   p->ext_scratch = (double *)ws.take((size_t)p->Efc[0] * p->Efc[1] * p->Efc[2] * sizeof(double));
+  if (p->fp32 && p->walled[1])
+    for (int i = 0; i < 3; ++i)
+      p->edge[i] = ws.take((size_t)2 * p->n[2] * d->fc_d * p->H * sizeof(double2));
   for (int i = 0; i < 3; ++i) {
     p->ghx[i] = (double *)ws.take((size_t)p->n[1] * p->n[2] * 2 * kSymR * sizeof(double));
     p->ghy[i] = (double *)ws.take((size_t)2 * kSymR * (p->n[0] + 2 * kSymR) * p->n[2] * sizeof(double));
@@ -791,6 +795,47 @@ hipError_t cols_launch(fcsph_plan *p, const ColsArgs &c, int gy, const char *nam
   return launch_cols(c, gy, p->fp32, p->ctx->stream);
 }
 
+// FP32 plans: FP64 x spectra of the fc_d first and fc_d last rows of every
+// z plane of field f (FC_x fused as in the x pass), the FP64 inputs of FC_y.
+hipError_t edge_fwd(fcsph_plan *p, const double *f, int fc, void *edge) {
+  const int d = p->d.fc_d, nz = p->n[2], rows = nz * d;
+  for (int h = 0; h < 2; ++h) {
+    RowsFwdArgs a{};
+    a.plan = p->op64[0];
+    a.nlines = (rows + 1) / 2;
+    a.nx = p->n[0];
+    a.E = p->E[0];
+    a.H = p->H;
+    a.fc = walls_for(p, 0, fc);
+    a.inA = f + (h ? (size_t)(p->n[1] - d) * p->n[0] : 0);
+    a.nB = rows / 2;
+    a.map_per = d;
+    a.map_plane = (long)p->n[1] * p->n[0];
+    a.outA = (double2 *)edge + (size_t)h * rows * p->H;
+    a.outB = (double2 *)a.outA + p->H;
+    a.ostrideA = a.ostrideB = 2L * p->H;
+    a.B = pick_B(a.plan, false, p->want_B);
+    a.ldsM = padded_len(a.plan.M, a.plan.pad);
+    LaunchTimer t(p->ctx, "rows_fwd_edge");
+    hipError_t e = launch_rows_fwd(a, false, p->ctx->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Attach FP64 boundary rows of nf fields to a strided pass that applies FC
+// along y (FP32 plans only; FP64 plans read the line's own values).
+hipError_t set_edges(fcsph_plan *p, ColsArgs &c, int nf, const double *const *fields, int fc) {
+  for (int f = 0; f < 3; ++f) c.edge[f] = nullptr;
+  if (!p->fp32 || !p->edge[0] || !c.fc.on || c.line_axis != 1) return hipSuccess;
+  for (int f = 0; f < nf; ++f) {
+    hipError_t e = edge_fwd(p, fields[f], fc, p->edge[f]);
+    if (e != hipSuccess) return e;
+    c.edge[f] = (const double2 *)p->edge[f];
+  }
+  return hipSuccess;
+}
+
 hipError_t x_inv_store(fcsph_plan *p, const void *spec0, const void *spec1, void *out0, void *out1,
                        bool out_double, double scale) {
   RowsInvArgs a{};
@@ -877,8 +922,10 @@ ColsArgs z_pass_args(fcsph_plan *p, int mode) {
 }
 
 // y forward of nf spectra (FC along y with the field class's walls)
-hipError_t y_fwd(fcsph_plan *p, int nf, void *const *in, void *const *out, int fc) {
+hipError_t y_fwd(fcsph_plan *p, int nf, void *const *in, void *const *out, int fc, const double *const *fields) {
   ColsArgs c = y_pass_args(p, COLS_FWD, fc);
+  hipError_t e = set_edges(p, c, nf, fields, fc);
+  if (e != hipSuccess) return e;
   for (int f = 0; f < nf; ++f) {
     c.in[f] = in[f];
     c.out[f][0] = out[f];
@@ -1278,7 +1325,7 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
   fcsph_status st = FCSPH_OK;
   if (p->nd == 3) {
     if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "grad x", st)) return st;
-    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc), "grad y", st)) return st;
+    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc, &f), "grad y", st)) return st;
     ColsArgs c = z_pass_args(p, COLS_OP);
     c.in[0] = p->Y[0];
     for (int q = 0; q < 3; ++q) {
@@ -1302,6 +1349,7 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
   }
   if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "grad x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, fc);
+  if (!chk(p, set_edges(p, c, 1, &f, fc), "grad edges", st)) return st;
   c.in[0] = p->S[0];
   c.out[0][0] = p->O[0];
   c.out[0][1] = p->O[1];
@@ -1319,7 +1367,7 @@ fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *la
   fcsph_status st = FCSPH_OK;
   if (p->nd == 3) {
     if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
-    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc), "lap y", st)) return st;
+    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc, &f), "lap y", st)) return st;
     ColsArgs c = z_pass_args(p, COLS_OP);
     c.in[0] = p->Y[0];
     c.out[0][0] = p->O[0];
@@ -1339,6 +1387,7 @@ fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *la
   }
   if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, fc);
+  if (!chk(p, set_edges(p, c, 1, &f, fc), "lap edges", st)) return st;
   c.in[0] = p->S[0];
   c.out[0][0] = p->O[0];
   c.nout = 1;
@@ -1352,7 +1401,7 @@ static fcsph_status div3_impl(fcsph_plan *p, const double *const *u, void *out, 
   fcsph_status st = FCSPH_OK;
   if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
   if (!chk(p, x_fwd_single(p, u[2], FCSPH_FIELD_VELOCITY, p->S[2]), "div x", st)) return st;
-  if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY), "div y", st)) return st;
+  if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY, u), "div y", st)) return st;
   ColsArgs c = z_pass_args(p, COLS_DIV);
   for (int f = 0; f < 3; ++f) {
     c.in[f] = p->Y[f];
@@ -1381,6 +1430,10 @@ static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, 
   }
   if (!chk(p, x_fwd_pair(p, u0, u1, FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
   ColsArgs c = cols_base(p, COLS_DIV, FCSPH_FIELD_VELOCITY);
+  {
+    const double *uu[2] = {u0, u1};
+    if (!chk(p, set_edges(p, c, 2, uu, FCSPH_FIELD_VELOCITY), "div edges", st)) return st;
+  }
   c.in[0] = p->S[0];
   c.in[1] = p->S[1];
   c.out[0][0] = p->O[0];
@@ -1422,7 +1475,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     // A: 12 derivatives of (u, v, w), fused u*
     if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "step3 A x", st)) return st;
     if (!chk(p, x_fwd_single(p, u[2], FCSPH_FIELD_VELOCITY, p->S[2]), "step3 A x", st)) return st;
-    if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY), "step3 A y", st)) return st;
+    if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY, u), "step3 A y", st)) return st;
     ColsArgs c = z_pass_args(p, COLS_OP);
     for (int f = 0; f < 3; ++f) {
       c.in[f] = p->Y[f];
@@ -1473,9 +1526,11 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     double *phi = p_out ? p_out : p->phi;
     st = run_ppe(p, p->rhs, phi);
     if (st != FCSPH_OK) return st;
-    // D
+    // D (FP64 transforms in both forms, as in 2D)
+    Fp64Passes g64(p);
+    const bool fd = p->fp32;
     if (!chk(p, x_fwd_single(p, phi, FCSPH_FIELD_PRESSURE, p->S[0]), "step3 D x", st)) return st;
-    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], FCSPH_FIELD_PRESSURE), "step3 D y", st)) return st;
+    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], FCSPH_FIELD_PRESSURE, &phi), "step3 D y", st)) return st;
     ColsArgs cd = z_pass_args(p, COLS_OP);
     cd.in[0] = p->Y[0];
     for (int q = 0; q < 3; ++q) {
@@ -1486,12 +1541,14 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     if (!chk(p, cols_launch(p, cd, 1, "cols_z_op_step_d"), "step3 D z", st)) return st;
     if (!chk(p, y_inv(p, 3, &p->O[0]), "step3 D y inv", st)) return st;
     RowsInvArgs rd = r;
+    rd.plan = p->op[0];
+    rd.ldsM = padded_len(rd.plan.M, rd.plan.pad);
     rd.spec[0] = p->O[0];
     rd.spec[1] = p->O[1];
     rd.spec[2] = p->O[2];
     {
       LaunchTimer t(p->ctx, "rows_inv_step_d3");
-      if (!chk(p, launch_rows_inv(rd, EPI_STEP_D3, f32, s), "step3 D x inv", st)) return st;
+      if (!chk(p, launch_rows_inv(rd, EPI_STEP_D3, fd, s), "step3 D x inv", st)) return st;
     }
     return FCSPH_OK;
   }
@@ -1527,6 +1584,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   // A: u* = u - dt [(u.grad)u - nu lap u - f], Dirichlet walls <- wall data
   if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "step A x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, FCSPH_FIELD_VELOCITY);
+  if (!chk(p, set_edges(p, c, 2, u, FCSPH_FIELD_VELOCITY), "step A edges", st)) return st;
   c.in[0] = p->S[0];
   c.in[1] = p->S[1];
   c.out[0][0] = p->O[0];
@@ -1585,9 +1643,17 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   double *phi = p_out ? p_out : p->phi;
   st = run_ppe(p, p->rhs, phi);
   if (st != FCSPH_OK) return st;
-  // D: u = u* - dt/rho grad phi, walls reset
+  // D: u = u* - dt/rho grad phi, walls reset; FP64 transforms in both forms
+  // (the projection cancels the irrotational part of u*, so FP32 rounding
+  // relative to |grad phi| would dominate the result)
+  Fp64Passes g64(p);
+  const bool fd = p->fp32;
   if (!chk(p, x_fwd_single(p, phi, FCSPH_FIELD_PRESSURE, p->S[0]), "step D x", st)) return st;
   ColsArgs cd = cols_base(p, COLS_OP, FCSPH_FIELD_PRESSURE);
+  {
+    const double *ph = phi;
+    if (!chk(p, set_edges(p, cd, 1, &ph, FCSPH_FIELD_PRESSURE), "step D edges", st)) return st;
+  }
   cd.in[0] = p->S[0];
   cd.out[0][0] = p->O[0];
   cd.out[0][1] = p->O[1];
@@ -1596,14 +1662,16 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   cd.sym[1] = SYM_GY;
   if (!chk(p, cols_launch(p, cd, 1, "cols_op_step_d"), "step D y", st)) return st;
   RowsInvArgs rd = r;
+  rd.plan = p->op[0];
+  rd.ldsM = padded_len(rd.plan.M, rd.plan.pad);
   rd.spec[0] = p->O[0];
   rd.spec[1] = p->O[1];
-  rd.B = pick_B(rd.plan, f32, p->want_B);
+  rd.B = pick_B(rd.plan, fd, p->want_B);
   rd.unew[0] = u[0];
   rd.unew[1] = u[1];
   {
     LaunchTimer t(p->ctx, "rows_inv_step_d");
-    if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, f32, s), "step D x inv", st)) return st;
+    if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, fd, s), "step D x inv", st)) return st;
   }
   return FCSPH_OK;
 }
@@ -1688,7 +1756,7 @@ extern "C" {
 
 // Per item: at most kBatchMaxLaunches launches of at most kBatchMaxArgs bytes,
 // plus the 256-byte alignment of each group's array.
-constexpr int kBatchMaxLaunches = 32;
+constexpr int kBatchMaxLaunches = 64;
 constexpr size_t kBatchMaxArgs = 2048;
 static_assert(sizeof(RowsFwdArgs) <= kBatchMaxArgs && sizeof(RowsInvArgs) <= kBatchMaxArgs &&
                   sizeof(ColsArgs) <= kBatchMaxArgs && sizeof(PpeRowsArgs) <= kBatchMaxArgs &&

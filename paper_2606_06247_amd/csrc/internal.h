@@ -98,6 +98,10 @@ struct RowsFwdArgs {
   long ostrideA, ostrideB;   // complex elements between consecutive lines
   int B;               // line groups per workgroup
   int ldsM;            // complex slots per line buffer
+  // map_per > 0: line l packs logical rows 2l, 2l+1 of inA, logical row r at
+  // inA + (r / map_per) * map_plane + (r % map_per) * nx (boundary-row blocks)
+  int map_per;
+  long map_plane;
 };
 
 enum RowsEpi {
@@ -165,6 +169,10 @@ struct ColsArgs {
   int outer_axis;      // lattice axis of the outer index (-1: none)
   int B;               // lines (adjacent inner indices) per workgroup
   int ldsM;
+  // FP32 plans: FP64 x spectra of the d first and d last rows of every outer
+  // plane, per input field: edge[f][((h * nouter + o) * d + r) * ninner + c]
+  // (h = 0 low rows, 1 high rows), the inputs of FC along the line in FP64
+  const double2 *edge[3];
 };
 
 // ---------------------------------------------------------------- PPE passes

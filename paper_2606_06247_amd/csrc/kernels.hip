@@ -63,8 +63,16 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(KArg<RowsFwdArgs, G> k
   const int line = blockIdx.x * a.B + g;
   Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
   const bool active = line < a.nlines;
-  const double *pa = active ? a.inA + (size_t)line * a.strideA : nullptr;
-  const double *pb = (active && line < a.nB && a.inB) ? a.inB + (size_t)line * a.strideB : nullptr;
+  const double *pa, *pb;
+  if (a.map_per > 0) {
+    const int rA = 2 * line, rB = 2 * line + 1;
+    pa = active ? a.inA + (size_t)(rA / a.map_per) * a.map_plane + (size_t)(rA % a.map_per) * a.nx : nullptr;
+    pb = (active && line < a.nB) ? a.inA + (size_t)(rB / a.map_per) * a.map_plane + (size_t)(rB % a.map_per) * a.nx
+                                 : nullptr;
+  } else {
+    pa = active ? a.inA + (size_t)line * a.strideA : nullptr;
+    pb = (active && line < a.nB && a.inB) ? a.inB + (size_t)line * a.strideB : nullptr;
+  }
   batched<8, cpx<T>>(lt, a.nx, TL, [&](int j) { return to_cpx<T>(pa ? pa[j] : 0.0, pb ? pb[j] : 0.0); },
                      [&](int j, cpx<T> v) { buf[j] = v; });
   if (a.fc.on) {
@@ -394,14 +402,25 @@ __device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem
 }
 
 template <typename T>
-__device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, int TL) {
+__device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, int TL, int f, int c, int o) {
   const int n = a.nload, L = a.plan.n;
+  const double2 *edge = a.edge[f];
+  const int d = a.fc.d;
+  // FP64 boundary rows when the plan keeps them (FP32 spectra would carry
+  // their rounding, amplified by the continuation maps, into the extension)
+  auto val = [&](int q) -> double2 {
+    if (edge) {
+      const int h = q < d ? 0 : 1, r = q < d ? q : q - (n - d);
+      return edge[(((size_t)h * a.nouter + o) * d + r) * a.ninner + (c < a.ninner ? c : 0)];
+    }
+    return make_double2((double)buf[q].r, (double)buf[q].i);
+  };
   for (int j = n + lt; j < L; j += TL) {
     const int i = fc_slot(a.fc, n, L, j);
     double re = 0.0, im = 0.0;
     if (i >= 0) {
-      re = fc_cont(a.fc, n, i, [&](int q) { return (double)buf[q].r; });
-      im = fc_cont(a.fc, n, i, [&](int q) { return (double)buf[q].i; });
+      re = fc_cont(a.fc, n, i, [&](int q) { return val(q).x; });
+      im = fc_cont(a.fc, n, i, [&](int q) { return val(q).y; });
     }
     buf[j] = to_cpx<T>(re, im);
   }
@@ -431,7 +450,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
     cols_load<T>(a, smem, in, c0, obase_in, a.nload);
     __syncthreads();
     if (MODE == COLS_FWD && a.fc.on) {
-      cols_fc<T>(a, buf, lt, TL);
+      cols_fc<T>(a, buf, lt, TL, f, c, o);
       __syncthreads();
     }
     constexpr bool inv = MODE == COLS_INV;
@@ -448,7 +467,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
         cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[f]), c0, obase_in, a.nload);
         __syncthreads();
         if (a.fc.on) {
-          cols_fc<T>(a, buf, lt, TL);
+          cols_fc<T>(a, buf, lt, TL, f, c, o);
           __syncthreads();
         }
       } else {
@@ -481,7 +500,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
         cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[pass]), c0, obase_in, a.nload);
         __syncthreads();
         if (a.fc.on) {
-          cols_fc<T>(a, buf, lt, TL);
+          cols_fc<T>(a, buf, lt, TL, pass, c, o);
           __syncthreads();
         }
       } else {
