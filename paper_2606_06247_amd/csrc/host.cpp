@@ -300,10 +300,11 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
 }
 
 // Workgroup line count for a plan and per-line buffer size.
-int pick_B(const LinePlan &p, bool fp32, int want, int nbuf = 1) {
+int pick_B(const LinePlan &p, bool fp32, int want, int nbuf = 1, int len = 0) {
   const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  const int m = len > 0 ? len : p.M;
   int B = want;
-  while (B > 1 && ((size_t)B * nbuf * padded_len(p.M, p.pad) * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
+  while (B > 1 && ((size_t)B * nbuf * padded_len(m, p.pad) * es > (size_t)kMaxLds || B * p.TL > kMaxThreads)) --B;
   return B;
 }
 
@@ -394,6 +395,7 @@ struct fcsph_plan {
   int ncoef[3] = {0, 0, 0};
   const double *mu[3] = {nullptr, nullptr, nullptr};
   const void *qtw[3] = {nullptr, nullptr, nullptr};   // quarter-wave pre-twiddles
+  const double2 *dcs[3] = {nullptr, nullptr, nullptr};  // DCT-I at length N: (cos, sin)(pi j / N)
   // symbols
   SymTables st{};
   // scratch
@@ -415,6 +417,15 @@ struct fcsph_plan {
   int ntaps = 0, reach = 0;
   size_t ws_bytes = 0;
 };
+
+namespace {
+// Line buffer elements of the PPE transform along axis a: the transform work
+// length, plus the result and 8 partial-sum slots for the length-N DCT-I.
+int ppe_line_len(const fcsph_plan *p, int a) {
+  const LinePlan &t = p->trig[a];
+  return p->dcs[a] ? t.M + 1 + t.n + 1 + 8 : t.M;
+}
+}  // namespace
 
 namespace {
 
@@ -613,6 +624,11 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     } else {
       kind = d->prs_bc[a][0] == FCSPH_BC_NEUMANN ? TRIG_DCT1 : TRIG_DST1;
       L = 2 * (nn - 1);
+      // FP64 DCT-I: one DFT of length N = n - 1 and a running sum (half the
+      // transform length of the even extension; at n = 1024 a 2048-point
+      // instead of a 4096-point Bluestein FFT).  The FP32 form keeps the even
+      // extension: the running sum would add FP32 rounding over N / 2 terms.
+      if (kind == TRIG_DCT1 && !f32 && nn >= 3) L = nn - 1;
     }
     p->trig_kind[a] = kind;
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
@@ -647,6 +663,19 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     u.dst = ws.take(u.data.size());
     p->mu[a] = (const double *)u.dst;
     up.push_back(std::move(u));
+    if (kind == TRIG_DCT1 && L == nn - 1) {
+      Upload q;
+      const int N = nn - 1;
+      std::vector<double2> t(N / 2 + 1);
+      for (int j = 0; j <= N / 2; ++j) {
+        const LD ang = kPi * (LD)j / (LD)N;
+        t[j] = make_double2((double)cosl(ang), (double)sinl(ang));
+      }
+      q.data.assign((const char *)t.data(), (const char *)(t.data() + t.size()));
+      q.dst = ws.take(q.data.size());
+      p->dcs[a] = (const double2 *)q.dst;
+      up.push_back(std::move(q));
+    }
     if (qw) {
       // exp(-i pi j / 2N), j < 2N, N = n - 1
       Upload q;
@@ -998,8 +1027,9 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.qtw = p->qtw[0];
-  r.B = pick_B(r.plan, f32, p->want_B);
-  r.ldsM = padded_len(r.plan.M, r.plan.pad);
+  r.dcs = p->dcs[0];
+  r.B = pick_B(r.plan, f32, p->want_B, 1, ppe_line_len(p, 0));
+  r.ldsM = padded_len(ppe_line_len(p, 0), r.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_rows_fwd");
     if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
@@ -1015,8 +1045,9 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   cy.ncoef = p->ncoef[1];
   cy.data = p->coef;
   cy.qtw = p->qtw[1];
-  cy.B = pick_B(cy.plan, f32, p->want_B);
-  cy.ldsM = padded_len(cy.plan.M, cy.plan.pad);
+  cy.dcs = p->dcs[1];
+  cy.B = pick_B(cy.plan, f32, p->want_B, 1, ppe_line_len(p, 1));
+  cy.ldsM = padded_len(ppe_line_len(p, 1), cy.plan.pad);
   cy.solve = 0;
   {
     LaunchTimer t(p->ctx, "ppe_cols_y_fwd");
@@ -1040,8 +1071,10 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   const double sy = p->trig_kind[1] == TRIG_DFT ? 1.0 / ny : 1.0 / (2.0 * (ny - 1));
   cz.scale = sy / nz;
   cz.data = p->coef;
-  cz.B = pick_B(cz.plan, f32, p->want_B);
-  cz.ldsM = padded_len(cz.plan.M, cz.plan.pad);
+  cz.qtw = p->qtw[2];
+  cz.dcs = p->dcs[2];
+  cz.B = pick_B(cz.plan, f32, p->want_B, 1, ppe_line_len(p, 2));
+  cz.ldsM = padded_len(ppe_line_len(p, 2), cz.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_cols_z_solve");
     if (!chk(p, launch_ppe_cols(cz, f32, p->ctx->stream), "ppe z", st)) return st;
@@ -1083,8 +1116,9 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.in_float = f32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.qtw = p->qtw[0];
-  r.B = pick_B(r.plan, f32, p->want_B);
-  r.ldsM = padded_len(r.plan.M, r.plan.pad);
+  r.dcs = p->dcs[0];
+  r.B = pick_B(r.plan, f32, p->want_B, 1, ppe_line_len(p, 0));
+  r.ldsM = padded_len(ppe_line_len(p, 0), r.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_rows_fwd");
     if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
@@ -1108,8 +1142,9 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   c.scale = p->trig_kind[1] == TRIG_DFT ? 1.0 / p->n[1] : 1.0 / (2.0 * (p->n[1] - 1));
   c.data = p->coef;
   c.qtw = p->qtw[1];
-  c.B = pick_B(c.plan, f32, p->want_B);
-  c.ldsM = padded_len(c.plan.M, c.plan.pad);
+  c.dcs = p->dcs[1];
+  c.B = pick_B(c.plan, f32, p->want_B, 1, ppe_line_len(p, 1));
+  c.ldsM = padded_len(ppe_line_len(p, 1), c.plan.pad);
   {
     LaunchTimer t(p->ctx, "ppe_cols_solve");
     if (!chk(p, launch_ppe_cols(c, f32, p->ctx->stream), "ppe cols", st)) return st;

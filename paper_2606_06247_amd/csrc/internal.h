@@ -202,6 +202,7 @@ struct PpeRowsArgs {
   const double *in_real;   // forward input (double), or null when in_float used
   const float *in_float;
   const void *qtw;     // QWS / QWC: cpx<T> exp(-i pi j / 2N), j < 2N
+  const double2 *dcs;  // DCT1 at length N (plan.n == N): (cos, sin)(pi j / N), j <= N / 2; null: length 2N
   void *coef;          // cpx<T> coefficient rows
   double *out;         // inverse output (physical rows)
   double scale;
@@ -224,6 +225,7 @@ struct PpeColsArgs {
   const double *mu_outer;  // eigenvalues along the outer axis (or null)
   double scale;
   const void *qtw;     // QWS / QWC line axis: cpx<T> exp(-i pi j / 2N), j < 2N
+  const double2 *dcs;  // DCT1 at length N, as for the rows
   void *data;          // cpx<T>, in place
   int B, ldsM;
 };

@@ -521,6 +521,92 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
   }
 }
 
+// ============================================================= DCT-I at length N
+// DCT-I of the N + 1 values f = buf[0..N] of a complex line,
+//   Z_k = f_0 + (-1)^k f_N + 2 sum_{j=1}^{N-1} f_j cos(pi j k / N),   k = 0..N,
+// which is the DFT of the even extension of length 2N, computed from one DFT
+// of length N.  With y_j = (f_j + f_{N-j}) / 2 - sin(pi j / N) (f_j - f_{N-j})
+// (j < N) and Y = DFT_N(y), the symmetric and antisymmetric parts of y give
+//   Z_{2k} = Y_k + Y_{N-k},    Z_{2k+1} = Z_{2k-1} + i (Y_k - Y_{N-k}),
+// and the odd outputs are a running sum started at
+//   Z_1 = f_0 - f_N + 2 sum_{j=1}^{N-1} f_j cos(pi j / N).
+// dct1_pre forms y in place and returns Z_1 (every thread of the line group
+// holds it); the caller runs the length-N transform (plan p) on buf; dct1_post
+// forms Z into buf[0..N].  Line buffer: [0, M) transform, [M + 1, M + N + 2)
+// the result (clear of buf[0..N] also when M == N), then 8 slots for per-wave
+// partial sums.  cs[j] = (cos, sin)(pi j / N)
+// for j <= N / 2.  Line groups are whole waves (TL is a multiple of 64).
+template <typename T>
+__device__ __forceinline__ cpx<T> wave_incl_scan(cpx<T> v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T r = __shfl_up(v.r, d, 64), i = __shfl_up(v.i, d, 64);
+    if (lane >= d) {
+      v.r += r;
+      v.i += i;
+    }
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> dct1_pre(Line<T> buf, const LinePlan &p, const double2 *cs, int lt, int TL) {
+  const int N = p.n, H = N / 2;
+  const int tail = p.M + N + 2;
+  cpx<T> z = {T(0), T(0)};
+  for (int j = lt; j <= H; j += TL) {
+    if (j == 0) {
+      const cpx<T> a = buf[0], b = buf[N];
+      buf[0] = cscale(cadd(a, b), T(0.5));
+      z = csub(a, b);
+    } else if (2 * j != N) {
+      // positions j and N - j belong to this thread only
+      const cpx<T> a = buf[j], b = buf[N - j];
+      const double2 w = cs[j];
+      const T s = T(w.y), c2 = T(2.0 * w.x);
+      const cpx<T> h = cscale(cadd(a, b), T(0.5)), d = csub(a, b);
+      buf[j] = {h.r - s * d.r, h.i - s * d.i};
+      buf[N - j] = {h.r + s * d.r, h.i + s * d.i};
+      z = {z.r + c2 * d.r, z.i + c2 * d.i};
+    }
+  }
+  z = wave_incl_scan(z);
+  if ((threadIdx.x & 63) == 63) buf[tail + (lt >> 6)] = z;
+  __syncthreads();
+  cpx<T> z1 = {T(0), T(0)};
+  for (int w = 0; w < (TL >> 6); ++w) z1 = cadd(z1, buf[tail + w]);
+  return z1;
+}
+
+template <typename T>
+__device__ __forceinline__ void dct1_post(Line<T> buf, const LinePlan &p, cpx<T> z1, int lt, int TL) {
+  const int N = p.n, H = N / 2, O = p.M + 1;
+  const int tail = O + N + 1;
+  // k = 0..H in contiguous chunks per thread: even output 2k, odd output
+  // 2k + 1 (while 2k + 1 <= N) as a chunk-local running sum first
+  const int q = (H + TL) / TL;
+  const int k0 = lt * q, k1 = min(k0 + q, H + 1);
+  cpx<T> run = {T(0), T(0)};
+  for (int k = k0; k < k1; ++k) {
+    const cpx<T> yk = buf[k], ynk = buf[k == 0 ? 0 : N - k];
+    buf[O + 2 * k] = cadd(yk, ynk);
+    if (k > 0) run = cadd(run, cpi(csub(yk, ynk)));
+    if (2 * k + 1 <= N) buf[O + 2 * k + 1] = run;
+  }
+  // offsets: Z_1 + the sums of the chunks before this thread's
+  const cpx<T> incl = wave_incl_scan(run);
+  if ((threadIdx.x & 63) == 63) buf[tail + (lt >> 6)] = incl;
+  __syncthreads();
+  cpx<T> off = cadd(z1, csub(incl, run));
+  for (int w = 0; w < (lt >> 6); ++w) off = cadd(off, buf[tail + w]);
+  for (int k = k0; k < k1; ++k)
+    if (2 * k + 1 <= N) buf[O + 2 * k + 1] = cadd(buf[O + 2 * k + 1], off);
+  __syncthreads();
+  for (int k = lt; k <= N; k += TL) buf[k] = buf[O + k];
+  __syncthreads();
+}
+
 // ============================================================= PPE rows
 // Coefficient row layout: DCT-I / DST-I rows are real; coefficient m of a row
 // is stored in component (m & 1) of complex slot m >> 1.  DFT rows are complex
@@ -592,8 +678,10 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
     }
   }
   __syncthreads();
+  const bool half = a.kind == TRIG_DCT1 && a.dcs;
   if (a.kind == TRIG_DCT1) {
-    for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];             // even extension
+    if (!half)
+      for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];           // even extension
   } else if (a.kind == TRIG_DST1) {
     for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));   // odd extension
   } else if (qw && !a.inverse) {
@@ -608,8 +696,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
     for (int j = n - 1 + lt; j < L; j += TL) buf[j] = cscale(buf[L - 1 - j], sg);
   }
   __syncthreads();
+  cpx<T> z1 = {T(0), T(0)};
+  if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
   line_dft<T>(buf, a.plan, lt, TL, cj, cj);
+  if (half) dct1_post<T>(buf, a.plan, z1, lt, TL);
 
   // ---- results
   if (!a.inverse) {
@@ -699,7 +790,7 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
     // coefficients at 0..N-1: mirror to 2N-1-l
     const T sg = qws ? T(-1) : T(1);
     for (int j = n - 1 + lt; j < L; j += TL) buf[j] = cscale(buf[L - 1 - j], sg);
-  } else if (a.kind == TRIG_DCT1) {
+  } else if (a.kind == TRIG_DCT1 && !a.dcs) {
     for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
   } else if (a.kind == TRIG_DST1) {
     // odd extension: positions 0 and n-1 are zero, j > n-1 holds -buf[L-j]
@@ -710,9 +801,14 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
     for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));
   }
   __syncthreads();
+  const bool half = a.kind == TRIG_DCT1 && a.dcs;
+  cpx<T> z1 = {T(0), T(0)};
+  if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
   const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
   line_dft<T>(buf, a.plan, lt, TL, cj, cj);
-  if (qw && !is_values) {
+  if (half) {
+    dct1_post<T>(buf, a.plan, z1, lt, TL);
+  } else if (qw && !is_values) {
     // F = 2i W (QWS), 2 W (QWC); position N holds no mode
     for (int j = lt; j < n; j += TL) {
       const cpx<T> w = buf[j];
