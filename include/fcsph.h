@@ -134,6 +134,12 @@ const char *fcsph_ctx_last_error(fcsph_ctx *c);
 fcsph_status fcsph_ctx_set_timing(fcsph_ctx *c, int enable);
 fcsph_status fcsph_ctx_read_timing(fcsph_ctx *c, int cap, char *names, int *counts,
                                    double *total_ms, int *n);
+/* Restrict timing to launches of one kernel kind (the name read_timing
+ * reports, copied; at most 31 characters); NULL or "" times every kind.
+ * Timing one kind brackets one launch per call with events instead of every
+ * launch, which keeps the event overhead out of the other kernels.
+ * FCSPH_E_INVALID for a longer name. */
+fcsph_status fcsph_ctx_set_timing_only(fcsph_ctx *c, const char *name);
 
 /* Bytes of device workspace a plan for *d needs (tables + scratch); the
  * workspace must be 256-byte aligned. */

@@ -37,7 +37,7 @@ EXPORTS = [
     "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
     "fcsph_spectral_div",
     "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_ctx_set_timing",
-    "fcsph_ctx_read_timing", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
+    "fcsph_ctx_read_timing", "fcsph_ctx_set_timing_only", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
     "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_ppe", "fcsph_batch_launch",
     "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
 ]
@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_ppe_solve.argtypes = [vp, vp, vp]
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
     L.fcsph_ctx_set_timing.argtypes = [vp, i]
+    L.fcsph_ctx_set_timing_only.argtypes = [vp, ctypes.c_char_p]
     L.fcsph_ctx_read_timing.argtypes = [vp, i, ctypes.c_char_p, P(i), P(d), P(i)]
     L.fcsph_batch_workspace_bytes.argtypes = [i, P(ctypes.c_size_t)]
     L.fcsph_batch_create.argtypes = [vp, i, vp, ctypes.c_size_t, P(vp)]
@@ -170,7 +171,10 @@ class Context:
     def sync(self):
         _check(lib().fcsph_ctx_sync(self.handle), self.handle, "fcsph_ctx_sync")
 
-    def set_timing(self, on: bool):
+    def set_timing(self, on: bool, only: str | None = None):
+        """Bracket launches with events (all kinds, or only kind `only`)."""
+        _check(lib().fcsph_ctx_set_timing_only(self.handle, only.encode() if only else None),
+               self.handle, "set_timing_only")
         _check(lib().fcsph_ctx_set_timing(self.handle, int(bool(on))), self.handle, "set_timing")
 
     def read_timing(self) -> dict:

@@ -29,6 +29,7 @@ struct fcsph_ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   bool timing = false;
+  std::string timing_only;               // time only this kernel kind (empty: all)
   std::vector<TimedLaunch> launches;     // recorded while timing is on
   std::vector<hipEvent_t> event_pool;    // reusable events
 };
@@ -51,7 +52,7 @@ struct LaunchTimer {
   const char *name;
   hipEvent_t a = nullptr, b = nullptr;
   LaunchTimer(fcsph_ctx *ctx, const char *n) : c(ctx), name(n) {
-    if (c && c->timing && !active_recorder()) {
+    if (c && c->timing && !active_recorder() && (c->timing_only.empty() || c->timing_only == n)) {
       a = pool_event(c);
       b = pool_event(c);
       if (a) hipEventRecord(a, c->stream);
@@ -205,10 +206,8 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
   if (tl > kMaxThreads) return false;
   p.TL = tl;
   // LDS padding (one slot every 16 elements): a sweep of 0..5 on the 1024^2
-  // step put 3..5 ahead of none by 2-4 % (power-of-two Bluestein lengths gain
-  // most), so it is on for every length
-  p.pad = 4;
-  if (const char *e = getenv("FCSPH_LDS_PAD")) p.pad = atoi(e) == 0 ? 0 : (atoi(e) < 0 ? p.pad : atoi(e));
+  // step put 3..5 ahead of none by 2-4 %; the device code uses the fixed shift
+  p.pad = kLdsPadShift;
   const size_t es = fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
   // twiddles exp(-2 pi i t / M)
   {
@@ -1221,6 +1220,13 @@ const char *fcsph_ctx_last_error(fcsph_ctx *c) { return c ? c->last_error.c_str(
 fcsph_status fcsph_ctx_set_timing(fcsph_ctx *c, int enable) {
   if (!c) return FCSPH_E_INVALID;
   c->timing = enable != 0;
+  return FCSPH_OK;
+}
+
+fcsph_status fcsph_ctx_set_timing_only(fcsph_ctx *c, const char *name) {
+  if (!c) return FCSPH_E_INVALID;
+  if (name && std::strlen(name) > 31) return fail(c, FCSPH_E_INVALID, "timer name longer than 31 characters");
+  c->timing_only = name ? name : "";
   return FCSPH_OK;
 }
 

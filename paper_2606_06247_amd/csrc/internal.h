@@ -27,11 +27,16 @@ struct alignas(2 * sizeof(T)) cpx {
 __host__ __device__ constexpr int pad_index(int p, int pad) { return pad ? p + (p >> pad) : p; }
 __host__ __device__ constexpr int padded_len(int m, int pad) { return ((pad_index(m, pad) + 8) & ~7) + 1; }
 
+// LDS line buffers hold one padding slot after every 2^kLdsPadShift elements
+// (fewer bank conflicts on the strided butterfly reads).  The shift is a
+// compile-time constant so that the index arithmetic folds; plans record it
+// in LinePlan::pad for the host-side sizes.
+constexpr int kLdsPadShift = 4;
+
 template <typename T>
 struct Line {
   cpx<T> *p;
-  int sh;     // padding shift, 31 = none
-  __device__ __forceinline__ cpx<T> &operator[](int i) const { return p[i + (i >> sh)]; }
+  __device__ __forceinline__ cpx<T> &operator[](int i) const { return p[i + (i >> kLdsPadShift)]; }
 };
 
 // One batched 1D DFT of length n along a line, executed by a group of TL

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(KArg<RowsFwdArgs, G> k
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
   const int line = blockIdx.x * a.B + g;
-  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+  Line<T> buf{smem + (size_t)g * a.ldsM};
   const bool active = line < a.nlines;
   const double *pa, *pb;
   if (a.map_per > 0) {
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> 
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+  Line<T> buf{smem + (size_t)g * a.ldsM};
   const long P = a.spec_pitch;
 
   if constexpr (EPI == EPI_STORE) {
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> 
     for (int r0 = 0; r0 < NL; r0 += G) {
       const int q = r0 + g;
       const bool act = q < NL;
-      Line<T> lb{smem + (size_t)(act ? q : 0) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+      Line<T> lb{smem + (size_t)(act ? q : 0) * a.ldsM};
       if (act) {
         const cpx<T> *sA, *sB;
         if constexpr (EPI == EPI_STEP_A2 || EPI == EPI_STEP_A3) {
@@ -223,8 +223,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> 
     }
     const size_t ro = (size_t)row * a.nx;
     if constexpr (EPI == EPI_STEP_A2) {
-      const int sh = a.plan.pad ? a.plan.pad : 31;
-      const Line<T> b0{smem, sh}, b1{smem + a.ldsM, sh}, b2{smem + 2 * (size_t)a.ldsM, sh};
+      const Line<T> b0{smem}, b1{smem + a.ldsM}, b2{smem + 2 * (size_t)a.ldsM};
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         const double u = a.u[0][ro + x], v = a.u[1][ro + x];
         const double gxu = b0[x].r, gyu = b0[x].i, gxv = b1[x].r, gyv = b1[x].i;
@@ -243,7 +242,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> 
     } else if constexpr (EPI == EPI_STEP_A3) {
       Line<T> b[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) b[k] = Line<T>{smem + (size_t)k * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+      for (int k = 0; k < 6; ++k) b[k] = Line<T>{smem + (size_t)k * a.ldsM};
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         const double u = a.u[0][ro + x], v = a.u[1][ro + x], w = a.u[2][ro + x];
@@ -267,8 +266,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> 
         a.ustar[2][ro + x] = ws;
       }
     } else {
-      const int sh = a.plan.pad ? a.plan.pad : 31;
-      const Line<T> b0{smem, sh}, b1{smem + a.ldsM, sh};
+      const Line<T> b0{smem}, b1{smem + a.ldsM};
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)b0[x].r;
@@ -387,7 +385,7 @@ __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const
                      },
                      [&](int idx, cpx<T> v) {
                        const int l = idx % a.B, j = idx / a.B;
-                       Line<T>{smem + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j] = v;
+                       Line<T>{smem + (size_t)l * a.ldsM}[j] = v;
                      });
 }
 
@@ -397,7 +395,7 @@ __device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
     const int c = c0 + l;
-    if (c < a.ninner) out[obase + (size_t)j * a.es_out + c] = Line<T>{const_cast<cpx<T> *>(smem) + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j];
+    if (c < a.ninner) out[obase + (size_t)j * a.es_out + c] = Line<T>{const_cast<cpx<T> *>(smem) + (size_t)l * a.ldsM}[j];
   }
 }
 
@@ -434,7 +432,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+  Line<T> buf{smem + (size_t)g * a.ldsM};
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const int bid = xcd_panel(blockIdx.x, gridDim.x);
   const int o = bid / npanel;
@@ -460,7 +458,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
     // pass 0: FC + forward DFT, kept in a second LDS line (xb); pass q + 1:
     // symbol q times xb, inverse DFT, store.  One transform call site keeps
     // the kernel's register footprint at that of a single transform.
-    Line<T> xb{smem + (size_t)(a.B + g) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+    Line<T> xb{smem + (size_t)(a.B + g) * a.ldsM};
     const int f = blockIdx.y;
     for (int pass = 0; pass <= a.nout; ++pass) {
       if (pass == 0) {
@@ -491,7 +489,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
     // COLS_DIV: out = sum_f S_f DFT(FC(in_f)), one output; passes 0..nin-1
     // transform input f and accumulate in a second LDS line (each thread owns
     // its positions), the last pass inverts the sum
-    Line<T> acc{smem + (size_t)(a.B + g) * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+    Line<T> acc{smem + (size_t)(a.B + g) * a.ldsM};
     for (int k = lt; k < E; k += TL) acc[k] = {T(0), T(0)};
     const int nin = a.st.ndim;
     for (int pass = 0; pass <= nin; ++pass) {
@@ -630,7 +628,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+  Line<T> buf{smem + (size_t)g * a.ldsM};
   const int line = blockIdx.x * a.B + g;
   const int rA = 2 * line, rB = 2 * line + 1;
   const bool okA = rA < a.nrows, okB = rB < a.nrows;
@@ -840,7 +838,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
   const int TL = a.plan.TL;
   const int g = threadIdx.x / TL;
   const int lt = threadIdx.x - g * TL;
-  Line<T> buf{smem + (size_t)g * a.ldsM, a.plan.pad ? a.plan.pad : 31};
+  Line<T> buf{smem + (size_t)g * a.ldsM};
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const int bid = xcd_panel(blockIdx.x, gridDim.x);
   const int o = bid / npanel;
@@ -857,7 +855,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
                      },
                      [&](int idx, cpx<T> v) {
                        const int l = idx % a.B, j = idx / a.B;
-                       Line<T>{smem + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j] = v;
+                       Line<T>{smem + (size_t)l * a.ldsM}[j] = v;
                      });
   __syncthreads();
   // solve == 0: forward only; 1: forward, divide, inverse; 2: inverse only
@@ -894,7 +892,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
     const int cc = c0 + l;
-    if (cc < a.ninner) data[(size_t)j * a.es + cc] = Line<T>{smem + (size_t)l * a.ldsM, a.plan.pad ? a.plan.pad : 31}[j];
+    if (cc < a.ninner) data[(size_t)j * a.es + cc] = Line<T>{smem + (size_t)l * a.ldsM}[j];
   }
 }
 
