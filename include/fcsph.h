@@ -147,7 +147,17 @@ fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes);
 /* Builds a plan: validates *d, computes every table on the host and copies
  * it into the workspace on the context stream.  Validation: ndim 2 or 3;
  * walled axes need n >= 2 fc_d; the kernel support 2h must be below half of
- * every extended period; FCSPH_E_UNSUPPORTED for combinations not built. */
+ * every extended period; FCSPH_E_UNSUPPORTED for combinations not built.
+ * Every transform line runs in one workgroup of at most 512 threads.  An
+ * operator line's thread holds two butterflies of radix <= 4 or one of radix
+ * 5..8 per stage, a PPE line's up to six of radix 2 and two of radix 5..8; a
+ * length whose stages need more threads uses Bluestein, with a work length
+ * up to 4096 (operators) or 8192 (PPE), and a length beyond that is
+ * FCSPH_E_UNSUPPORTED (in practice: lattice sides above about 2020 on the
+ * whole-period and direct routes, whose plans hold whole-period transforms;
+ * on the windowed route up to 4092 with Neumann pressure walls in FP64, and
+ * up to 2049 where the PPE needs a transform of length 2(n - 1), depending
+ * on its factors). */
 fcsph_status fcsph_plan_create(fcsph_ctx *c, const fcsph_desc *d, void *workspace,
                                size_t bytes, fcsph_plan **out);
 fcsph_status fcsph_plan_destroy(fcsph_plan *p);

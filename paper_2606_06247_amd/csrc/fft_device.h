@@ -66,12 +66,6 @@ __device__ __forceinline__ int xcd_panel(int b, int nb) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
-// Largest number of butterflies per thread and stage for radix R (bounds the
-// registers a stage holds); the host sizes TL with the same rule.
-__host__ __device__ constexpr int nb_max(int R) {
-  return R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1;
-}
-
 // ---- radix-R DFTs (forward, exp(-2 pi i j k / R)) on a register array ----
 template <typename T, int R>
 struct Dft;
@@ -224,10 +218,10 @@ template <typename T, int R>
 __device__ __forceinline__ constexpr bool is_pow2_radix() { return R == 2 || R == 3 || R == 4 || R == 8; }
 
 // One Stockham stage.  N: work length; Ns: product of previous radices.
-template <typename T, int R>
+template <typename T, int R, bool WIDE = false>
 __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const cpx<T> *tw,
                                                int lt, int TL, bool active) {
-  constexpr int NB = nb_max(R);
+  constexpr int NB = nb_max(R, WIDE);
   const int NR = N / R;
   const int tstride = N / (Ns * R);
   cpx<T> v[NB][R];
@@ -291,9 +285,10 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
 }
 
 // Forward FFT of length N = prod(radix) in place on buf (natural order).
-// BIG enables the odd radices 17..31 (held whole in registers); only the PPE
-// kernels instantiate it, which keeps the register budget of the others.
-template <typename T, bool BIG = false>
+// BIG enables the odd radices 11..31 (held whole in registers); no kernel
+// instantiates it at present, which keeps every kernel's register budget at
+// that of radices <= 8.
+template <typename T, bool BIG = false, bool WIDE = false>
 __device__ __forceinline__ void fft_stockham(Line<T> buf, const LinePlan &p, int N, int lt, int TL,
                                              bool active) {
   const cpx<T> *tw = static_cast<const cpx<T> *>(p.tw);
@@ -301,22 +296,22 @@ __device__ __forceinline__ void fft_stockham(Line<T> buf, const LinePlan &p, int
   for (int s = 0; s < p.nstages; ++s) {
     const int R = p.radix[s];
     switch (R) {
-      case 2: stockham_stage<T, 2>(buf, N, Ns, tw, lt, TL, active); break;
-      case 3: stockham_stage<T, 3>(buf, N, Ns, tw, lt, TL, active); break;
-      case 4: stockham_stage<T, 4>(buf, N, Ns, tw, lt, TL, active); break;
-      case 5: stockham_stage<T, 5>(buf, N, Ns, tw, lt, TL, active); break;
-      case 7: stockham_stage<T, 7>(buf, N, Ns, tw, lt, TL, active); break;
-      case 8: stockham_stage<T, 8>(buf, N, Ns, tw, lt, TL, active); break;
-      case 11: stockham_stage<T, 11>(buf, N, Ns, tw, lt, TL, active); break;
-      case 13: stockham_stage<T, 13>(buf, N, Ns, tw, lt, TL, active); break;
+      case 2: stockham_stage<T, 2, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+      case 3: stockham_stage<T, 3, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+      case 4: stockham_stage<T, 4, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+      case 5: stockham_stage<T, 5, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+      case 7: stockham_stage<T, 7, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+      case 8: stockham_stage<T, 8, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
       default:
         if constexpr (BIG) {
           switch (R) {
-            case 17: stockham_stage<T, 17>(buf, N, Ns, tw, lt, TL, active); break;
-            case 19: stockham_stage<T, 19>(buf, N, Ns, tw, lt, TL, active); break;
-            case 23: stockham_stage<T, 23>(buf, N, Ns, tw, lt, TL, active); break;
-            case 29: stockham_stage<T, 29>(buf, N, Ns, tw, lt, TL, active); break;
-            case 31: stockham_stage<T, 31>(buf, N, Ns, tw, lt, TL, active); break;
+            case 11: stockham_stage<T, 11, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+            case 13: stockham_stage<T, 13, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+            case 17: stockham_stage<T, 17, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+            case 19: stockham_stage<T, 19, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+            case 23: stockham_stage<T, 23, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+            case 29: stockham_stage<T, 29, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
+            case 31: stockham_stage<T, 31, WIDE>(buf, N, Ns, tw, lt, TL, active); break;
             default: break;
           }
         }
@@ -330,7 +325,7 @@ __device__ __forceinline__ void fft_stockham(Line<T> buf, const LinePlan &p, int
 // conj_in / conj_out conjugate the input / output, which turns the forward
 // transform into the unnormalised inverse.  Ends with a barrier.  An inactive
 // line group touches no memory but executes the same barriers.
-template <typename T, bool BIG = false>
+template <typename T, bool BIG = false, bool WIDE = false>
 __device__ __forceinline__ void line_dft(Line<T> buf, const LinePlan &p, int lt, int TL, bool conj_in,
                                          bool conj_out, bool active = true) {
   if (!active) {
@@ -362,7 +357,7 @@ __device__ __forceinline__ void line_dft(Line<T> buf, const LinePlan &p, int lt,
   const int npass = p.blue ? 2 : 1;
 #pragma unroll 1
   for (int pass = 0; pass < npass; ++pass) {
-    fft_stockham<T, BIG>(buf, p, len, lt, TL, active);
+    fft_stockham<T, BIG, WIDE>(buf, p, len, lt, TL, active);
     if (pass == 0 && p.blue) {
       // pointwise product with the filter spectrum; conjugate for the inverse FFT
       for (int j = lt; j < p.M; j += TL) buf[j] = cconj(cmul(buf[j], filt[j]));

@@ -98,11 +98,11 @@ bool factor_direct(int n, std::vector<int> &rad, bool big = false) {
   if (m % 8 == 0) { rad.push_back(8); m /= 8; }
   while (m % 4 == 0) { rad.push_back(4); m /= 4; }
   while (m % 2 == 0) { rad.push_back(2); m /= 2; }
-  const int odd[] = {3, 5, 7, 11, 13};
+  const int odd[] = {3, 5, 7};
   for (int p : odd)
     while (m % p == 0) { rad.push_back(p); m /= p; }
   if (big) {
-    const int odd_big[] = {17, 19, 23, 29, 31};
+    const int odd_big[] = {11, 13, 17, 19, 23, 29, 31};
     for (int p : odd_big)
       while (m % p == 0) { rad.push_back(p); m /= p; }
   }
@@ -118,8 +118,16 @@ bool smooth7(int m) {
   return m == 1;
 }
 
-int nb_max_host(int R) {
-  return R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1;
+// Threads per line group (a multiple of 64) that a Stockham plan with these
+// radices needs on a work length M, or 0 if it exceeds the workgroup bound.
+int line_threads(int M, const std::vector<int> &rad, int min_TL = 64, bool wide = false) {
+  int tl = std::max(64, min_TL);
+  for (int R : rad) {
+    if (R <= 1) continue;
+    tl = std::max(tl, (M / R + nb_max(R, wide) - 1) / nb_max(R, wide));
+  }
+  tl = (tl + 63) / 64 * 64;
+  return tl > kMaxThreads ? 0 : tl;
 }
 
 // Transform length of a windowed walled axis: the cheapest L >= n + 2 R whose
@@ -131,13 +139,13 @@ int window_length(int n, int R) {
   if (const char *e = getenv("FCSPH_WINDOW_L")) {
     const int L = atoi(e);
     std::vector<int> rad;
-    if (L >= lo && factor_direct(L, rad)) return L;
+    if (L >= lo && factor_direct(L, rad) && line_threads(L, rad)) return L;
   }
   double best = 1e300;
   int bestL = -1;
   for (int L = lo; L <= 2 * lo + 8; ++L) {
     std::vector<int> rad;
-    if (!factor_direct(L, rad)) continue;
+    if (!factor_direct(L, rad) || !line_threads(L, rad)) continue;
     double c = 4.0;
     bool ok = true;
     for (int r : rad) {
@@ -176,34 +184,29 @@ struct LineSpec {
 // Build a line plan for length n.  min_TL forces a minimum thread count per
 // line (used where the kernel keeps E / TL spectrum values in registers).
 bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> &up, LinePlan &p,
-                    bool big = false) {
+                    bool big = false, bool wide = false) {
   std::memset(&p, 0, sizeof(p));
   p.n = n;
   std::vector<int> rad;
   int M = n;
+  int tl = 0;
   if (n == 1) {
     rad = {};
-  } else if (factor_direct(n, rad, big)) {
+    tl = std::max(64, (min_TL + 63) / 64 * 64);
+  } else if (factor_direct(n, rad, big) && (tl = line_threads(n, rad, min_TL, wide)) > 0) {
     p.blue = 0;
   } else {
+    // Bluestein: the smallest 7-smooth M >= 2n - 1 whose stages fit one
+    // workgroup's line group (a direct length too long for it comes here too)
     p.blue = 1;
-    M = 2 * n - 1;
-    while (!smooth7(M)) ++M;
-    if (!factor_direct(M, rad)) return false;
+    for (M = 2 * n - 1; M <= 8 * n; ++M)
+      if (smooth7(M) && factor_direct(M, rad) && (tl = line_threads(M, rad, min_TL, wide)) > 0) break;
+    if (tl <= 0 || tl > kMaxThreads) return false;
   }
   p.M = M;
   p.nstages = (int)rad.size();
   if (n == 1) p.nstages = 0;
   for (int s = 0; s < p.nstages; ++s) p.radix[s] = rad[s];
-  int tl = 64;
-  for (int s = 0; s < p.nstages; ++s) {
-    const int R = rad[s];
-    const int need = (M / R + nb_max_host(R) - 1) / nb_max_host(R);
-    tl = std::max(tl, need);
-  }
-  tl = std::max(tl, min_TL);
-  tl = (tl + 63) / 64 * 64;
-  if (tl > kMaxThreads) return false;
   p.TL = tl;
   // LDS padding (one slot every 16 elements): a sweep of 0..5 on the 1024^2
   // step put 3..5 ahead of none by 2-4 %; the device code uses the fixed shift
@@ -524,8 +527,9 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       p->E[a] = window_length(p->n[a], p->reach);
       if (d->window_len[a] > 0) {
         std::vector<int> rad;
-        if (d->window_len[a] < p->n[a] + 2 * p->reach || !factor_direct(d->window_len[a], rad)) {
-          msg = "window_len must be >= n + 2 R with radices 2..13";
+        if (d->window_len[a] < p->n[a] + 2 * p->reach || !factor_direct(d->window_len[a], rad) ||
+            !line_threads(d->window_len[a], rad)) {
+          msg = "window_len must be >= n + 2 R, a product of radices 2, 3, 4, 5, 7, 8, and fit 512 threads per line";
           return FCSPH_E_INVALID;
         }
         p->E[a] = d->window_len[a];
@@ -633,7 +637,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
     p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : qw ? nn - 1 : nn - 2);
     const int minTL = (a == 0) ? 64 : 64;
-    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false)) {
+    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false, /*wide=*/true)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }

@@ -20,10 +20,22 @@ struct alignas(2 * sizeof(T)) cpx {
   T r, i;
 };
 
+// Largest number of butterflies per thread and stage for radix R; a line
+// group needs ceil(N / (R nb_max(R))) threads for a stage of radix R on N
+// points.  The stage keeps nb_max(R) butterflies in registers across its
+// barrier, so this bounds the kernels' register budget: with at most 8
+// complex values per thread the operator kernels of the FP64 step stay near
+// 128 VGPRs (3-4 waves per SIMD instead of 2).  The PPE kernels use the wide
+// rule (up to 16 values per thread): their transforms of length 2(n - 1) then
+// fit one 512-thread workgroup up to a 8192-point Bluestein work length.
+__host__ __device__ constexpr int nb_max(int R, bool wide = false) {
+  return wide ? (R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1) : (R <= 4 ? 2 : 1);
+}
+
 // LDS line buffers hold one padding slot after every 16 complex values, so
 // that the strided accesses of the Stockham stages spread over the LDS banks,
 // and consecutive lines start one bank group apart.
-// The padding is a per-plan choice (pad = 0: none, else one slot per 2^pad).
+// pad_index / padded_len take the shift (0: no padding).
 __host__ __device__ constexpr int pad_index(int p, int pad) { return pad ? p + (p >> pad) : p; }
 __host__ __device__ constexpr int padded_len(int m, int pad) { return ((pad_index(m, pad) + 8) & ~7) + 1; }
 

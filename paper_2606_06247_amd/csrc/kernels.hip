@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
-  line_dft<T>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, false, true>(buf, a.plan, lt, TL, cj, cj);
   if (half) dct1_post<T>(buf, a.plan, z1, lt, TL);
 
   // ---- results
@@ -803,7 +803,7 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
   const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
-  line_dft<T>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, false, true>(buf, a.plan, lt, TL, cj, cj);
   if (half) {
     dct1_post<T>(buf, a.plan, z1, lt, TL);
   } else if (qw && !is_values) {

@@ -38,14 +38,23 @@ def _factor(L: int):
     return rad if m == 1 else None
 
 
+def _line_threads(L: int, rad) -> int:
+    """Threads per line group a plan of these radices needs (the library's
+    rule: two butterflies per thread for radices <= 4, one above), rounded to
+    whole waves."""
+    tl = max([64] + [-(-(L // r) // (2 if r <= 4 else 1)) for r in rad])
+    return -(-tl // 64) * 64
+
+
 def window_candidates(n: int, reach: int = 2, count: int = 5, span: float = 1.35) -> list:
     """The `count` cheapest smooth window lengths in [n + 2R, span (n + 2R)]
-    under a per-point cost model (HBM term + butterfly stages)."""
+    under a per-point cost model (HBM term + butterfly stages), among those
+    whose line groups fit one 512-thread workgroup."""
     lo = n + 2 * reach
     scored = []
     for L in range(lo, int(math.ceil(span * lo)) + 1):
         rad = _factor(L)
-        if rad is None:
+        if rad is None or _line_threads(L, rad) > 512:
             continue
         scored.append(((4.0 + sum(RADIX_COST[r] for r in rad)) * L, L))
     scored.sort()
@@ -102,11 +111,17 @@ def tune_2d(ctx, n: int, precision: str = "fp64", lines=(1, 2, 4, 8), cache_path
     trials = []
     for L in window_candidates(n):
         for b in lines:
-            ms = time_step(ctx, _problem_2d(n, precision, L, b))
+            try:
+                ms = time_step(ctx, _problem_2d(n, precision, L, b))
+            except api.FcsphError:
+                continue               # a schedule the library cannot plan
             trials.append((L, b, ms))
             if best is None or ms < best[2]:
                 best = (L, b, ms)
     default_ms = time_step(ctx, _problem_2d(n, precision))
+    if best is None:
+        # no candidate could be planned: the library's own choice (0 = default)
+        best = (0, 0, default_ms)
     rec = {"window_len": best[0], "lines_per_group": best[1], "ms": round(best[2], 4),
            "default_ms": round(default_ms, 4), "trials": len(trials)}
     if log:
