@@ -204,6 +204,7 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
     if (tl <= 0 || tl > kMaxThreads) return false;
   }
   p.M = M;
+  p.wide = wide ? 1 : 0;
   p.nstages = (int)rad.size();
   if (n == 1) p.nstages = 0;
   for (int s = 0; s < p.nstages; ++s) p.radix[s] = rad[s];
@@ -637,7 +638,10 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
     p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : qw ? nn - 1 : nn - 2);
     const int minTL = (a == 0) ? 64 : 64;
-    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false, /*wide=*/true)) {
+    // the narrow butterfly rule where the line fits (more waves per SIMD),
+    // else the wide one (longer lines per workgroup)
+    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false, false) &&
+        !make_line_plan(L, f32, minTL, ws, up, p->trig[a], false, true)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }

@@ -26,8 +26,9 @@ struct alignas(2 * sizeof(T)) cpx {
 // barrier, so this bounds the kernels' register budget: with at most 8
 // complex values per thread the operator kernels of the FP64 step stay near
 // 128 VGPRs (3-4 waves per SIMD instead of 2).  The PPE kernels use the wide
-// rule (up to 16 values per thread): their transforms of length 2(n - 1) then
-// fit one 512-thread workgroup up to a 8192-point Bluestein work length.
+// rule (up to 16 values per thread) for lines the narrow rule cannot fit in
+// one 512-thread workgroup: transforms of length 2(n - 1) then fit up to a
+// 8192-point Bluestein work length.
 __host__ __device__ constexpr int nb_max(int R, bool wide = false) {
   return wide ? (R <= 2 ? 6 : R == 3 ? 4 : R == 4 ? 3 : R <= 8 ? 2 : 1) : (R <= 4 ? 2 : 1);
 }
@@ -63,6 +64,7 @@ struct LinePlan {
   int radix[kMaxStages];
   int TL;          // threads per line the plan is sized for
   int pad;         // LDS padding shift of the line buffers (0: none)
+  int wide;        // 1: sized for the wide butterfly rule (PPE kernels only)
   const void *tw;     // [M]  exp(-2 pi i t / M)
   const void *chirp;  // [n]  exp(-pi i (t^2 mod 2n) / n)        (Bluestein)
   const void *filt;   // [M]  DFT_M(wrapped conj chirp) / M       (Bluestein)

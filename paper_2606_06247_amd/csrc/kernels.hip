@@ -620,7 +620,7 @@ __device__ __forceinline__ T get_real_coef(const cpx<T> *row, int m) {
   return p[m & 1];
 }
 
-template <typename T, bool G>
+template <typename T, bool G, bool W>
 __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> ka) {
   const PpeRowsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
-  line_dft<T, false, true>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, false, W>(buf, a.plan, lt, TL, cj, cj);
   if (half) dct1_post<T>(buf, a.plan, z1, lt, TL);
 
   // ---- results
@@ -769,7 +769,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
 // ============================================================= PPE strided pass
 // Symmetric extension of buf[0..n) to length L and transform.  Coefficients
 // (is_values = false) or values (true) of the complex line end up in buf[0..n).
-template <typename T>
+template <typename T, bool W>
 __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArgs &a, int lt, int TL,
                                                    bool is_values) {
   // extension / twiddle before, one transform, mode extraction after
@@ -803,7 +803,7 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
   const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
-  line_dft<T, false, true>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, false, W>(buf, a.plan, lt, TL, cj, cj);
   if (half) {
     dct1_post<T>(buf, a.plan, z1, lt, TL);
   } else if (qw && !is_values) {
@@ -830,7 +830,7 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
   }
 }
 
-template <typename T, bool G>
+template <typename T, bool G, bool W>
 __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> ka) {
   const PpeColsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -862,7 +862,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
   const int npass = a.solve == 1 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const bool values = a.solve == 2 || pass == 1;
-    ppe_line_transform<T>(buf, a, lt, TL, values);
+    ppe_line_transform<T, W>(buf, a, lt, TL, values);
     if (a.solve == 1 && pass == 0) {
       // divide by -(mu_inner + mu_line + mu_outer) in FP64; a vanishing sum
       // (the constant mode) gives zero
@@ -1008,16 +1008,25 @@ hipError_t launch_ppe_rows(const PpeRowsArgs &a, bool fp32, hipStream_t s) {
   const int nl = (a.nrows + 1) / 2;
   const dim3 grid((nl + a.B - 1) / a.B), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
-  if (fp32) return issue(k_ppe_rows<float, false>, k_ppe_rows<float, true>, a, grid, block, lds, s);
-  return issue(k_ppe_rows<double, false>, k_ppe_rows<double, true>, a, grid, block, lds, s);
+  // plans whose lines do not fit the narrow butterfly rule run the wide kernels
+  if (a.plan.wide) {
+    if (fp32) return issue(k_ppe_rows<float, false, true>, k_ppe_rows<float, true, true>, a, grid, block, lds, s);
+    return issue(k_ppe_rows<double, false, true>, k_ppe_rows<double, true, true>, a, grid, block, lds, s);
+  }
+  if (fp32) return issue(k_ppe_rows<float, false, false>, k_ppe_rows<float, true, false>, a, grid, block, lds, s);
+  return issue(k_ppe_rows<double, false, false>, k_ppe_rows<double, true, false>, a, grid, block, lds, s);
 }
 
 hipError_t launch_ppe_cols(const PpeColsArgs &a, bool fp32, hipStream_t s) {
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const dim3 grid(npanel * a.nouter), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
-  if (fp32) return issue(k_ppe_cols<float, false>, k_ppe_cols<float, true>, a, grid, block, lds, s);
-  return issue(k_ppe_cols<double, false>, k_ppe_cols<double, true>, a, grid, block, lds, s);
+  if (a.plan.wide) {
+    if (fp32) return issue(k_ppe_cols<float, false, true>, k_ppe_cols<float, true, true>, a, grid, block, lds, s);
+    return issue(k_ppe_cols<double, false, true>, k_ppe_cols<double, true, true>, a, grid, block, lds, s);
+  }
+  if (fp32) return issue(k_ppe_cols<float, false, false>, k_ppe_cols<float, true, false>, a, grid, block, lds, s);
+  return issue(k_ppe_cols<double, false, false>, k_ppe_cols<double, true, false>, a, grid, block, lds, s);
 }
 
 hipError_t launch_fc_extend_axis(const double *in, double *out, int ndim, const int *shape_in,
