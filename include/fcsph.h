@@ -84,9 +84,11 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *  op_eval     fcsph_op_eval
  *  window_len[a], lines_per_group   schedule hints (0 = the library's
  *              choice): the transform length of a walled axis under
- *              FCSPH_OPS_FFT_WINDOW (>= n + 2R, factors 2..13), and the upper
- *              bound on lines per workgroup of the line kernels (1..16).  They
- *              change speed, never the result beyond rounding.
+ *              FCSPH_OPS_FFT_WINDOW (>= n + 2R, a product of radices 2, 3, 4,
+ *              5, 7, 8 whose stages fit 512 threads per line), and the upper
+ *              bound on lines per workgroup of the line kernels (1..16;
+ *              default 1).  They change speed, never the result beyond
+ *              rounding.
  */
 typedef struct {
   int ndim;

@@ -515,7 +515,9 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->fp32 = d->prec == FCSPH_FP32_MIXED;
   p->nd = d->ndim;
   p->window = d->op_eval == FCSPH_OPS_FFT_WINDOW;
-  p->want_B = d->lines_per_group > 0 ? d->lines_per_group : 4;
+  // one line per workgroup unless asked: the schedule tuner picked it at
+  // every lattice size it timed (more workgroups in flight per CU)
+  p->want_B = d->lines_per_group > 0 ? d->lines_per_group : 1;
   {
     std::vector<Tap> tl = wendland_tap_list(d->ndim, d->dx, d->h_over_dx, p->reach);
   }
