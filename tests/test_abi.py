@@ -85,3 +85,39 @@ def test_ctx_create_rejects_bad_device():
     from paper_2606_06247_amd import api
     h = ctypes.c_void_p()
     assert api.lib().fcsph_ctx_create(-1, None, ctypes.byref(h)) == api.E_INVALID
+
+
+def _plannable(n, precision="fp64", op_eval="fft_window", prs=("N", "N"), window_len=()):
+    from paper_2606_06247_amd import api
+    prob = api.Problem(n=(n, n), walled=(True, True), dx=1.0 / (n - 1), vel_bc=(("D", "D"), ("D", "D")),
+                       prs_bc=(prs, prs), precision=precision, op_eval=op_eval, window_len=window_len)
+    try:
+        api.workspace_bytes(prob)
+        return True
+    except api.FcsphError as e:
+        assert "unsupported" in str(e) or "invalid" in str(e), e
+        return False
+
+
+@pytest.mark.parametrize("n", [64, 1024, 1100, 1500, 2049])
+def test_line_lengths_within_the_thread_bound_plan(n):
+    """Every route and pressure-wall kind plans up to the documented sizes:
+    operator lines fit 256-512 threads at two butterflies of radix <= 4 or one
+    of radix 5..8 per thread; PPE lines fall back to the wide form."""
+    assert _plannable(n)
+    assert _plannable(n, prs=("D", "D"))
+    assert _plannable(n, prs=("D", "N"))
+    assert _plannable(n, precision="fp32")
+    if n <= 2020:
+        assert _plannable(n, op_eval="fft")
+        assert _plannable(n, op_eval="direct")
+
+
+def test_lines_beyond_the_thread_bound_are_refused_cleanly():
+    # whole-period transform of 2073 points: Bluestein beyond 4096 -> refused
+    assert not _plannable(2048, op_eval="fft")
+    # a PPE transform of length 2 (n - 1) = 5998 needs more than 8192 points
+    assert not _plannable(3000, prs=("D", "D"))
+    # a window length whose radix-5 stage needs 640 threads
+    assert not _plannable(1024, window_len=(3200, 3200))
+    assert _plannable(1024, window_len=(1120, 1120))
