@@ -136,8 +136,12 @@ __device__ __forceinline__ size_t spec_row(const RowsInvArgs &a, int r) {
   return ((size_t)(r / a.rpp) * a.prow + (r % a.rpp)) * (size_t)a.spec_pitch;
 }
 
+// At most 128 VGPRs (4 waves per SIMD): the fused step epilogues run 512-thread
+// workgroups, and at the compiler's own choice (137) only one of them fitted a
+// CU; capped, two do (no spills; the 1024^2 step 3 % faster).
 template <typename T, int EPI, bool GR>
-__global__ void __launch_bounds__(kMaxThreads) k_rows_inv(KArg<RowsInvArgs, GR> ka) {
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_rows_inv(KArg<RowsInvArgs, GR> ka) {
   const RowsInvArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
@@ -424,8 +428,12 @@ __device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, 
   }
 }
 
+// At most 168 VGPRs (3 waves per SIMD): the FP64 instantiations need 137 and
+// are unchanged; the FP32 ones (FP64 symbol coefficients and FC inputs) came
+// out at 171, one wave per SIMD fewer, and fit the cap without spills.
 template <typename T, int MODE, bool G>
-__global__ void __launch_bounds__(kMaxThreads) k_cols(KArg<ColsArgs, G> ka) {
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3)))
+k_cols(KArg<ColsArgs, G> ka) {
   const ColsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *smem = reinterpret_cast<cpx<T> *>(smem_raw);
