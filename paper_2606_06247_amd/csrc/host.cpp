@@ -630,11 +630,12 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     } else {
       kind = d->prs_bc[a][0] == FCSPH_BC_NEUMANN ? TRIG_DCT1 : TRIG_DST1;
       L = 2 * (nn - 1);
-      // FP64 DCT-I: one DFT of length N = n - 1 and a running sum (half the
-      // transform length of the even extension; at n = 1024 a 2048-point
-      // instead of a 4096-point Bluestein FFT).  The FP32 form keeps the even
-      // extension: the running sum would add FP32 rounding over N / 2 terms.
-      if (kind == TRIG_DCT1 && !f32 && nn >= 3) L = nn - 1;
+      // FP64 DCT-I / DST-I: one DFT of length N = n - 1 and a running sum
+      // (half the transform length of the even / odd extension; at n = 1024
+      // a 2048-point instead of a 4096-point Bluestein FFT).  The FP32 form
+      // keeps the extension: the running sum would add FP32 rounding over
+      // N / 2 terms.
+      if (!f32 && nn >= 3) L = nn - 1;
     }
     p->trig_kind[a] = kind;
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
@@ -672,7 +673,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     u.dst = ws.take(u.data.size());
     p->mu[a] = (const double *)u.dst;
     up.push_back(std::move(u));
-    if (kind == TRIG_DCT1 && L == nn - 1) {
+    if ((kind == TRIG_DCT1 || kind == TRIG_DST1) && L == nn - 1) {
       Upload q;
       const int N = nn - 1;
       std::vector<double2> t(N / 2 + 1);

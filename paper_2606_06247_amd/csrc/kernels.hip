@@ -527,21 +527,26 @@ k_cols(KArg<ColsArgs, G> ka) {
   }
 }
 
-// ============================================================= DCT-I at length N
-// DCT-I of the N + 1 values f = buf[0..N] of a complex line,
-//   Z_k = f_0 + (-1)^k f_N + 2 sum_{j=1}^{N-1} f_j cos(pi j k / N),   k = 0..N,
-// which is the DFT of the even extension of length 2N, computed from one DFT
-// of length N.  With y_j = (f_j + f_{N-j}) / 2 - sin(pi j / N) (f_j - f_{N-j})
-// (j < N) and Y = DFT_N(y), the symmetric and antisymmetric parts of y give
-//   Z_{2k} = Y_k + Y_{N-k},    Z_{2k+1} = Z_{2k-1} + i (Y_k - Y_{N-k}),
-// and the odd outputs are a running sum started at
-//   Z_1 = f_0 - f_N + 2 sum_{j=1}^{N-1} f_j cos(pi j / N).
-// dct1_pre forms y in place and returns Z_1 (every thread of the line group
-// holds it); the caller runs the length-N transform (plan p) on buf; dct1_post
-// forms Z into buf[0..N].  Line buffer: [0, M) transform, [M + 1, M + N + 2)
-// the result (clear of buf[0..N] also when M == N), then 8 slots for per-wave
-// partial sums.  cs[j] = (cos, sin)(pi j / N)
-// for j <= N / 2.  Line groups are whole waves (TL is a multiple of 64).
+// ============================================================= DCT-I / DST-I at length N
+// The DFT of the even (DCT-I) or odd (DST-I) extension of length 2N of the
+// N + 1 values f = buf[0..N] of a complex line,
+//   DCT-I: Z_k = f_0 + (-1)^k f_N + 2 sum_{j=1}^{N-1} f_j cos(pi j k / N),
+//   DST-I: Z_k = -2i sum_{j=1}^{N-1} f_j sin(pi j k / N)   (f_0 = f_N = 0),
+// k = 0..N, computed from one DFT of length N (Y = DFT_N(y), j < N):
+//   DCT-I: y_j = (f_j + f_{N-j}) / 2 - sin(pi j / N) (f_j - f_{N-j});
+//          Z_{2k} = Y_k + Y_{N-k},  Z_{2k+1} = Z_{2k-1} + i (Y_k - Y_{N-k}),
+//          started at Z_1 = f_0 - f_N + 2 sum_{j=1}^{N-1} f_j cos(pi j / N);
+//   DST-I: y_j = sin(pi j / N) (f_j + f_{N-j}) + (f_j - f_{N-j}) / 2;
+//          Z_{2k} = Y_k - Y_{N-k},  Z_{2k+1} = -i W_{2k+1} with
+//          W_{2k+1} = W_{2k-1} + Y_k + Y_{N-k}, started at W_1 = Y_0.
+// (The symmetric / antisymmetric parts of y under j -> N - j carry the even
+// and odd outputs.)  trig1_pre forms y in place and returns the DCT-I start
+// Z_1 (every thread of the line group holds it); the caller runs the
+// length-N transform (plan p) on buf; trig1_post forms Z into buf[0..N].
+// Line buffer: [0, M) transform, [M + 1, M + N + 2) the result (clear of
+// buf[0..N] also when M == N), then 8 slots for per-wave partial sums.
+// cs[j] = (cos, sin)(pi j / N) for j <= N / 2.  Line groups are whole waves
+// (TL is a multiple of 64).
 template <typename T>
 __device__ __forceinline__ cpx<T> wave_incl_scan(cpx<T> v) {
   const int lane = threadIdx.x & 63;
@@ -557,14 +562,15 @@ __device__ __forceinline__ cpx<T> wave_incl_scan(cpx<T> v) {
 }
 
 template <typename T>
-__device__ __forceinline__ cpx<T> dct1_pre(Line<T> buf, const LinePlan &p, const double2 *cs, int lt, int TL) {
+__device__ __forceinline__ cpx<T> trig1_pre(Line<T> buf, const LinePlan &p, const double2 *cs, bool sine,
+                                            int lt, int TL) {
   const int N = p.n, H = N / 2;
   const int tail = p.M + N + 2;
   cpx<T> z = {T(0), T(0)};
   for (int j = lt; j <= H; j += TL) {
     if (j == 0) {
       const cpx<T> a = buf[0], b = buf[N];
-      buf[0] = cscale(cadd(a, b), T(0.5));
+      buf[0] = cscale(sine ? csub(a, b) : cadd(a, b), T(0.5));
       z = csub(a, b);
     } else if (2 * j != N) {
       // positions j and N - j belong to this thread only
@@ -572,21 +578,32 @@ __device__ __forceinline__ cpx<T> dct1_pre(Line<T> buf, const LinePlan &p, const
       const double2 w = cs[j];
       const T s = T(w.y), c2 = T(2.0 * w.x);
       const cpx<T> h = cscale(cadd(a, b), T(0.5)), d = csub(a, b);
-      buf[j] = {h.r - s * d.r, h.i - s * d.i};
-      buf[N - j] = {h.r + s * d.r, h.i + s * d.i};
-      z = {z.r + c2 * d.r, z.i + c2 * d.i};
+      if (sine) {
+        const T s2 = s + s;
+        const cpx<T> u = {s2 * h.r, s2 * h.i}, v = cscale(d, T(0.5));
+        buf[j] = cadd(u, v);
+        buf[N - j] = csub(u, v);
+      } else {
+        buf[j] = {h.r - s * d.r, h.i - s * d.i};
+        buf[N - j] = {h.r + s * d.r, h.i + s * d.i};
+        z = {z.r + c2 * d.r, z.i + c2 * d.i};
+      }
+    } else if (sine) {
+      buf[j] = cscale(buf[j], T(2));     // sin(pi / 2) (f + f)
     }
   }
   z = wave_incl_scan(z);
   if ((threadIdx.x & 63) == 63) buf[tail + (lt >> 6)] = z;
   __syncthreads();
   cpx<T> z1 = {T(0), T(0)};
-  for (int w = 0; w < (TL >> 6); ++w) z1 = cadd(z1, buf[tail + w]);
+  if (!sine)
+    for (int w = 0; w < (TL >> 6); ++w) z1 = cadd(z1, buf[tail + w]);
   return z1;
 }
 
 template <typename T>
-__device__ __forceinline__ void dct1_post(Line<T> buf, const LinePlan &p, cpx<T> z1, int lt, int TL) {
+__device__ __forceinline__ void trig1_post(Line<T> buf, const LinePlan &p, cpx<T> z1, bool sine, int lt,
+                                           int TL) {
   const int N = p.n, H = N / 2, O = p.M + 1;
   const int tail = O + N + 1;
   // k = 0..H in contiguous chunks per thread: even output 2k, odd output
@@ -596,18 +613,26 @@ __device__ __forceinline__ void dct1_post(Line<T> buf, const LinePlan &p, cpx<T>
   cpx<T> run = {T(0), T(0)};
   for (int k = k0; k < k1; ++k) {
     const cpx<T> yk = buf[k], ynk = buf[k == 0 ? 0 : N - k];
-    buf[O + 2 * k] = cadd(yk, ynk);
-    if (k > 0) run = cadd(run, cpi(csub(yk, ynk)));
+    if (sine) {
+      buf[O + 2 * k] = k == 0 ? cpx<T>{T(0), T(0)} : csub(yk, ynk);
+      run = cadd(run, k == 0 ? yk : cadd(yk, ynk));
+    } else {
+      buf[O + 2 * k] = cadd(yk, ynk);
+      if (k > 0) run = cadd(run, cpi(csub(yk, ynk)));
+    }
     if (2 * k + 1 <= N) buf[O + 2 * k + 1] = run;
   }
-  // offsets: Z_1 + the sums of the chunks before this thread's
+  // offsets: the start value + the sums of the chunks before this thread's
   const cpx<T> incl = wave_incl_scan(run);
   if ((threadIdx.x & 63) == 63) buf[tail + (lt >> 6)] = incl;
   __syncthreads();
   cpx<T> off = cadd(z1, csub(incl, run));
   for (int w = 0; w < (lt >> 6); ++w) off = cadd(off, buf[tail + w]);
   for (int k = k0; k < k1; ++k)
-    if (2 * k + 1 <= N) buf[O + 2 * k + 1] = cadd(buf[O + 2 * k + 1], off);
+    if (2 * k + 1 <= N) {
+      const cpx<T> v = cadd(buf[O + 2 * k + 1], off);
+      buf[O + 2 * k + 1] = sine ? cmi(v) : v;
+    }
   __syncthreads();
   for (int k = lt; k <= N; k += TL) buf[k] = buf[O + k];
   __syncthreads();
@@ -684,12 +709,13 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
     }
   }
   __syncthreads();
-  const bool half = a.kind == TRIG_DCT1 && a.dcs;
+  const bool half = (a.kind == TRIG_DCT1 || a.kind == TRIG_DST1) && a.dcs;
   if (a.kind == TRIG_DCT1) {
     if (!half)
       for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];           // even extension
   } else if (a.kind == TRIG_DST1) {
-    for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));   // odd extension
+    if (!half)
+      for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));   // odd extension
   } else if (qw && !a.inverse) {
     // samples N+1 .. 2N-1 of the quarter-wave extension: +x (QWS) / -x (QWC) at 2N - j
     const T sg = a.kind == TRIG_QWS ? T(1) : T(-1);
@@ -703,10 +729,10 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   }
   __syncthreads();
   cpx<T> z1 = {T(0), T(0)};
-  if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
+  if (half) z1 = trig1_pre<T>(buf, a.plan, a.dcs, a.kind == TRIG_DST1, lt, TL);
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
   line_dft<T, false, W>(buf, a.plan, lt, TL, cj, cj);
-  if (half) dct1_post<T>(buf, a.plan, z1, lt, TL);
+  if (half) trig1_post<T>(buf, a.plan, z1, a.kind == TRIG_DST1, lt, TL);
 
   // ---- results
   if (!a.inverse) {
@@ -800,21 +826,22 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
     for (int j = n + lt; j < L; j += TL) buf[j] = buf[L - j];
   } else if (a.kind == TRIG_DST1) {
     // odd extension: positions 0 and n-1 are zero, j > n-1 holds -buf[L-j]
+    // (none at length N)
     if (lt == 0) {
       buf[0] = {T(0), T(0)};
       buf[n - 1] = {T(0), T(0)};
     }
-    for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));
+    if (!a.dcs)
+      for (int j = n + lt; j < L; j += TL) buf[j] = cscale(buf[L - j], T(-1));
   }
   __syncthreads();
-  const bool half = a.kind == TRIG_DCT1 && a.dcs;
+  const bool half = (a.kind == TRIG_DCT1 || a.kind == TRIG_DST1) && a.dcs;
   cpx<T> z1 = {T(0), T(0)};
-  if (half) z1 = dct1_pre<T>(buf, a.plan, a.dcs, lt, TL);
+  if (half) z1 = trig1_pre<T>(buf, a.plan, a.dcs, a.kind == TRIG_DST1, lt, TL);
   const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
   line_dft<T, false, W>(buf, a.plan, lt, TL, cj, cj);
-  if (half) {
-    dct1_post<T>(buf, a.plan, z1, lt, TL);
-  } else if (qw && !is_values) {
+  if (half) trig1_post<T>(buf, a.plan, z1, a.kind == TRIG_DST1, lt, TL);
+  if (qw && !is_values) {
     // F = 2i W (QWS), 2 W (QWC); position N holds no mode
     for (int j = lt; j < n; j += TL) {
       const cpx<T> w = buf[j];
