@@ -157,9 +157,10 @@ fcsph_status fcsph_plan_workspace_bytes(const fcsph_desc *d, size_t *bytes);
  * up to 4096 (operators) or 8192 (PPE), and a length beyond that is
  * FCSPH_E_UNSUPPORTED (in practice: lattice sides above about 2020 on the
  * whole-period and direct routes, whose plans hold whole-period transforms;
- * on the windowed route up to 4092 with Neumann pressure walls in FP64, and
- * up to 2049 where the PPE needs a transform of length 2(n - 1), depending
- * on its factors). */
+ * on the windowed route up to about 3050 with Neumann or Dirichlet pressure
+ * walls in FP64 (the PPE at length n - 1), and up to 2049 where the
+ * PPE needs a transform of length 2(n - 1) (the FP32 form, mixed walls),
+ * depending on the factors). */
 fcsph_status fcsph_plan_create(fcsph_ctx *c, const fcsph_desc *d, void *workspace,
                                size_t bytes, fcsph_plan **out);
 fcsph_status fcsph_plan_destroy(fcsph_plan *p);
