@@ -213,6 +213,19 @@ struct Dft {
   }
 };
 
+// j mod Ns for 0 <= j < 2^13, 1 <= Ns <= 2^13 (line work lengths stay below
+// 8192): a float quotient with rns = 1 / Ns is off by at most one and one
+// correction step in each direction makes it exact (checked for every pair
+// in range).  Full-rate float and 24-bit integer operations instead of the
+// runtime integer division (quarter-rate 32-bit multiplies).
+__device__ __forceinline__ int mod_small(int j, int Ns, float rns) {
+  const int q = (int)((float)j * rns);
+  int k = j - __mul24(q, Ns);
+  k = k >= Ns ? k - Ns : k;
+  k = k < 0 ? k + Ns : k;
+  return k;
+}
+
 // Radices 2, 4 and 8 compute in registers and then store.
 template <typename T, int R>
 __device__ __forceinline__ constexpr bool is_pow2_radix() { return R == 2 || R == 3 || R == 4 || R == 8; }
@@ -224,6 +237,7 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
   constexpr int NB = nb_max(R, WIDE);
   const int NR = N / R;
   const int tstride = N / (Ns * R);
+  const float rns = 1.0f / (float)Ns;
   cpx<T> v[NB][R];
   cpx<T> w1[NB];
 #pragma unroll
@@ -231,11 +245,11 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
     const int j = lt + b * TL;
     if (active && j < NR) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NR];
+      for (int r = 0; r < R; ++r) v[b][r] = buf[j + __mul24(r, NR)];
       // radix <= 8: one twiddle per butterfly, loaded before the barrier (its
       // latency hides behind the barrier), its powers formed by products of
       // depth <= 3; larger radices load each twiddle
-      if constexpr (R <= 8) w1[b] = tw[(j % Ns) * tstride];
+      if constexpr (R <= 8) w1[b] = tw[__mul24(mod_small(j, Ns, rns), tstride)];
     }
   }
   __syncthreads();
@@ -243,7 +257,7 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
   for (int b = 0; b < NB; ++b) {
     const int j = lt + b * TL;
     if (active && j < NR) {
-      const int k = j % Ns;
+      const int k = mod_small(j, Ns, rns);
       if (k != 0) {
         if constexpr (R <= 4) {
           cpx<T> t = w1[b];
@@ -271,13 +285,13 @@ __device__ __forceinline__ void stockham_stage(Line<T> buf, int N, int Ns, const
           for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * tstride]);
         }
       }
-      const int o = (j - k) * R + k;
+      const int o = __mul24(j - k, R) + k;
       if constexpr (is_pow2_radix<T, R>()) {
         Dft<T, R>::run(v[b], tw, NR);
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
+        for (int r = 0; r < R; ++r) buf[o + __mul24(r, Ns)] = v[b][r];
       } else {
-        Dft<T, R>::run_store(v[b], tw, NR, [&](int r, cpx<T> val) { buf[o + r * Ns] = val; });
+        Dft<T, R>::run_store(v[b], tw, NR, [&](int r, cpx<T> val) { buf[o + __mul24(r, Ns)] = val; });
       }
     }
   }

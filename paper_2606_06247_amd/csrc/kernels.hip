@@ -381,6 +381,14 @@ __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_
 template <typename T>
 __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const cpx<T> *in,
                                           int c0, size_t obase, int n) {
+  if (a.B == 1) {
+    // one column per workgroup (the default): no division by the panel width
+    const bool ok = c0 < a.ninner;
+    batched<8, cpx<T>>(threadIdx.x, n, blockDim.x,
+                       [&](int j) { return ok ? in[obase + (size_t)j * a.es + c0] : cpx<T>{T(0), T(0)}; },
+                       [&](int j, cpx<T> v) { Line<T>{smem}[j] = v; });
+    return;
+  }
   batched<8, cpx<T>>(threadIdx.x, a.B * n, blockDim.x,
                      [&](int idx) {
                        const int l = idx % a.B, j = idx / a.B;
@@ -396,6 +404,12 @@ __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const
 template <typename T>
 __device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem, cpx<T> *out,
                                            int c0, size_t obase, int n) {
+  if (a.B == 1) {
+    if (c0 < a.ninner)
+      for (int j = threadIdx.x; j < n; j += blockDim.x)
+        out[obase + (size_t)j * a.es_out + c0] = Line<T>{const_cast<cpx<T> *>(smem)}[j];
+    return;
+  }
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
     const int c = c0 + l;
