@@ -896,16 +896,24 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
   cpx<T> *data = static_cast<cpx<T> *>(a.data) + (size_t)o * a.os;
   const int n = a.nline;
 
-  batched<8, cpx<T>>(threadIdx.x, a.B * n, blockDim.x,
-                     [&](int idx) {
-                       const int l = idx % a.B, j = idx / a.B;
-                       const int cc = c0 + l;
-                       return cc < a.ninner ? data[(size_t)j * a.es + cc] : cpx<T>{T(0), T(0)};
-                     },
-                     [&](int idx, cpx<T> v) {
-                       const int l = idx % a.B, j = idx / a.B;
-                       Line<T>{smem + (size_t)l * a.ldsM}[j] = v;
-                     });
+  if (a.B == 1) {
+    // one column pair per workgroup (the default): no division by the panel width
+    const bool ok = c0 < a.ninner;
+    batched<8, cpx<T>>(threadIdx.x, n, blockDim.x,
+                       [&](int j) { return ok ? data[(size_t)j * a.es + c0] : cpx<T>{T(0), T(0)}; },
+                       [&](int j, cpx<T> v) { Line<T>{smem}[j] = v; });
+  } else {
+    batched<8, cpx<T>>(threadIdx.x, a.B * n, blockDim.x,
+                       [&](int idx) {
+                         const int l = idx % a.B, j = idx / a.B;
+                         const int cc = c0 + l;
+                         return cc < a.ninner ? data[(size_t)j * a.es + cc] : cpx<T>{T(0), T(0)};
+                       },
+                       [&](int idx, cpx<T> v) {
+                         const int l = idx % a.B, j = idx / a.B;
+                         Line<T>{smem + (size_t)l * a.ldsM}[j] = v;
+                       });
+  }
   __syncthreads();
   // solve == 0: forward only; 1: forward, divide, inverse; 2: inverse only
   const int npass = a.solve == 1 ? 2 : 1;
@@ -937,6 +945,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
       }
       __syncthreads();
     }
+  }
+  if (a.B == 1) {
+    if (c0 < a.ninner)
+      for (int j = threadIdx.x; j < n; j += blockDim.x) data[(size_t)j * a.es + c0] = Line<T>{smem}[j];
+    return;
   }
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
