@@ -399,6 +399,7 @@ struct fcsph_plan {
   const double *mu[3] = {nullptr, nullptr, nullptr};
   const void *qtw[3] = {nullptr, nullptr, nullptr};   // quarter-wave pre-twiddles
   const double2 *dcs[3] = {nullptr, nullptr, nullptr};  // DCT-I at length N: (cos, sin)(pi j / N)
+  const double2 *symR2 = nullptr;   // 2D: tabulated symbol line coefficients
   // symbols
   SymTables st{};
   // scratch
@@ -616,6 +617,33 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       p->st.ph[a] = (const double2 *)u.dst;
       up.push_back(std::move(u));
     }
+    if (p->nd == 2) {
+      // line coefficients along y of every symbol at every x wavenumber k of
+      // the half spectrum: R[sl] = sum_sx W[sl][sx] exp(-2 pi i k sx / E_x)
+      // (uniform across a column's workgroup; tabulated once instead of per
+      // column and pass)
+      const int Ex = p->E[0], Hx = Ex / 2 + 1;
+      Upload u;
+      u.data.resize((size_t)4 * Hx * kSymW * sizeof(double2));
+      double2 *t = (double2 *)u.data.data();
+      for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < Hx; ++k)
+          for (int sl = -kSymR; sl <= kSymR; ++sl) {
+            LD re = 0.0L, im = 0.0L;
+            for (int sx = -kSymR; sx <= kSymR; ++sx) {
+              const LD w = (LD)W[q][(sl + kSymR) * kSymW + (sx + kSymR)];
+              if (w == 0.0L) continue;
+              const long long m = (((long long)k * sx) % Ex + Ex) % Ex;
+              const LD ang = -2.0L * kPi * (LD)m / (LD)Ex;
+              re += w * cosl(ang);
+              im += w * sinl(ang);
+            }
+            t[((size_t)q * Hx + k) * kSymW + sl + kSymR] = make_double2((double)re, (double)im);
+          }
+      u.dst = ws.take(u.data.size());
+      p->symR2 = (const double2 *)u.dst;
+      up.push_back(std::move(u));
+    }
   }
   // PPE plans and eigenvalues
   for (int a = 0; a < p->nd; ++a) {
@@ -824,6 +852,7 @@ ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
   c.line_axis = 1;
   c.inner_axis = 0;
   c.outer_axis = -1;
+  c.symR = p->symR2;
   c.B = pick_B(c.plan, p->fp32, p->want_B, cols_lines_per_column(mode));
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;

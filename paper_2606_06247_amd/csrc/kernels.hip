@@ -360,6 +360,18 @@ __device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int ki
   }
 }
 
+// Line coefficients of symbol q at inner wavenumber kin: from the plan's table
+// (2D column passes) or computed.
+__device__ __forceinline__ void line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
+  if (a.symR) {
+    const double2 *t = a.symR + ((size_t)q * a.ninner + kin) * kSymW;
+#pragma unroll
+    for (int s = 0; s < kSymW; ++s) R[s] = t[s];
+    return;
+  }
+  sym_line_coeffs(a, q, kin, kout, R);
+}
+
 __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
   // exp(-2 pi i k s / E) for s = 1 from the table, s = 2, 3 by products
   double2 p[kSymR + 1];
@@ -492,7 +504,7 @@ k_cols(KArg<ColsArgs, G> ka) {
         }
       } else {
         double2 R[kSymW];
-        sym_line_coeffs(a, a.sym[pass - 1], c < a.ninner ? c : 0, o, R);
+        line_coeffs(a, a.sym[pass - 1], c < a.ninner ? c : 0, o, R);
         __syncthreads();   // the previous output's store has finished reading buf
         for (int k = lt; k < E; k += TL) {
           const double2 sv = sym_eval(R, ph_line, k);
@@ -530,7 +542,7 @@ k_cols(KArg<ColsArgs, G> ka) {
       line_dft<T>(buf, a.plan, lt, TL, pass == nin, pass == nin);
       if (pass < nin) {
         double2 R[kSymW];
-        sym_line_coeffs(a, a.sym[pass], c < a.ninner ? c : 0, o, R);
+        line_coeffs(a, a.sym[pass], c < a.ninner ? c : 0, o, R);
         for (int k = lt; k < E; k += TL) {
           const double2 sv = sym_eval(R, ph_line, k);
           acc[k] = cadd(acc[k], cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
