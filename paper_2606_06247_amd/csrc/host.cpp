@@ -399,7 +399,8 @@ struct fcsph_plan {
   const double *mu[3] = {nullptr, nullptr, nullptr};
   const void *qtw[3] = {nullptr, nullptr, nullptr};   // quarter-wave pre-twiddles
   const double2 *dcs[3] = {nullptr, nullptr, nullptr};  // DCT-I at length N: (cos, sin)(pi j / N)
-  const double2 *symR2 = nullptr;   // 2D: tabulated symbol line coefficients
+  const double2 *symR2 = nullptr;   // 2D: tabulated symbol line coefficients (y lines)
+  const double2 *symR3 = nullptr;   // 3D: the same for the z lines (inner x, outer y)
   // symbols
   SymTables st{};
   // scratch
@@ -642,6 +643,43 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
           }
       u.dst = ws.take(u.data.size());
       p->symR2 = (const double2 *)u.dst;
+      up.push_back(std::move(u));
+    }
+    if (p->nd == 3) {
+      // z lines: R[sl] = sum_{sy, sx} W[sl][sy][sx] exp(-2 pi i (k sx / E_x + o sy / E_y))
+      // for k < E_x / 2 + 1 (x half spectrum) and o < E_y (y-extended rows)
+      const int Ex = p->E[0], Ey = p->E[1], Hx = Ex / 2 + 1;
+      auto phase = [](int k, int s, int E) {
+        const long long m = (((long long)k * s) % E + E) % E;
+        const LD ang = -2.0L * kPi * (LD)m / (LD)E;
+        return std::make_pair(cosl(ang), sinl(ang));
+      };
+      std::vector<std::pair<LD, LD>> px((size_t)Hx * kSymW), py((size_t)Ey * kSymW);
+      for (int k = 0; k < Hx; ++k)
+        for (int sx = -kSymR; sx <= kSymR; ++sx) px[(size_t)k * kSymW + sx + kSymR] = phase(k, sx, Ex);
+      for (int o = 0; o < Ey; ++o)
+        for (int sy = -kSymR; sy <= kSymR; ++sy) py[(size_t)o * kSymW + sy + kSymR] = phase(o, sy, Ey);
+      Upload u;
+      u.data.resize((size_t)4 * Hx * Ey * kSymW * sizeof(double2));
+      double2 *t = (double2 *)u.data.data();
+      for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < Hx; ++k)
+          for (int o = 0; o < Ey; ++o)
+            for (int sl = -kSymR; sl <= kSymR; ++sl) {
+              LD re = 0.0L, im = 0.0L;
+              for (int sy = -kSymR; sy <= kSymR; ++sy)
+                for (int sx = -kSymR; sx <= kSymR; ++sx) {
+                  const LD w = (LD)W[q][((sl + kSymR) * kSymW + (sy + kSymR)) * kSymW + (sx + kSymR)];
+                  if (w == 0.0L) continue;
+                  const auto &a = px[(size_t)k * kSymW + sx + kSymR];
+                  const auto &b = py[(size_t)o * kSymW + sy + kSymR];
+                  re += w * (a.first * b.first - a.second * b.second);
+                  im += w * (a.first * b.second + a.second * b.first);
+                }
+              t[(((size_t)q * Hx + k) * Ey + o) * kSymW + sl + kSymR] = make_double2((double)re, (double)im);
+            }
+      u.dst = ws.take(u.data.size());
+      p->symR3 = (const double2 *)u.dst;
       up.push_back(std::move(u));
     }
   }
@@ -984,6 +1022,7 @@ ColsArgs z_pass_args(fcsph_plan *p, int mode) {
   c.line_axis = 2;
   c.inner_axis = 0;
   c.outer_axis = 1;
+  c.symR = p->symR3;
   c.B = pick_B(c.plan, p->fp32, p->want_B, cols_lines_per_column(mode));
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;

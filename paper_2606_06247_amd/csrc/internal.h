@@ -192,9 +192,10 @@ struct ColsArgs {
   // plane, per input field: edge[f][((h * nouter + o) * d + r) * ninner + c]
   // (h = 0 low rows, 1 high rows), the inputs of FC along the line in FP64
   const double2 *edge[3];
-  // 2D column passes: the line coefficients of every symbol at every inner
-  // wavenumber, symR[(q * ninner + k) * kSymW + sl + R] (what sym_line_coeffs
-  // computes, tabulated at plan creation); null: computed in the kernel
+  // symbol passes: the line coefficients of every symbol at every inner and
+  // outer wavenumber, symR[((q * ninner + k) * nouter + o) * kSymW + sl + R]
+  // (what sym_line_coeffs computes, tabulated at plan creation; 2D: one
+  // outer index); null: computed in the kernel
   const double2 *symR;
 };
 

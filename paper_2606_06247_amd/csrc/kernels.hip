@@ -364,7 +364,7 @@ __device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int ki
 // (2D column passes) or computed.
 __device__ __forceinline__ void line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
   if (a.symR) {
-    const double2 *t = a.symR + ((size_t)q * a.ninner + kin) * kSymW;
+    const double2 *t = a.symR + (((size_t)q * a.ninner + kin) * a.nouter + (kout < 0 ? 0 : kout)) * kSymW;
 #pragma unroll
     for (int s = 0; s < kSymW; ++s) R[s] = t[s];
     return;
