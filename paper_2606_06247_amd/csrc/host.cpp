@@ -596,13 +596,6 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     wendland_taps(p->nd, d->dx, d->h_over_dx, p->E, W);
     p->st.ndim = p->nd;
     for (int a = 0; a < 3; ++a) p->st.E[a] = p->E[a];
-    for (int q = 0; q < 4; ++q) {
-      Upload u;
-      u.data.assign((const char *)W[q].data(), (const char *)(W[q].data() + W[q].size()));
-      u.dst = ws.take(u.data.size());
-      p->st.W[q] = (const double *)u.dst;
-      up.push_back(std::move(u));
-    }
     for (int a = 0; a < p->nd; ++a) {
       Upload u;
       const int E = p->E[a];

@@ -92,13 +92,12 @@ __host__ __device__ inline int fc_slot(const FcWalls &fc, int n, int L, int j) {
   return t <= fc.tail ? fc.C - t : -1;
 }
 
-// Spectral symbol of one operator: dense tap weights (already scaled by
-// 1/prod(E_a)) on a kSymW^ndim cube, and per-axis phase tables
-// ph_a[k * (kSymR+1) + s] = exp(-2 pi i k s / E_a), s = 0..kSymR.
+// Spectral symbols: per-axis phase tables ph_a[k * (kSymR+1) + s] =
+// exp(-2 pi i k s / E_a), s = 0..kSymR, for the sum along the line axis (the
+// transverse sums are tabulated per plan, ColsArgs::symR).
 struct SymTables {
   int ndim;
   int E[3];
-  const double *W[4];        // grad x, grad y, grad z, lap
   const double2 *ph[3];      // per axis phase table (FP64)
 };
 
@@ -192,10 +191,9 @@ struct ColsArgs {
   // plane, per input field: edge[f][((h * nouter + o) * d + r) * ninner + c]
   // (h = 0 low rows, 1 high rows), the inputs of FC along the line in FP64
   const double2 *edge[3];
-  // symbol passes: the line coefficients of every symbol at every inner and
-  // outer wavenumber, symR[((q * ninner + k) * nouter + o) * kSymW + sl + R]
-  // (what sym_line_coeffs computes, tabulated at plan creation; 2D: one
-  // outer index); null: computed in the kernel
+  // symbol passes (OP, DIV): the line coefficients of every symbol at every
+  // inner and outer wavenumber, symR[((q * ninner + k) * nouter + o) * kSymW
+  // + sl + R], tabulated at plan creation (2D: one outer index)
   const double2 *symR;
 };
 

@@ -290,86 +290,20 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
 }
 
 // ============================================================= strided passes
-// Phase factor exp(-2 pi i k s / E) from a per-axis table (s may be negative).
-__device__ __forceinline__ double2 phase(const double2 *ph, int k, int s) {
-  const int as = s < 0 ? -s : s;
-  double2 v = ph[(size_t)k * (kSymR + 1) + as];
-  if (s < 0) v.y = -v.y;
-  return v;
-}
-
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 // Coefficients R[s] (s = -kSymR..kSymR along the line axis) of the symbol of
-// operator q at fixed wavenumbers of the transverse axes:
-//   S(k) = sum_s R[s] exp(-2 pi i k_line s / E_line).
-__device__ __forceinline__ void sym_line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
-  // R[sl + kSymR] = sum over the other offsets of the tap weight times the
-  // phases of the other axes' wavenumbers.  All loads are independent and
-  // issued up front (no branches on loaded values): the phases of the inner
-  // (and outer) wavenumber once, the tap weights (uniform across the
-  // workgroup) as one batch.
-  const double *W = a.st.W[q];
-  double2 pin[kSymR + 1];
-#pragma unroll
-  for (int s = 0; s <= kSymR; ++s) pin[s] = a.st.ph[a.inner_axis][(size_t)kin * (kSymR + 1) + s];
-  if (a.st.ndim == 2) {
-    // W[(sy + R) * kSymW + (sx + R)]; line axis y, inner axis x (or the reverse)
-    const int stl = a.line_axis == 1 ? kSymW : 1;
-    const int sti = a.line_axis == 1 ? 1 : kSymW;
-#pragma unroll
-    for (int sl = -kSymR; sl <= kSymR; ++sl) {
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int si = -kSymR; si <= kSymR; ++si) {
-        const double w = W[(sl + kSymR) * stl + (si + kSymR) * sti];
-        const double2 p = pin[si < 0 ? -si : si];
-        acc.x += w * p.x;
-        acc.y += w * (si < 0 ? -p.y : p.y);
-      }
-      R[sl + kSymR] = acc;
-    }
-  } else {
-    // W[(sz + R) * kSymW^2 + (sy + R) * kSymW + (sx + R)]: index strides per axis
-    const int stl = a.line_axis == 0 ? 1 : a.line_axis == 1 ? kSymW : kSymW * kSymW;
-    const int sti = a.inner_axis == 0 ? 1 : a.inner_axis == 1 ? kSymW : kSymW * kSymW;
-    const int sto = a.outer_axis == 0 ? 1 : a.outer_axis == 1 ? kSymW : kSymW * kSymW;
-#pragma unroll
-    for (int s = 0; s < kSymW; ++s) R[s] = make_double2(0.0, 0.0);
-    const double2 *pho = a.st.ph[a.outer_axis] + (size_t)kout * (kSymR + 1);
-#pragma unroll 1
-    for (int so = -kSymR; so <= kSymR; ++so) {
-      double2 po = pho[so < 0 ? -so : so];
-      if (so < 0) po.y = -po.y;
-      const double *Wo = W + (so + kSymR) * sto;
-#pragma unroll
-      for (int si = -kSymR; si <= kSymR; ++si) {
-        double2 pi_ = pin[si < 0 ? -si : si];
-        if (si < 0) pi_.y = -pi_.y;
-        const double2 p = zmul(pi_, po);
-#pragma unroll
-        for (int sl = -kSymR; sl <= kSymR; ++sl) {
-          const double w = Wo[(sl + kSymR) * stl + (si + kSymR) * sti];
-          R[sl + kSymR].x += w * p.x;
-          R[sl + kSymR].y += w * p.y;
-        }
-      }
-    }
-  }
-}
-
-// Line coefficients of symbol q at inner wavenumber kin: from the plan's table
-// (2D column passes) or computed.
+// operator q at fixed wavenumbers of the transverse axes,
+//   S(k) = sum_s R[s] exp(-2 pi i k_line s / E_line),
+// read from the plan's table (tabulated at plan creation: R[s] is the sum over
+// the other offsets of the tap weight times the phases of the other axes'
+// wavenumbers).  Uniform across a column's workgroup.
 __device__ __forceinline__ void line_coeffs(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
-  if (a.symR) {
-    const double2 *t = a.symR + (((size_t)q * a.ninner + kin) * a.nouter + (kout < 0 ? 0 : kout)) * kSymW;
+  const double2 *t = a.symR + (((size_t)q * a.ninner + kin) * a.nouter + (kout < 0 ? 0 : kout)) * kSymW;
 #pragma unroll
-    for (int s = 0; s < kSymW; ++s) R[s] = t[s];
-    return;
-  }
-  sym_line_coeffs(a, q, kin, kout, R);
+  for (int s = 0; s < kSymW; ++s) R[s] = t[s];
 }
 
 __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
@@ -1075,6 +1009,8 @@ hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s)
   const dim3 grid(npanel * a.nouter, ngrid_y), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B * cols_lines_per_column(a.mode), a.ldsM, fp32);
   if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+  // the symbol passes read their line coefficients from the plan's table
+  if ((a.mode == COLS_OP || a.mode == COLS_DIV) && !a.symR) return hipErrorInvalidValue;
   return fp32 ? cols_dispatch<float>(a, grid, block, lds, s) : cols_dispatch<double>(a, grid, block, lds, s);
 }
 
