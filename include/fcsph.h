@@ -87,8 +87,8 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *              FCSPH_OPS_FFT_WINDOW (>= n + 2R, a product of radices 2, 3, 4,
  *              5, 7, 8 whose stages fit 512 threads per line), and the upper
  *              bound on lines per workgroup of the line kernels (1..16;
- *              default 1 in 2D, 4 in 3D).  They change speed, never the
- *              result beyond rounding.
+ *              default 1).  They change speed, never the result beyond
+ *              rounding.
  */
 typedef struct {
   int ndim;

@@ -517,11 +517,9 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->fp32 = d->prec == FCSPH_FP32_MIXED;
   p->nd = d->ndim;
   p->window = d->op_eval == FCSPH_OPS_FFT_WINDOW;
-  // unless asked: one line per workgroup in 2D (the tuner's choice at every
-  // size it timed, 64..1024: more workgroups in flight per CU), four in 3D
-  // (256^3: 7.77 ms per step against 8.11 with one; its short z and y lines
-  // then read four adjacent columns per element, coalesced)
-  p->want_B = d->lines_per_group > 0 ? d->lines_per_group : (d->ndim == 3 ? 4 : 1);
+  // one line per workgroup unless asked: the schedule tuner picked it at
+  // every lattice size it timed (more workgroups in flight per CU)
+  p->want_B = d->lines_per_group > 0 ? d->lines_per_group : 1;
   {
     std::vector<Tap> tl = wendland_tap_list(d->ndim, d->dx, d->h_over_dx, p->reach);
   }
