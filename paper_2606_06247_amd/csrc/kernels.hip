@@ -388,11 +388,12 @@ __device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, 
   }
 }
 
-// At most 168 VGPRs (3 waves per SIMD): the FP64 instantiations need 137 and
-// are unchanged; the FP32 ones (FP64 symbol coefficients and FC inputs) came
-// out at 171, one wave per SIMD fewer, and fit the cap without spills.
+// At most 128 VGPRs (4 waves per SIMD): with the symbol coefficients read from
+// the plan's table the column kernels need 105-137; capped, only the FP64
+// operator form spills (12 B per lane), and the 1024^2 step gains 1 %, the
+// 256^3 step 2.5 % (four 4-wave workgroups per CU, as the LDS allows).
 template <typename T, int MODE, bool G>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_cols(KArg<ColsArgs, G> ka) {
   const ColsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
