@@ -584,7 +584,7 @@ def main() -> int:
         print(json.dumps({"copy_probe_MiB": args.copy_probe, "bytes": src.numel() * 8}))
         return 0
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
+        print("bench.py: the library runs one lattice per GPU in one process; --gpus must be 1 (there is no multi-GPU path)", file=sys.stderr)
         return 2
     n = args.n
     from paper_2606_06247_amd import api as _api, tune
