@@ -403,7 +403,27 @@ k_cols(KArg<ColsArgs, G> ka) {
   const int lt = threadIdx.x - g * TL;
   Line<T> buf{smem + (size_t)g * a.ldsM};
   const int npanel = (a.ninner + a.B - 1) / a.B;
-  const int bid = xcd_panel(blockIdx.x, gridDim.x);
+  // task = (input field f, panel); normally f = blockIdx.y.  A split launch
+  // (COLS_OP only) numbers the tasks linearly, field-major: workgroup b <
+  // nfull runs task b whole, a later one runs output qsel of task
+  // nfull + (b - nfull) / nout.  Every output is formed by the same code
+  // either way.
+  int f = blockIdx.y, bx = blockIdx.x, nbx = gridDim.x, qsel = -1;
+  if constexpr (!G && MODE == COLS_OP) {
+    if (a.nfull > 0) {
+      const int npo = npanel * a.nouter;
+      int t = blockIdx.x;
+      if (t >= a.nfull) {
+        const int r = t - a.nfull, q = r / a.nout;
+        t = a.nfull + q;
+        qsel = r - q * a.nout;
+      }
+      f = t / npo;
+      bx = t - f * npo;
+      nbx = npo;
+    }
+  }
+  const int bid = xcd_panel(bx, nbx);
   const int o = bid / npanel;
   const int c0 = (bid - o * npanel) * a.B;
   const int c = c0 + g;
@@ -412,7 +432,6 @@ k_cols(KArg<ColsArgs, G> ka) {
   const double2 *ph_line = a.st.ph[a.line_axis];
 
   if constexpr (MODE == COLS_FWD || MODE == COLS_INV) {
-    const int f = blockIdx.y;
     const cpx<T> *in = static_cast<const cpx<T> *>(a.in[f]);
     cols_load<T>(a, smem, in, c0, obase_in, a.nload);
     __syncthreads();
@@ -428,8 +447,8 @@ k_cols(KArg<ColsArgs, G> ka) {
     // symbol q times xb, inverse DFT, store.  One transform call site keeps
     // the kernel's register footprint at that of a single transform.
     Line<T> xb{smem + (size_t)(a.B + g) * a.ldsM};
-    const int f = blockIdx.y;
     for (int pass = 0; pass <= a.nout; ++pass) {
+      if (pass > 0 && qsel >= 0 && pass != qsel + 1) continue;   // uniform per workgroup
       if (pass == 0) {
         cols_load<T>(a, smem, static_cast<const cpx<T> *>(a.in[f]), c0, obase_in, a.nload);
         __syncthreads();
@@ -1005,6 +1024,28 @@ static hipError_t cols_dispatch(const ColsArgs &a, dim3 grid, dim3 block, size_t
   return hipErrorInvalidValue;
 }
 
+// Workgroups of the one-problem COLS_OP kernel resident on the whole device
+// at once (0 if unknown).  Cached per host thread for the last shape asked.
+template <typename T>
+static int cols_op_slots(int block, size_t lds) {
+  struct Entry {
+    int dev = -1, block = 0, slots = 0;
+    size_t lds = 0;
+  };
+  thread_local Entry e;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (e.dev == dev && e.block == block && e.lds == lds) return e.slots;
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (set_kernel_lds(k_cols<T, COLS_OP, false>, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cols<T, COLS_OP, false>, block, lds) !=
+      hipSuccess)
+    return 0;
+  e = Entry{dev, block, per * cus, lds};
+  return e.slots;
+}
+
 hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s) {
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const dim3 grid(npanel * a.nouter, ngrid_y), block(a.B * a.plan.TL);
@@ -1012,6 +1053,24 @@ hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s)
   if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
   // the symbol passes read their line coefficients from the plan's table
   if ((a.mode == COLS_OP || a.mode == COLS_DIV) && !a.symR) return hipErrorInvalidValue;
+  if (a.nfull != 0) return hipErrorInvalidValue;
+  // Tail split: when the tasks (field, panel) exceed the resident workgroups
+  // by at most a third of them divided by the outputs, the leftover tasks
+  // would run as a second, nearly empty round of whole tasks (forward + nout
+  // inverse transforms).  Their outputs go to separate workgroups instead
+  // (forward + one inverse each), which fill one round after the first.
+  // The 1024^2 stage-A pass has 1122 tasks for 1024 resident workgroups.
+  if (a.mode == COLS_OP && a.nout > 1 && !active_recorder()) {
+    const long tasks = (long)grid.x * ngrid_y;
+    const int slots = fp32 ? cols_op_slots<float>(block.x, lds) : cols_op_slots<double>(block.x, lds);
+    const long rest = tasks - slots;
+    if (slots > 0 && rest > 0 && rest * a.nout <= slots) {
+      ColsArgs b = a;
+      b.nfull = slots;
+      const dim3 g2((unsigned)(slots + rest * a.nout), 1);
+      return fp32 ? cols_dispatch<float>(b, g2, block, lds, s) : cols_dispatch<double>(b, g2, block, lds, s);
+    }
+  }
   return fp32 ? cols_dispatch<float>(a, grid, block, lds, s) : cols_dispatch<double>(a, grid, block, lds, s);
 }
 

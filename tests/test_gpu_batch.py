@@ -189,3 +189,28 @@ def test_batch_tuned_schedules_bitwise(ctx):
         for a in range(2):
             assert torch.equal(plain[i][a], batched[i][a]), (i, a, float((plain[i][a] - batched[i][a]).abs().max()))
         assert torch.equal(pp[i], pb[i]), i
+
+
+@pytest.mark.parametrize("prec,oe", [("fp64", "fft_window"), ("fp32", "fft_window"), ("fp64", "fft")])
+def test_tail_split_bitwise_1024(ctx, prec, oe):
+    """At 1024^2 the one-problem stage-A column pass has more (field, column)
+    tasks than resident workgroups on MI355X and splits the leftover tasks'
+    outputs over separate workgroups; the grouped (batched) launch never
+    splits.  Both must give the same step bitwise."""
+    import torch
+    from paper_2606_06247_amd import api
+    s = spec((1024, 1024), (True, True), vel=(("D", "D"), ("D", "D")), prs=(("N", "N"), ("N", "N")))
+    plan = api.Plan(ctx, problem(s, precision=prec, op_eval=oe))
+    u = make_inputs(s, 77)
+    plain = [to_dev(c) for c in u]
+    batched = [to_dev(c) for c in u]
+    wall = [to_dev(c) for c in u]
+    pp, pb = torch.empty_like(plain[0]), torch.empty_like(plain[0])
+    plan.project_step(plain, 1e-4, 1e-3, p_out=pp, wall=wall)
+    b = api.Batch(ctx, 1)
+    b.add_step(plan, batched, 1e-4, 1e-3, p_out=pb, wall=wall)
+    b.launch()
+    torch.cuda.synchronize()
+    for a in range(2):
+        assert torch.equal(plain[a], batched[a]), (a, float((plain[a] - batched[a]).abs().max()))
+    assert torch.equal(pp, pb)
