@@ -25,10 +25,23 @@ Modes:
   symbol sum vanishes are left untouched), u_hat -= (dt/rho) S_a phi_hat.  This
   definition is spectral, so the oracle uses numpy's FFT for it.
 
+Low-storage RK3 (``rk3_substep``): the same equations with the RK3
+coefficient table of that section, sub-step k = 0, 1, 2:
+* F^k = (u^k . grad) u^k - nu lap u^k  (sign reading as above);
+* u* = u^k - dt [ g_k F^k + z_k F^{k-1} - a_k f ]  (pressure term dropped as
+  in the first-order form; f is the forcing averaged over the sub-step);
+* lap phi = rho / (a_k dt) div u*  (a_k read as dividing dt, the form that
+  makes u^{k+1} below divergence-free; identical for a_k = 1);
+* u^{k+1} = u* - a_k (dt / rho) grad phi;  Dirichlet walls as above.
+
 Parity: built from pinned parts (operators, PPE, FC); the step itself is pinned
 by the projection identities P-PRJ1/P-PRJ2 and by direct-vs-fft mode agreement
-in ``tests/test_oracle_step.py``.  Multi-step trajectories: parity unpinned
-beyond those.
+in ``tests/test_oracle_step.py``.  The RK3 sub-steps are pinned by the
+stability polynomial 1 + z + z^2/2 + z^3/6 of a three-stage third-order
+scheme on a forced linear shear mode, and by the projected velocity being
+divergence-free to rounding on an all-periodic lattice with the SPH
+eigenvalue family (``tests/test_oracle_rk3.py``).  Multi-step trajectories:
+parity unpinned beyond those.
 """
 from __future__ import annotations
 
@@ -107,3 +120,37 @@ def project_step(lat, tables, u, force=None, wall=None, dt=1e-4, nu=1e-3, rho=1.
         parts.update(S=S, uhat_new=uhat_new, D=D, phihat=phihat)
         return (unew, phi, parts) if return_parts else (unew, phi)
     raise ValueError(mode)
+
+
+# RK3 coefficient table of the temporal discretisation section
+RK3_A = (8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0)
+RK3_G = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
+RK3_Z = (0.0, -17.0 / 60.0, -5.0 / 12.0)
+
+
+def rk3_substep(lat, tables, u, k, F_prev=None, force=None, wall=None, dt=1e-4, nu=1e-3, rho=1.0,
+                family: str = "spectral", opmode: str = "direct"):
+    """Sub-step k (0, 1, 2) of the low-storage RK3 step of length dt.
+    u: velocity components; F_prev: F of the previous sub-step (ignored for
+    k = 0); force: forcing averaged over the sub-step; wall: Dirichlet data at
+    the end of the sub-step.  Returns (u_new, phi, F)."""
+    a, g, z = RK3_A[k], RK3_G[k], RK3_Z[k]
+    ops = operators.Operators(lat, tables, mode=opmode)
+    nd = lat.ndim
+    u = [np.asarray(c, dtype=np.float64) for c in u]
+    grads = [ops.grad(c, "u") for c in u]            # grads[c][b] = G_b u_c
+    laps = [ops.lap(c, "u") for c in u]
+    F, ustar = [], []
+    for c in range(nd):
+        Fc = sum(u[b] * grads[c][b] for b in range(nd)) - nu * laps[c]
+        Fp = 0.0 if (k == 0 or F_prev is None) else F_prev[c]
+        fc = 0.0 if force is None else force[c]
+        us = u[c] - dt * (g * Fc + z * Fp - a * fc)
+        F.append(Fc)
+        ustar.append(set_dirichlet_walls(us, lat, None if wall is None else wall[c]))
+    b = (rho / (a * dt)) * ops.div(ustar)
+    phi = ppe.solve(b, lat, family=family)
+    gphi = ops.grad(phi, "p")
+    unew = [set_dirichlet_walls(ustar[c] - a * (dt / rho) * gphi[c], lat, None if wall is None else wall[c])
+            for c in range(nd)]
+    return unew, phi, F
