@@ -37,15 +37,20 @@ sys.path.insert(0, ROOT)
 METRIC = "FC-spectral ISPH step Mpts/s + %HBM roofline; batched solves/s, p99 latency"
 HBM_PEAK_GBS = 8000.0
 CYCLE = 25
+# RK3 restart cycle in whole steps: three projections per step, so the corner
+# mode of the four-wall lattice grows three times as fast per step as in FOP
+CYCLE_RK3 = 8
 C_FC = 25
 
 
 # ------------------------------------------------------------------ bytes
-def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0) -> dict:
+def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0, rk3: bool = False) -> dict:
     """Compulsory HBM bytes of one launch of each kernel kind of the 2D n x n
     step (every input read once, every output written once).  State arrays are
     FP64; spectra and derivative outputs are FP64 or FP32; L is the operator
-    transform length of the walled axes (n + C, or the window length)."""
+    transform length of the walled axes (n + C, or the window length).  rk3:
+    the u* epilogue also writes F (2 fields) and, in sub-steps 1 and 2, reads
+    the previous F (2 fields): 10/3 fields more per launch on average."""
     P = n * n
     H = (L or n + C_FC) // 2 + 1
     ce = 8 if fp32 else 16
@@ -53,7 +58,7 @@ def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0) -> dict:
     S = n * H * ce                 # one x half-spectrum array
     R = P * 8                      # one real FP64 field
     Rt = P * te                    # one derivative / rhs field
-    return {
+    out = {
         "rows_fwd_pair": 2 * R + 2 * S,
         "cols_op_step_a": 2 * S + 6 * S,
         "rows_inv_step_a": 6 * S + 4 * R + 2 * R,
@@ -69,6 +74,10 @@ def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0) -> dict:
         "direct_div": 2 * R + Rt,
         "direct_step_d": 5 * R,
     }
+    if rk3:
+        out["rows_inv_step_a"] += 10 * R // 3
+        out["direct_step_a"] += 10 * R // 3
+    return out
 
 
 def algorithmic_bytes_3d(n: int, fp32: bool = False, L: int = 0, force: bool = False) -> dict:
@@ -249,8 +258,10 @@ def rel_l2(a, b) -> float:
 
 
 # ------------------------------------------------------------------ 2D workload
-def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64", schedule=None) -> dict:
-    """Time `steps` FOP steps of the 2D n x n workload."""
+def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64", schedule=None,
+           scheme: str = "fop") -> dict:
+    """Time `steps` FOP steps (scheme "fop") or whole low-storage RK3 steps of
+    three sub-steps (scheme "rk3") of the 2D n x n workload."""
     import torch
 
     from paper_2606_06247_amd import api, synth
@@ -265,12 +276,17 @@ def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64
     A = [torch.from_numpy(c).to(dev) for c in A]
     B = [torch.from_numpy(c).to(dev) for c in B]
     forces, walls = [], []
-    for c in range(CYCLE):
-        th = (c + 0.5) * dt
-        forces.append([(math.exp(-th) * a + math.exp(-2 * th) * b).contiguous() for a, b in zip(A, B)])
-        walls.append([(math.exp(-(c + 1) * dt) * v).contiguous() for v in u0])
+    cycle = CYCLE if scheme == "fop" else CYCLE_RK3
+    # sub-step boundaries within a step (one sub-step for FOP)
+    cs = [0.0, 1.0] if scheme == "fop" else [0.0, 8 / 15, 10 / 15, 1.0]
+    for c in range(cycle):
+        for q in range(len(cs) - 1):
+            th = (c + 0.5 * (cs[q] + cs[q + 1])) * dt
+            forces.append([(math.exp(-th) * a + math.exp(-2 * th) * b).contiguous() for a, b in zip(A, B)])
+            walls.append([(math.exp(-(c + cs[q + 1]) * dt) * v).contiguous() for v in u0])
     u = [c.clone() for c in u0]
     p = torch.empty_like(u0[0])
+    F = [torch.zeros_like(u0[0]) for _ in range(2)]
 
     ctx = api.Context(0)
     prob = api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
@@ -281,18 +297,23 @@ def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64
     plan = api.Plan(ctx, prob)
 
     def step(k):
-        c = k % CYCLE
+        c = k % cycle
         if c == 0:
             u[0].copy_(u0[0])
             u[1].copy_(u0[1])
-        plan.project_step(u, dt, nu, p_out=p, force=forces[c], wall=walls[c])
+        if scheme == "fop":
+            plan.project_step(u, dt, nu, p_out=p, force=forces[c], wall=walls[c])
+        else:
+            for q in range(3):
+                plan.rk3_substep(q, u, F, dt, nu, p_out=p, force=forces[3 * c + q], wall=walls[3 * c + q])
 
     # the timed steps start at k = 0, which restarts the trajectory
     wall_s, gpu_ms, live, profile = timed(ctx, step, steps, warmup)
     ms_per_step = 1e3 * wall_s / steps
     finite = bool(all(torch.isfinite(c).all().item() for c in u))
-    ab = algorithmic_bytes_2d(n, precision == "fp32", plan.transform_lengths()[0])
-    roofline, per_kernel = summarise(live, profile, ab, steps, ms_per_step, f"2d_{n}_{precision}_{op_eval}")
+    ab = algorithmic_bytes_2d(n, precision == "fp32", plan.transform_lengths()[0], rk3=scheme == "rk3")
+    wl = f"2d_{n}_{precision}_{op_eval}" + ("" if scheme == "fop" else "_rk3")
+    roofline, per_kernel = summarise(live, profile, ab, steps, ms_per_step, wl)
     return {"value": round(n * n * steps / wall_s / 1e6, 2), "ms_per_step": round(ms_per_step, 4),
             "gpu_event_ms": round(gpu_ms, 3), "state_finite": finite, "roofline": roofline,
             "kernels": per_kernel, "transform_lengths": plan.transform_lengths()}
@@ -617,6 +638,13 @@ def main() -> int:
                 log(f"variant 2d {n} fp64 {oe}")
                 v = run_2d(oe, n, args.steps, args.warmup, schedule=sched64)
                 var[f"2d_{n}_fp64_{oe}"] = {k: v[k] for k in keep}
+        log(f"variant 2d {n} fp64 {args.op_eval} RK3")
+        v = run_2d(args.op_eval, n, max(1, args.steps // 3), args.warmup, schedule=sched64, scheme="rk3")
+        rec = {k: v[k] for k in keep}
+        rec["workload"] = ("the same 1024^2 workload advanced by whole low-storage RK3 steps (three sub-steps, "
+                           "forcing at sub-step midpoints, wall data at sub-step ends), restart every "
+                           f"{CYCLE_RK3} steps; value = points x RK3 steps / s")
+        var[f"2d_{n}_fp64_{args.op_eval}_rk3"] = rec
         for oe in ("fft", "fft_window", "direct"):
             log(f"variant 2d {n} fp32 {oe}")
             v = run_2d(oe, n, args.steps, args.warmup, precision="fp32", schedule=sched32)

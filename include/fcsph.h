@@ -219,6 +219,28 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out,
                                 double dt, double nu);
 
 /*
+ * Sub-step k (0, 1, 2) of the low-storage third-order Runge-Kutta scheme
+ * (temporal discretisation section: eqs. uStarRK3, rhsMomtem, PPE and u^n+1
+ * with the RK3 coefficients a = (8/15, 2/15, 1/3), g = (8/15, 5/12, 3/4),
+ * z = (0, -17/60, -5/12)); signs and the dropped pressure term read as in
+ * fcsph_project_step:
+ *   F   = (u . grad) u - nu lap u
+ *   u*  = u - dt [ g_k F + z_k F_prev - a_k force ],  Dirichlet walls <- wall_vel
+ *   lap phi = rho / (a_k dt) div u*,   u <- u* - a_k (dt/rho) grad phi,  walls <- wall_vel
+ * dt is the whole RK3 step; sub-step k spans a_k dt, so wall_vel holds the
+ * wall data at the end of the sub-step and force its time average over it.
+ * F_store[a]: caller-owned FP64 physical arrays, one per velocity component:
+ * F_prev on entry (not read for k = 0) and this sub-step's F on exit.
+ * u, p_out, force, wall_vel: as for fcsph_project_step.  A full RK3 step is
+ * the three calls k = 0, 1, 2 in order on the same F_store.
+ * Errors: FCSPH_E_INVALID for k outside 0..2 or a NULL F_store component,
+ * otherwise as fcsph_project_step.
+ */
+fcsph_status fcsph_rk3_substep(fcsph_plan *p, int k, double *const *u, double *p_out,
+                               const double *const *force, const double *const *wall_vel,
+                               double *const *F_store, double dt, double nu);
+
+/*
  * Batches: the projection steps and PPE solves of many independent plans
  * (different sizes, wall types, precisions and operator evaluations) issued
  * together.  Each added call is validated and its launch sequence recorded

@@ -36,7 +36,7 @@ EXPORTS = [
     "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
     "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
     "fcsph_spectral_div",
-    "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_ctx_set_timing",
+    "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
     "fcsph_ctx_read_timing", "fcsph_ctx_set_timing_only", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
     "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_ppe", "fcsph_batch_launch",
     "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_spectral_lap.argtypes = [vp, i, vp, vp]
     L.fcsph_ppe_solve.argtypes = [vp, vp, vp]
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
+    L.fcsph_rk3_substep.argtypes = [vp, i, P(vp), vp, P(vp), P(vp), P(vp), d, d]
     L.fcsph_ctx_set_timing.argtypes = [vp, i]
     L.fcsph_ctx_set_timing_only.argtypes = [vp, ctypes.c_char_p]
     L.fcsph_ctx_read_timing.argtypes = [vp, i, ctypes.c_char_p, P(i), P(d), P(i)]
@@ -347,6 +348,19 @@ class Plan:
         pp = self._phys(p_out) if p_out is not None else None
         _check(lib().fcsph_project_step(self.handle, up, pp, fp, wp, float(dt), float(nu)),
                self.ctx.handle, "fcsph_project_step")
+        return u, p_out
+
+    def rk3_substep(self, k: int, u, F, dt: float, nu: float, p_out=None, force=None, wall=None):
+        """RK3 sub-step k (0, 1, 2) of the whole step dt; u (list of tensors) is
+        updated in place, F (list of FP64 tensors, one per component) carries
+        F of the previous sub-step in and this sub-step's F out."""
+        up = self._ptrs([self._phys(c).value for c in u])
+        Fp = self._ptrs([self._phys(c).value for c in F])
+        fp = self._ptrs([self._phys(c).value for c in force]) if force is not None else None
+        wp = self._ptrs([self._phys(c).value for c in wall]) if wall is not None else None
+        pp = self._phys(p_out) if p_out is not None else None
+        _check(lib().fcsph_rk3_substep(self.handle, int(k), up, pp, fp, wp, Fp, float(dt), float(nu)),
+               self.ctx.handle, "fcsph_rk3_substep")
         return u, p_out
 
 

@@ -268,8 +268,8 @@ __global__ void __launch_bounds__(NT) k_direct2d(KArg<DirectArgs, G> ka) {
     } else if constexpr (MODE == DIR_STEP_A) {
       const double u = tile[0][ty0 + o + R][tx + R], v = tile[1][ty0 + o + R][tx + R];
       const double fx = a.f[0] ? a.f[0][off] : 0.0, fy = a.f[1] ? a.f[1][off] : 0.0;
-      double us = u - a.dt * (u * acc[o][0][0] + v * acc[o][0][1] - a.nu * acc[o][0][2] - fx);
-      double vs = v - a.dt * (u * acc[o][1][0] + v * acc[o][1][1] - a.nu * acc[o][1][2] - fy);
+      double us = rk_ustar(a.rk, u, u * acc[o][0][0] + v * acc[o][0][1], a.nu, acc[o][0][2], fx, a.dt, off, 0);
+      double vs = rk_ustar(a.rk, v, u * acc[o][1][0] + v * acc[o][1][1], a.nu, acc[o][1][2], fy, a.dt, off, 1);
       if (dirichlet_pt(a.wi, x, y, 0)) {
         us = a.wall[0] ? a.wall[0][off] : 0.0;
         vs = a.wall[1] ? a.wall[1][off] : 0.0;

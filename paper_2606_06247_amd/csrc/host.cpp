@@ -1573,8 +1573,13 @@ fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi) {
   return run_ppe(p, rhs, phi);
 }
 
-fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, const double *const *force,
-                                const double *const *wall_vel, double dt, double nu) {
+// One projection step or RK3 sub-step.  u* uses dt and the RK terms; the
+// PPE right-hand side is (rho / dt_proj) div u* and the correction
+// u* - (dt_proj / rho) grad phi (eqs. PPE and u^n+1 with dt_proj = a_k dt;
+// the first-order form has dt_proj = dt).
+static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, const double *const *force,
+                              const double *const *wall_vel, double dt, double nu, double dt_proj,
+                              const RkTerms &rk) {
   if (!p) return FCSPH_E_INVALID;
   if (!u) return fail(p->ctx, FCSPH_E_INVALID, "null velocity");
   for (int a = 0; a < p->nd; ++a)
@@ -1623,8 +1628,9 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
       r.unew[q] = u[q];
     }
     r.dt = dt;
+    r.rk = rk;
     r.nu = nu;
-    r.dt_over_rho = dt / p->d.rho;
+    r.dt_over_rho = dt_proj / p->d.rho;
     r.wi = wall_info(p);
     {
       LaunchTimer t(p->ctx, "rows_inv_step_a3");
@@ -1633,7 +1639,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     // B (FP64 transforms in both forms), C
     {
       Fp64Passes g64(p);
-      st = div3_impl(p, p->ustar, p->rhs, !f32, p->d.rho / dt);
+      st = div3_impl(p, p->ustar, p->rhs, !f32, p->d.rho / dt_proj);
     }
     if (st != FCSPH_OK) return st;
     double *phi = p_out ? p_out : p->phi;
@@ -1675,10 +1681,11 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
       a.ustar[q] = p->ustar[q];
     }
     a.dt = dt;
+    a.rk = rk;
     a.nu = nu;
-    a.dt_over_rho = dt / p->d.rho;
+    a.dt_over_rho = dt_proj / p->d.rho;
     if (!chk(p, direct_launch(p, a, DIR_STEP_A, "direct_step_a"), "step A", st)) return st;
-    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
+    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt_proj);
     if (st != FCSPH_OK) return st;
     double *phi = p_out ? p_out : p->phi;
     st = run_ppe(p, p->rhs, phi);
@@ -1690,7 +1697,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
       b.ustar_in[q] = p->ustar[q];
       b.unew[q] = u[q];
     }
-    b.dt_over_rho = dt / p->d.rho;
+    b.dt_over_rho = dt_proj / p->d.rho;
     if (!chk(p, direct_launch(p, b, DIR_STEP_D, "direct_step_d"), "step D", st)) return st;
     return FCSPH_OK;
   }
@@ -1737,8 +1744,9 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   r.ustar[0] = p->ustar[0];
   r.ustar[1] = p->ustar[1];
   r.dt = dt;
+  r.rk = rk;
   r.nu = nu;
-  r.dt_over_rho = dt / p->d.rho;
+  r.dt_over_rho = dt_proj / p->d.rho;
   r.wi = wall_info(p);
   if (3ull * r.ldsM * (f32 ? 8 : 16) > (size_t)kMaxLds)
     return fail(p->ctx, FCSPH_E_UNSUPPORTED, "x line too long for the fused step kernel");
@@ -1749,7 +1757,7 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
   // B: b = (rho/dt) div u*, FP64 transforms in both forms
   {
     Fp64Passes g64(p);
-    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt);
+    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt_proj);
   }
   if (st != FCSPH_OK) return st;
   // C: PPE
@@ -1787,6 +1795,32 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
     if (!chk(p, launch_rows_inv(rd, EPI_STEP_D2, fd, s), "step D x inv", st)) return st;
   }
   return FCSPH_OK;
+}
+
+fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, const double *const *force,
+                                const double *const *wall_vel, double dt, double nu) {
+  RkTerms rk{};
+  return step_impl(p, u, p_out, force, wall_vel, dt, nu, dt, rk);
+}
+
+fcsph_status fcsph_rk3_substep(fcsph_plan *p, int k, double *const *u, double *p_out, const double *const *force,
+                               const double *const *wall_vel, double *const *F_store, double dt, double nu) {
+  if (!p) return FCSPH_E_INVALID;
+  if (k < 0 || k > 2) return fail(p->ctx, FCSPH_E_INVALID, "RK3 sub-step index must be 0, 1 or 2");
+  if (!F_store) return fail(p->ctx, FCSPH_E_INVALID, "null RK3 F store");
+  for (int c = 0; c < p->nd; ++c)
+    if (!F_store[c]) return fail(p->ctx, FCSPH_E_INVALID, "null RK3 F store component");
+  // low-storage RK3 coefficients (temporal discretisation section)
+  static const double ka[3] = {8.0 / 15.0, 2.0 / 15.0, 1.0 / 3.0};
+  static const double kg[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+  static const double kz[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+  RkTerms rk{};
+  rk.on = 1;
+  rk.g = kg[k];
+  rk.z = kz[k];
+  rk.a = ka[k];
+  for (int c = 0; c < p->nd; ++c) rk.F[c] = F_store[c];
+  return step_impl(p, u, p_out, force, wall_vel, dt, nu, ka[k] * dt, rk);
 }
 
 }  // extern "C"

@@ -137,6 +137,30 @@ struct WallInfo {
   int dir[3][2];       // 1 if the velocity wall is Dirichlet
 };
 
+// Terms of the intermediate velocity of a low-storage RK3 sub-step (eq.
+// uStarRK3 with the RK3 coefficient table; the pressure term is dropped as in
+// the first-order form):
+//   u* = u - dt (g F + z F_prev - a f),   F = (u . grad) u - nu lap u.
+// on == 0: the first-order form u* = u - dt (F - f) (g = a = 1, z = 0).
+// F[c] holds F_prev of component c on entry (read only when z != 0) and F on
+// exit (physical layout, FP64).
+struct RkTerms {
+  int on;
+  double g, z, a;
+  double *F[3];
+};
+
+// u* of one component; F is formed from the same expression as the
+// first-order form, so on == 0 rounds exactly like it.
+__device__ __forceinline__ double rk_ustar(const RkTerms &rk, double u, double adv, double nu, double lap,
+                                           double f, double dt, size_t idx, int c) {
+  if (!rk.on) return u - dt * (adv - nu * lap - f);
+  const double F = adv - nu * lap;
+  const double Fp = rk.z != 0.0 ? rk.F[c][idx] : 0.0;
+  rk.F[c][idx] = F;
+  return u - dt * (rk.g * F + rk.z * Fp - rk.a * f);
+}
+
 struct RowsInvArgs {
   LinePlan plan;
   int nrows;           // real rows handled (2D: ny, 3D: ny*nz)
@@ -158,6 +182,7 @@ struct RowsInvArgs {
   double *ustar[3];
   double *unew[3];
   double dt, nu, dt_over_rho;
+  RkTerms rk;
   WallInfo wi;
 };
 
@@ -290,6 +315,7 @@ struct DirectArgs {
   const double *f[3], *wall[3], *ustar_in[3];
   double *ustar[3], *unew[3];
   double dt, nu, dt_over_rho;
+  RkTerms rk;
   WallInfo wi;
   // FC ghost values of the inputs within R points of the lattice (2D):
   // gx[f] [ny][2R] (x = -R..-1, nx..nx+R-1), gy[f] [2R][nx+2R] (same slots in y,

@@ -234,8 +234,8 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
         const double lu = b2[x].r, lv = b2[x].i;
         const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
         const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
-        double us = u - a.dt * (u * gxu + v * gyu - a.nu * lu - fx);
-        double vs = v - a.dt * (u * gxv + v * gyv - a.nu * lv - fy);
+        double us = rk_ustar(a.rk, u, u * gxu + v * gyu, a.nu, lu, fx, a.dt, ro + x, 0);
+        double vs = rk_ustar(a.rk, v, u * gxv + v * gyv, a.nu, lv, fy, a.dt, ro + x, 1);
         if (is_dirichlet_point(a.wi, x, row, 0)) {
           us = a.wall[0] ? a.wall[0][ro + x] : 0.0;
           vs = a.wall[1] ? a.wall[1][ro + x] : 0.0;
@@ -257,9 +257,9 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
         const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
         const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
         const double fz = a.f[2] ? a.f[2][ro + x] : 0.0;
-        double us = u - a.dt * (u * gxu + v * gyu + w * gzu - a.nu * lu - fx);
-        double vs = v - a.dt * (u * gxv + v * gyv + w * gzv - a.nu * lv - fy);
-        double ws = w - a.dt * (u * gxw + v * gyw + w * gzw - a.nu * lw - fz);
+        double us = rk_ustar(a.rk, u, u * gxu + v * gyu + w * gzu, a.nu, lu, fx, a.dt, ro + x, 0);
+        double vs = rk_ustar(a.rk, v, u * gxv + v * gyv + w * gzv, a.nu, lv, fy, a.dt, ro + x, 1);
+        double ws = rk_ustar(a.rk, w, u * gxw + v * gyw + w * gzw, a.nu, lw, fz, a.dt, ro + x, 2);
         if (is_dirichlet_point(a.wi, x, y, z)) {
           us = a.wall[0] ? a.wall[0][ro + x] : 0.0;
           vs = a.wall[1] ? a.wall[1][ro + x] : 0.0;

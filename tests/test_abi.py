@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     txt = open(os.path.join(ROOT, "include", "fcsph.h")).read()
-    return sorted(set(re.findall(r"\b(fcsph_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(fcsph_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_and_binding_agree():
