@@ -267,6 +267,13 @@ fcsph_status fcsph_batch_clear(fcsph_batch *b);
 fcsph_status fcsph_batch_add_step(fcsph_batch *b, fcsph_plan *p, double *const *u, double *p_out,
                                   const double *const *force, const double *const *wall_vel,
                                   double dt, double nu);
+/* Adds one fcsph_rk3_substep call (same arguments).  A replayed graph repeats
+ * the recorded sub-step index; the three sub-steps of an RK3 step are three
+ * batches. */
+fcsph_status fcsph_batch_add_rk3_substep(fcsph_batch *b, fcsph_plan *p, int k, double *const *u,
+                                         double *p_out, const double *const *force,
+                                         const double *const *wall_vel, double *const *F_store,
+                                         double dt, double nu);
 fcsph_status fcsph_batch_add_ppe(fcsph_batch *b, fcsph_plan *p, const void *rhs, double *phi);
 /* Uploads the argument arrays and issues the grouped launches (asynchronous). */
 fcsph_status fcsph_batch_launch(fcsph_batch *b);

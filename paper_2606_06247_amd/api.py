@@ -38,7 +38,7 @@ EXPORTS = [
     "fcsph_spectral_div",
     "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
     "fcsph_ctx_read_timing", "fcsph_ctx_set_timing_only", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
-    "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_ppe", "fcsph_batch_launch",
+    "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_rk3_substep", "fcsph_batch_add_ppe", "fcsph_batch_launch",
     "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
 ]
 
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_batch_destroy.argtypes = [vp]
     L.fcsph_batch_clear.argtypes = [vp]
     L.fcsph_batch_add_step.argtypes = [vp, vp, P(vp), vp, P(vp), P(vp), d, d]
+    L.fcsph_batch_add_rk3_substep.argtypes = [vp, vp, i, P(vp), vp, P(vp), P(vp), P(vp), d, d]
     L.fcsph_batch_add_ppe.argtypes = [vp, vp, vp, vp]
     L.fcsph_batch_launch.argtypes = [vp]
     L.fcsph_batch_capture.argtypes = [vp]
@@ -402,6 +403,18 @@ class Batch:
         _check(lib().fcsph_batch_add_step(self.handle, plan.handle, up, pp, fp, wp, float(dt), float(nu)),
                self.ctx.handle, "fcsph_batch_add_step")
         self._keep.append((plan, u, p_out, force, wall))
+
+    def add_rk3_substep(self, plan: "Plan", k: int, u, F, dt: float, nu: float, p_out=None, force=None,
+                        wall=None):
+        up = plan._ptrs([plan._phys(c).value for c in u])
+        Fp = plan._ptrs([plan._phys(c).value for c in F])
+        fp = plan._ptrs([plan._phys(c).value for c in force]) if force is not None else None
+        wp = plan._ptrs([plan._phys(c).value for c in wall]) if wall is not None else None
+        pp = plan._phys(p_out) if p_out is not None else None
+        _check(lib().fcsph_batch_add_rk3_substep(self.handle, plan.handle, int(k), up, pp, fp, wp, Fp,
+                                                 float(dt), float(nu)),
+               self.ctx.handle, "fcsph_batch_add_rk3_substep")
+        self._keep.append((plan, u, F, p_out, force, wall))
 
     def add_ppe(self, plan: "Plan", rhs, out=None):
         out = plan._new() if out is None else out

@@ -2000,6 +2000,25 @@ fcsph_status fcsph_batch_add_step(fcsph_batch *b, fcsph_plan *p, double *const *
   return FCSPH_OK;
 }
 
+fcsph_status fcsph_batch_add_rk3_substep(fcsph_batch *b, fcsph_plan *p, int k, double *const *u, double *p_out,
+                                         const double *const *force, const double *const *wall_vel,
+                                         double *const *F_store, double dt, double nu) {
+  if (!b || !p) return b ? batch_fail(b, FCSPH_E_INVALID, "null plan") : FCSPH_E_INVALID;
+  fcsph_status st = batch_add(b, p, BATCH_STEP);
+  if (st != FCSPH_OK) return st;
+  Recorder *&r = active_recorder();
+  r = &b->items.back().rec;
+  st = fcsph_rk3_substep(p, k, u, p_out, force, wall_vel, F_store, dt, nu);
+  r = nullptr;
+  if (st == FCSPH_OK && b->items.back().rec.recs.size() > (size_t)kBatchMaxLaunches)
+    st = fail(p->ctx, FCSPH_E_UNSUPPORTED, "too many launches for a batch item");
+  if (st != FCSPH_OK) {
+    b->items.pop_back();
+    return fail(b->ctx, st, std::string("batch RK3 sub-step: ") + fcsph_ctx_last_error(p->ctx));
+  }
+  return FCSPH_OK;
+}
+
 fcsph_status fcsph_batch_add_ppe(fcsph_batch *b, fcsph_plan *p, const void *rhs, double *phi) {
   if (!b || !p) return b ? batch_fail(b, FCSPH_E_INVALID, "null plan") : FCSPH_E_INVALID;
   fcsph_status st = batch_add(b, p, BATCH_PPE);

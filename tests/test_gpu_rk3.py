@@ -154,3 +154,52 @@ def test_rk3_rejects_bad_substep(ctx):
         plan.rk3_substep(3, u, F, 1e-4, 1e-3)
     with pytest.raises(api.FcsphError):
         plan.rk3_substep(-1, u, F, 1e-4, 1e-3)
+
+
+def test_rk3_batched_equals_plain_bitwise(ctx):
+    """Three batches (one per sub-step) over a mix of lattices give bitwise the
+    plain sub-steps; the third is also replayed from a captured graph."""
+    import torch
+    from paper_2606_06247_amd import api
+    items = [(CASES_2D[0], "fp64", "fft_window"), (CASES_2D[1], "fp64", "fft"), (CASES_2D[3], "fp32", "fft_window"),
+             (CASES_2D[2], "fp64", "direct"), (spec((24, 33, 16), (False, True, False)), "fp64", "fft_window")]
+    plans, plain, batched = [], [], []
+    for i, (s, prec, oe) in enumerate(items):
+        plans.append(api.Plan(ctx, problem(s, precision=prec, op_eval=oe)))
+        if s["nd"] == 2:
+            u = [synth.poly_trig_2d(s["n"], 300 + 2 * i + k, dx=s["dx"]) for k in range(2)]
+        else:
+            u = [np.ascontiguousarray(c) for c in synth.ChannelFlow3D(s["n"], 300 + i, 400 + i).u]
+        for store in (plain, batched):
+            ud = [to_dev(c) for c in u]
+            store.append(dict(u=ud, F=[torch.zeros_like(ud[0]) for _ in ud], p=torch.empty_like(ud[0]),
+                              w=[to_dev(c) for c in u]))
+    dt, nu = 1e-4, 1e-3
+    for k in range(3):
+        for i, plan in enumerate(plans):
+            st = plain[i]
+            plan.rk3_substep(k, st["u"], st["F"], dt, nu, p_out=st["p"], wall=st["w"])
+        b = api.Batch(ctx, len(plans))
+        for i, plan in enumerate(plans):
+            st = batched[i]
+            b.add_rk3_substep(plan, k, st["u"], st["F"], dt, nu, p_out=st["p"], wall=st["w"])
+        b.launch()
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            for c in range(len(plain[i]["u"])):
+                assert torch.equal(plain[i]["u"][c], batched[i]["u"][c]), (k, i, c)
+                assert torch.equal(plain[i]["F"][c], batched[i]["F"][c]), (k, i, "F", c)
+            assert torch.equal(plain[i]["p"], batched[i]["p"]), (k, i, "p")
+        if k == 2:
+            # replay the last sub-step once more on both sides
+            b.capture()
+            for i, plan in enumerate(plans):
+                st = plain[i]
+                plan.rk3_substep(k, st["u"], st["F"], dt, nu, p_out=st["p"], wall=st["w"])
+            torch.cuda.synchronize()
+            b.replay()
+            torch.cuda.synchronize()
+            for i in range(len(plans)):
+                for c in range(len(plain[i]["u"])):
+                    assert torch.equal(plain[i]["u"][c], batched[i]["u"][c]), ("replay", i, c)
+                assert torch.equal(plain[i]["p"], batched[i]["p"]), ("replay", i, "p")
