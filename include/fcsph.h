@@ -75,9 +75,16 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *  vel_bc, prs_bc [a][0|1]  wall types (fcsph_bc) of the low / high wall of a
  *              walled axis, for the velocity and the pressure field classes
  *              (wall conditions: eqs. BC_velocity and BC_pressure)
- *  fc_d, fc_C  FC(Gram) matching / continuation points (5 and 25)
+ *  fc_d, fc_C  FC matching / continuation points: 5 and 25 for FC(Gram);
+ *              any 1 <= fc_d <= 16, 2 <= fc_C <= 4096 (the paper's own FC:
+ *              d fit points, C = the extension length, e.g. 10 and n / 4)
  *  fc_M_dir, fc_M_neu  HOST pointers to the C x d row-major FP64 continuation
- *              maps of a Dirichlet / Neumann wall; copied at plan creation
+ *              maps of a Dirichlet / Neumann wall (row r - 1: the value r
+ *              lattice steps beyond the wall from the d values nearest it,
+ *              ordered inward to wall; the low wall uses the same map on its
+ *              mirrored values, so a map must be of that symmetric form, as
+ *              FC(Gram) and the paper's blended polynomial FC are); copied at
+ *              plan creation
  *  kernel, h_over_dx   SPH kernel and smoothing length h / dx
  *  prec        fcsph_precision;  ppe_domain  fcsph_ppe_domain;  eig  fcsph_eig
  *  rho         fluid density

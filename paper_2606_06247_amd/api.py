@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import fctables
+from . import fcpoly, fctables
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfcsph.so")
@@ -137,6 +137,10 @@ class Problem:
     op_eval: str = "fft"          # 'fft' | 'fft_window' | 'direct'
     fc_d: int = 5
     fc_C: int = 25
+    # "gram": FC(Gram) maps (fc_d = 5, fc_C = 25); "poly": the paper's own FC
+    # (fc_d fit points, degree fc_p, fc_C extension points)
+    fc_kind: str = "gram"
+    fc_p: int = 5
     window_len: tuple = ()        # schedule hint per axis (0 = library choice)
     lines_per_group: int = 0      # schedule hint (0 = library choice)
 
@@ -205,9 +209,15 @@ class Context:
 def make_desc(prob: "Problem"):
     """The C descriptor of a Problem, with the FC map arrays it points into
     (keep them alive while the descriptor is used)."""
-    tabs = fctables.load(prob.fc_d, prob.fc_C)
-    mdir = np.ascontiguousarray(tabs["dirichlet"], dtype=np.float64)
-    mneu = np.ascontiguousarray(tabs["neumann"], dtype=np.float64)
+    if prob.fc_kind == "gram":
+        tabs = fctables.load(prob.fc_d, prob.fc_C)
+        mdir, mneu = tabs["dirichlet"], tabs["neumann"]
+    elif prob.fc_kind == "poly":
+        mdir, mneu = fcpoly.build(prob.fc_d, prob.fc_p, prob.fc_C)
+    else:
+        raise ValueError(f"unknown fc_kind {prob.fc_kind!r}")
+    mdir = np.ascontiguousarray(mdir, dtype=np.float64)
+    mneu = np.ascontiguousarray(mneu, dtype=np.float64)
     d = Desc()
     d.ndim = prob.ndim
     for a in range(prob.ndim):

@@ -499,7 +499,7 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
     if (2.0 * 2.0 * d->h_over_dx >= (double)E) { msg = "kernel support exceeds half the extended period"; return FCSPH_E_INVALID; }
   }
   if (any_wall) {
-    if (d->fc_d < 1 || d->fc_C < 1 || d->fc_d > 16 || d->fc_C > 64) { msg = "bad FC sizes"; return FCSPH_E_INVALID; }
+    if (d->fc_d < 1 || d->fc_C < 2 || d->fc_d > 16 || d->fc_C > 4096) { msg = "bad FC sizes"; return FCSPH_E_INVALID; }
     if (!d->fc_M_dir || !d->fc_M_neu) { msg = "FC maps required for walled axes"; return FCSPH_E_INVALID; }
   }
   if (d->ndim == 3) {
