@@ -110,7 +110,7 @@ __device__ __forceinline__ bool is_dirichlet_point(const WallInfo &w, int x, int
 
 // Load one packed complex line Z = A + i B from two half spectra (length H)
 // of a real length-E signal: Z[k] = A[k] + i B[k], Z[E-k] = conj(A[k]) + i conj(B[k]).
-template <typename T>
+template <typename T, bool CONJ = false>
 __device__ __forceinline__ void load_packed_c2r(Line<T> buf, const cpx<T> *A, const cpx<T> *Bp,
                                                 int E, int H, int lt, int TL) {
   struct AB {
@@ -127,8 +127,15 @@ __device__ __forceinline__ void load_packed_c2r(Line<T> buf, const cpx<T> *A, co
                      av.i = T(0);
                      bv.i = T(0);
                    }
-                   buf[k] = {av.r - bv.i, av.i + bv.r};
-                   if (!selfconj) buf[E - k] = {av.r + bv.i, bv.r - av.i};
+                   if (CONJ) {
+                     // the input conjugation of an inverse DFT computed as
+                     // conj(DFT(conj(.))); readers take -im of its output
+                     buf[k] = {av.r - bv.i, -(av.i + bv.r)};
+                     if (!selfconj) buf[E - k] = {av.r + bv.i, -(bv.r - av.i)};
+                   } else {
+                     buf[k] = {av.r - bv.i, av.i + bv.r};
+                     if (!selfconj) buf[E - k] = {av.r + bv.i, bv.r - av.i};
+                   }
                  });
 }
 
@@ -161,18 +168,18 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
     const bool okA = rA < a.nrows, okB = rB < a.nrows;
     const cpx<T> *sA = okA ? static_cast<const cpx<T> *>(a.spec[0]) + spec_row(a, rA) : nullptr;
     const cpx<T> *sB = okB ? static_cast<const cpx<T> *>(pair ? a.spec[1] : a.spec[0]) + spec_row(a, rB) : nullptr;
-    load_packed_c2r<T>(buf, sA, sB, a.E, a.H, lt, TL);
+    load_packed_c2r<T, true>(buf, sA, sB, a.E, a.H, lt, TL);
     __syncthreads();
-    line_dft<T>(buf, a.plan, lt, TL, true, true);
+    line_dft<T>(buf, a.plan, lt, TL, false, false);   // conjugated output: im = -z.i
     const int oB = pair ? 1 : 0;
     for (int x = lt; x < a.nx; x += TL) {
       const cpx<T> z = buf[x];
       if (a.out_is_double) {
         if (okA) static_cast<double *>(a.out[0])[(size_t)rA * a.nx + x] = a.scale * (double)z.r;
-        if (okB) static_cast<double *>(a.out[oB])[(size_t)rB * a.nx + x] = a.scale * (double)z.i;
+        if (okB) static_cast<double *>(a.out[oB])[(size_t)rB * a.nx + x] = a.scale * (double)(-z.i);
       } else {
         if (okA) static_cast<float *>(a.out[0])[(size_t)rA * a.nx + x] = (float)(a.scale * (double)z.r);
-        if (okB) static_cast<float *>(a.out[oB])[(size_t)rB * a.nx + x] = (float)(a.scale * (double)z.i);
+        if (okB) static_cast<float *>(a.out[oB])[(size_t)rB * a.nx + x] = (float)(a.scale * (double)(-z.i));
       }
     }
   } else if constexpr (EPI == EPI_STEP_D2) {
@@ -180,14 +187,14 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
     const bool ok = row < a.nrows;
     const cpx<T> *sA = ok ? static_cast<const cpx<T> *>(a.spec[0]) + spec_row(a, row) : nullptr;
     const cpx<T> *sB = ok ? static_cast<const cpx<T> *>(a.spec[1]) + spec_row(a, row) : nullptr;
-    load_packed_c2r<T>(buf, sA, sB, a.E, a.H, lt, TL);
+    load_packed_c2r<T, true>(buf, sA, sB, a.E, a.H, lt, TL);
     __syncthreads();
-    line_dft<T>(buf, a.plan, lt, TL, true, true);
+    line_dft<T>(buf, a.plan, lt, TL, false, false);   // conjugated output
     if (!ok) return;
     const size_t ro = (size_t)row * a.nx;
     for (int x = lt; x < a.nx; x += TL) {
       double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)buf[x].r;
-      double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)buf[x].i;
+      double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)(-buf[x].i);
       if (is_dirichlet_point(a.wi, x, row, 0)) {
         un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
         vn = a.wall[1] ? a.wall[1][ro + x] : 0.0;
@@ -220,18 +227,18 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
           sA = static_cast<const cpx<T> *>(a.spec[q == 0 ? 0 : 2]) + ro_s;
           sB = q == 0 ? static_cast<const cpx<T> *>(a.spec[1]) + ro_s : nullptr;
         }
-        load_packed_c2r<T>(lb, sA, sB, a.E, a.H, lt, TL);
+        load_packed_c2r<T, true>(lb, sA, sB, a.E, a.H, lt, TL);
       }
       __syncthreads();
-      line_dft<T>(lb, a.plan, lt, TL, true, true, act);
+      line_dft<T>(lb, a.plan, lt, TL, false, false, act);   // conjugated outputs: im = -.i
     }
     const size_t ro = (size_t)row * a.nx;
     if constexpr (EPI == EPI_STEP_A2) {
       const Line<T> b0{smem}, b1{smem + a.ldsM}, b2{smem + 2 * (size_t)a.ldsM};
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         const double u = a.u[0][ro + x], v = a.u[1][ro + x];
-        const double gxu = b0[x].r, gyu = b0[x].i, gxv = b1[x].r, gyv = b1[x].i;
-        const double lu = b2[x].r, lv = b2[x].i;
+        const double gxu = b0[x].r, gyu = -b0[x].i, gxv = b1[x].r, gyv = -b1[x].i;
+        const double lu = b2[x].r, lv = -b2[x].i;
         const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
         const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
         double us = rk_ustar(a.rk, u, u * gxu + v * gyu, a.nu, lu, fx, a.dt, ro + x, 0);
@@ -250,10 +257,10 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         const double u = a.u[0][ro + x], v = a.u[1][ro + x], w = a.u[2][ro + x];
-        const double gxu = b[0][x].r, gyu = b[0][x].i, gzu = b[1][x].r;
-        const double gxv = b[1][x].i, gyv = b[2][x].r, gzv = b[2][x].i;
-        const double gxw = b[3][x].r, gyw = b[3][x].i, gzw = b[4][x].r;
-        const double lu = b[4][x].i, lv = b[5][x].r, lw = b[5][x].i;
+        const double gxu = b[0][x].r, gyu = -b[0][x].i, gzu = b[1][x].r;
+        const double gxv = -b[1][x].i, gyv = b[2][x].r, gzv = -b[2][x].i;
+        const double gxw = b[3][x].r, gyw = -b[3][x].i, gzw = b[4][x].r;
+        const double lu = -b[4][x].i, lv = b[5][x].r, lw = -b[5][x].i;
         const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
         const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
         const double fz = a.f[2] ? a.f[2][ro + x] : 0.0;
@@ -274,7 +281,7 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
         double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)b0[x].r;
-        double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)b0[x].i;
+        double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)(-b0[x].i);
         double wn = a.ustar[2][ro + x] - a.dt_over_rho * (double)b1[x].r;
         if (is_dirichlet_point(a.wi, x, y, z)) {
           un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
@@ -347,19 +354,23 @@ __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const
                      });
 }
 
-template <typename T>
+// CONJ stores the complex conjugate (the output conjugation of an inverse
+// transform computed as conj(DFT(conj(x))), folded into the store).
+template <typename T, bool CONJ = false>
 __device__ __forceinline__ void cols_store(const ColsArgs &a, const cpx<T> *smem, cpx<T> *out,
                                            int c0, size_t obase, int n) {
+  auto val = [](cpx<T> v) { return CONJ ? cconj(v) : v; };
   if (a.B == 1) {
     if (c0 < a.ninner)
       for (int j = threadIdx.x; j < n; j += blockDim.x)
-        out[obase + (size_t)j * a.es_out + c0] = Line<T>{const_cast<cpx<T> *>(smem)}[j];
+        out[obase + (size_t)j * a.es_out + c0] = val(Line<T>{const_cast<cpx<T> *>(smem)}[j]);
     return;
   }
   for (int idx = threadIdx.x; idx < a.B * n; idx += blockDim.x) {
     const int l = idx % a.B, j = idx / a.B;
     const int c = c0 + l;
-    if (c < a.ninner) out[obase + (size_t)j * a.es_out + c] = Line<T>{const_cast<cpx<T> *>(smem) + (size_t)l * a.ldsM}[j];
+    if (c < a.ninner)
+      out[obase + (size_t)j * a.es_out + c] = val(Line<T>{const_cast<cpx<T> *>(smem) + (size_t)l * a.ldsM}[j]);
   }
 }
 
@@ -460,17 +471,19 @@ k_cols(KArg<ColsArgs, G> ka) {
         double2 R[kSymW];
         line_coeffs(a, a.sym[pass - 1], c < a.ninner ? c : 0, o, R);
         __syncthreads();   // the previous output's store has finished reading buf
+        // the inverse DFT is conj(DFT(conj(.))): the input conjugation is
+        // folded into the symbol product, the output one into the store
         for (int k = lt; k < E; k += TL) {
           const double2 sv = sym_eval(R, ph_line, k);
-          buf[k] = cmul(to_cpx<T>(sv.x, sv.y), xb[k]);
+          buf[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), xb[k]));
         }
         __syncthreads();
       }
-      line_dft<T>(buf, a.plan, lt, TL, pass > 0, pass > 0);
+      line_dft<T>(buf, a.plan, lt, TL, false, false);
       if (pass == 0) {
         for (int k = lt; k < E; k += TL) xb[k] = buf[k];
       } else {
-        cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][pass - 1]), c0, obase_out, a.nstore);
+        cols_store<T, true>(a, smem, static_cast<cpx<T> *>(a.out[f][pass - 1]), c0, obase_out, a.nstore);
       }
     }
   } else {
@@ -490,10 +503,11 @@ k_cols(KArg<ColsArgs, G> ka) {
           __syncthreads();
         }
       } else {
-        for (int k = lt; k < E; k += TL) buf[k] = acc[k];
+        // inverse as conj(DFT(conj(.))), conjugations folded into this copy and the store
+        for (int k = lt; k < E; k += TL) buf[k] = cconj(acc[k]);
         __syncthreads();
       }
-      line_dft<T>(buf, a.plan, lt, TL, pass == nin, pass == nin);
+      line_dft<T>(buf, a.plan, lt, TL, false, false);
       if (pass < nin) {
         double2 R[kSymW];
         line_coeffs(a, a.sym[pass], c < a.ninner ? c : 0, o, R);
@@ -503,7 +517,7 @@ k_cols(KArg<ColsArgs, G> ka) {
         }
       }
     }
-    cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[0][0]), c0, obase_out, a.nstore);
+    cols_store<T, true>(a, smem, static_cast<cpx<T> *>(a.out[0][0]), c0, obase_out, a.nstore);
   }
 }
 
