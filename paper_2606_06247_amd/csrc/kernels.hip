@@ -331,7 +331,9 @@ __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_
 }
 
 
-template <typename T>
+// CONJ loads the complex conjugate (the input conjugation of an inverse
+// transform computed as conj(DFT(conj(x))), folded into the load).
+template <typename T, bool CONJ = false>
 __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const cpx<T> *in,
                                           int c0, size_t obase, int n) {
   if (a.B == 1) {
@@ -339,7 +341,7 @@ __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const
     const bool ok = c0 < a.ninner;
     batched<8, cpx<T>>(threadIdx.x, n, blockDim.x,
                        [&](int j) { return ok ? in[obase + (size_t)j * a.es + c0] : cpx<T>{T(0), T(0)}; },
-                       [&](int j, cpx<T> v) { Line<T>{smem}[j] = v; });
+                       [&](int j, cpx<T> v) { Line<T>{smem}[j] = CONJ ? cconj(v) : v; });
     return;
   }
   batched<8, cpx<T>>(threadIdx.x, a.B * n, blockDim.x,
@@ -350,7 +352,7 @@ __device__ __forceinline__ void cols_load(const ColsArgs &a, cpx<T> *smem, const
                      },
                      [&](int idx, cpx<T> v) {
                        const int l = idx % a.B, j = idx / a.B;
-                       Line<T>{smem + (size_t)l * a.ldsM}[j] = v;
+                       Line<T>{smem + (size_t)l * a.ldsM}[j] = CONJ ? cconj(v) : v;
                      });
 }
 
@@ -443,16 +445,18 @@ k_cols(KArg<ColsArgs, G> ka) {
   const double2 *ph_line = a.st.ph[a.line_axis];
 
   if constexpr (MODE == COLS_FWD || MODE == COLS_INV) {
+    // COLS_INV loads the whole line (nload == plan length) and computes the
+    // inverse as conj(DFT(conj(.))) with the conjugations in the load and store
+    constexpr bool inv = MODE == COLS_INV;
     const cpx<T> *in = static_cast<const cpx<T> *>(a.in[f]);
-    cols_load<T>(a, smem, in, c0, obase_in, a.nload);
+    cols_load<T, inv>(a, smem, in, c0, obase_in, a.nload);
     __syncthreads();
     if (MODE == COLS_FWD && a.fc.on) {
       cols_fc<T>(a, buf, lt, TL, f, c, o);
       __syncthreads();
     }
-    constexpr bool inv = MODE == COLS_INV;
-    line_dft<T>(buf, a.plan, lt, TL, inv, inv);
-    cols_store<T>(a, smem, static_cast<cpx<T> *>(a.out[f][0]), c0, obase_out, a.nstore);
+    line_dft<T>(buf, a.plan, lt, TL, false, false);
+    cols_store<T, inv>(a, smem, static_cast<cpx<T> *>(a.out[f][0]), c0, obase_out, a.nstore);
   } else if constexpr (MODE == COLS_OP) {
     // pass 0: FC + forward DFT, kept in a second LDS line (xb); pass q + 1:
     // symbol q times xb, inverse DFT, store.  One transform call site keeps
@@ -1068,6 +1072,8 @@ hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s)
   // the symbol passes read their line coefficients from the plan's table
   if ((a.mode == COLS_OP || a.mode == COLS_DIV) && !a.symR) return hipErrorInvalidValue;
   if (a.nfull != 0) return hipErrorInvalidValue;
+  // the inverse pass conjugates on load: it must load every line position
+  if (a.mode == COLS_INV && a.nload != a.plan.n) return hipErrorInvalidValue;
   // Tail split: when the tasks (field, panel) exceed the resident workgroups
   // by at most a third of them divided by the outputs, the leftover tasks
   // would run as a second, nearly empty round of whole tasks (forward + nout
