@@ -458,9 +458,10 @@ k_cols(KArg<ColsArgs, G> ka) {
     line_dft<T>(buf, a.plan, lt, TL, false, false);
     cols_store<T, inv>(a, smem, static_cast<cpx<T> *>(a.out[f][0]), c0, obase_out, a.nstore);
   } else if constexpr (MODE == COLS_OP) {
-    // pass 0: FC + forward DFT, kept in a second LDS line (xb); pass q + 1:
-    // symbol q times xb, inverse DFT, store.  One transform call site keeps
-    // the kernel's register footprint at that of a single transform.
+    // pass 0: FC + forward DFT in place (the spectrum stays in buf); pass
+    // q + 1: symbol q times buf into a second LDS line (xb), inverse DFT
+    // there, store.  One transform call site (on a line chosen per pass)
+    // keeps the kernel's register footprint at that of a single transform.
     Line<T> xb{smem + (size_t)(a.B + g) * a.ldsM};
     for (int pass = 0; pass <= a.nout; ++pass) {
       if (pass > 0 && qsel >= 0 && pass != qsel + 1) continue;   // uniform per workgroup
@@ -474,21 +475,19 @@ k_cols(KArg<ColsArgs, G> ka) {
       } else {
         double2 R[kSymW];
         line_coeffs(a, a.sym[pass - 1], c < a.ninner ? c : 0, o, R);
-        __syncthreads();   // the previous output's store has finished reading buf
+        __syncthreads();   // the previous output's store has finished reading xb
         // the inverse DFT is conj(DFT(conj(.))): the input conjugation is
         // folded into the symbol product, the output one into the store
         for (int k = lt; k < E; k += TL) {
           const double2 sv = sym_eval(R, ph_line, k);
-          buf[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), xb[k]));
+          xb[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
         }
         __syncthreads();
       }
-      line_dft<T>(buf, a.plan, lt, TL, false, false);
-      if (pass == 0) {
-        for (int k = lt; k < E; k += TL) xb[k] = buf[k];
-      } else {
-        cols_store<T, true>(a, smem, static_cast<cpx<T> *>(a.out[f][pass - 1]), c0, obase_out, a.nstore);
-      }
+      line_dft<T>(pass == 0 ? buf : xb, a.plan, lt, TL, false, false);
+      if (pass > 0)
+        cols_store<T, true>(a, smem + (size_t)a.B * a.ldsM, static_cast<cpx<T> *>(a.out[f][pass - 1]), c0,
+                            obase_out, a.nstore);
     }
   } else {
     // COLS_DIV: out = sum_f S_f DFT(FC(in_f)), one output; passes 0..nin-1
