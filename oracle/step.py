@@ -36,11 +36,15 @@ coefficient table of that section, sub-step k = 0, 1, 2:
 
 Parity: built from pinned parts (operators, PPE, FC); the step itself is pinned
 by the projection identities P-PRJ1/P-PRJ2 and by direct-vs-fft mode agreement
-in ``tests/test_oracle_step.py``.  The RK3 sub-steps are pinned by the
+in ``tests/test_oracle_step.py``, and its u* terms (advection order, viscous
+and forcing signs, in 2D and 3D) by closed forms on single Fourier modes of an
+all-periodic lattice in ``tests/test_oracle_step_terms.py``.  The RK3 sub-steps are pinned by the
 stability polynomial 1 + z + z^2/2 + z^3/6 of a three-stage third-order
 scheme on a forced linear shear mode, and by the projected velocity being
 divergence-free to rounding on an all-periodic lattice with the SPH
-eigenvalue family (``tests/test_oracle_rk3.py``).  Multi-step trajectories:
+eigenvalue family (``tests/test_oracle_rk3.py``); the F it returns and the
+first sub-step's u* by the same single-mode closed forms as the first-order
+step.  Multi-step trajectories:
 parity unpinned beyond those.
 """
 from __future__ import annotations

@@ -1,0 +1,60 @@
+"""Spectral radius of the projection map of the first-order step (no GPU).
+
+With nu = 0 and zero velocity the advection term is quadratic, so the
+linearisation of one step about the rest state is the projection map alone:
+    P(u*) = walls_0( u* - G_p PPE( div u* ) )          (rho = dt = 1)
+(div and G_p: the spectral SPH operators on FC-extended fields, velocity and
+pressure wall maps; PPE: the transform solve of the pressure wall types;
+walls_0: Dirichlet velocity wall points set to zero).  Power iteration gives
+its spectral radius.  These values are findings of the adopted readings, not
+properties the paper states:
+* walls on one axis (the 3D channel's configuration): radius 1 within the
+  iteration's convergence, for both eigenvalue families;
+* walls on two axes (the 2D lattices with four walls): radius about 1.46
+  (SPECTRAL) and 1.61 (FD2), the same at 16^2 and 24^2, with the dominant
+  mode at the lattice points diagonally next to the corners.  Extending phi
+  with the velocity (Dirichlet) maps instead of the Neumann maps gives 1.61,
+  Dirichlet pressure walls 1.04: no reading tried makes the four-wall map
+  contractive, so trajectories of the four-wall lattice grow without bound.
+"""
+import numpy as np
+import pytest
+
+from oracle import operators, ppe, step
+from oracle.lattice import Lattice, walled_box
+
+
+def _radius(lat, tables, family, iters=200, seed=0):
+    ops = operators.Operators(lat, tables)
+    rng = np.random.default_rng(seed)
+    u = [step.set_dirichlet_walls(rng.standard_normal(lat.shape), lat, None) for _ in range(lat.ndim)]
+    hist = []
+    for _ in range(iters):
+        nrm = np.sqrt(sum(np.sum(c * c) for c in u))
+        u = [c / nrm for c in u]
+        phi = ppe.solve(ops.div(u), lat, family=family)
+        g = ops.grad(phi, "p")
+        u = [step.set_dirichlet_walls(u[a] - g[a], lat, None) for a in range(lat.ndim)]
+        hist.append(np.sqrt(sum(np.sum(c * c) for c in u)))
+    return hist[-1], abs(hist[-1] - hist[-2]), u
+
+
+@pytest.mark.parametrize("family,expect", [("spectral", 1.458), ("fd2", 1.612)])
+def test_four_wall_projection_radius(fc_tables, family, expect):
+    r, dr, u = _radius(walled_box((16, 16)), fc_tables, family)
+    assert dr < 1e-5 * r                      # converged
+    assert abs(r - expect) < 2e-3, r
+    mag = np.hypot(u[0], u[1])
+    # the dominant mode sits at the points diagonally next to the corners
+    corner = max(mag[1, 1], mag[1, -2], mag[-2, 1], mag[-2, -2])
+    assert corner == mag.max()
+    assert np.median(mag) < 0.1 * corner
+
+
+@pytest.mark.parametrize("family", ["spectral", "fd2"])
+def test_channel_projection_radius(fc_tables, family):
+    n = 16
+    lat = Lattice(n=(n, n), walled=(False, True), dx=1.0 / (n - 1), vel_bc=(None, ("D", "D")),
+                  prs_bc=(None, ("N", "N")))
+    r, _, _ = _radius(lat, fc_tables, family)
+    assert 0.99 < r < 1.005, r
