@@ -133,11 +133,12 @@ RK3_Z = (0.0, -17.0 / 60.0, -5.0 / 12.0)
 
 
 def rk3_substep(lat, tables, u, k, F_prev=None, force=None, wall=None, dt=1e-4, nu=1e-3, rho=1.0,
-                family: str = "spectral", opmode: str = "direct"):
+                family: str = "spectral", opmode: str = "direct", return_parts: bool = False):
     """Sub-step k (0, 1, 2) of the low-storage RK3 step of length dt.
     u: velocity components; F_prev: F of the previous sub-step (ignored for
     k = 0); force: forcing averaged over the sub-step; wall: Dirichlet data at
-    the end of the sub-step.  Returns (u_new, phi, F)."""
+    the end of the sub-step.  Returns (u_new, phi, F), plus a dict with u*
+    and the PPE right-hand side b when return_parts is set."""
     a, g, z = RK3_A[k], RK3_G[k], RK3_Z[k]
     ops = operators.Operators(lat, tables, mode=opmode)
     nd = lat.ndim
@@ -157,4 +158,6 @@ def rk3_substep(lat, tables, u, k, F_prev=None, force=None, wall=None, dt=1e-4, 
     gphi = ops.grad(phi, "p")
     unew = [set_dirichlet_walls(ustar[c] - a * (dt / rho) * gphi[c], lat, None if wall is None else wall[c])
             for c in range(nd)]
+    if return_parts:
+        return unew, phi, F, dict(ustar=ustar, b=b)
     return unew, phi, F

@@ -689,12 +689,12 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     } else {
       kind = d->prs_bc[a][0] == FCSPH_BC_NEUMANN ? TRIG_DCT1 : TRIG_DST1;
       L = 2 * (nn - 1);
-      // FP64 DCT-I / DST-I: one DFT of length N = n - 1 and a running sum
-      // (half the transform length of the even / odd extension; at n = 1024
-      // a 2048-point instead of a 4096-point Bluestein FFT).  The FP32 form
-      // keeps the extension: the running sum would add FP32 rounding over
-      // N / 2 terms.
-      if (!f32 && nn >= 3) L = nn - 1;
+      // DCT-I / DST-I: one DFT of length N = n - 1 and a running sum (half
+      // the transform length of the even / odd extension; at n = 1024 a
+      // 2048-point instead of a 4096-point Bluestein FFT).  The PPE runs in
+      // FP64 in both forms (in FP32 the running sum over N / 2 terms alone
+      // would exceed the FP32 form's error target).
+      if (nn >= 3) L = nn - 1;
     }
     p->trig_kind[a] = kind;
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
@@ -702,8 +702,8 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     const int minTL = (a == 0) ? 64 : 64;
     // the narrow butterfly rule where the line fits (more waves per SIMD),
     // else the wide one (longer lines per workgroup)
-    if (!make_line_plan(L, f32, minTL, ws, up, p->trig[a], false, false) &&
-        !make_line_plan(L, f32, minTL, ws, up, p->trig[a], false, true)) {
+    if (!make_line_plan(L, false, minTL, ws, up, p->trig[a], false, false) &&
+        !make_line_plan(L, false, minTL, ws, up, p->trig[a], false, true)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }
@@ -748,12 +748,10 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     if (qw) {
       // exp(-i pi j / 2N), j < 2N, N = n - 1
       Upload q;
-      const size_t es = f32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
-      q.data.resize((size_t)L * es);
+      q.data.resize((size_t)L * sizeof(cpx<double>));
       for (int j = 0; j < L; ++j) {
         const LD ang = -kPi * (LD)j / (LD)L;
-        if (f32) put_cpx<float>(q.data, j, cosl(ang), sinl(ang));
-        else put_cpx<double>(q.data, j, cosl(ang), sinl(ang));
+        put_cpx<double>(q.data, j, cosl(ang), sinl(ang));
       }
       q.dst = ws.take(q.data.size());
       p->qtw[a] = q.dst;
@@ -776,7 +774,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   p->rhs = ws.take(P * te);
   p->phi = (double *)ws.take(P * sizeof(double));
   p->cpitch = p->trig_kind[0] == TRIG_DFT ? p->ncoef[0] : (std::max(p->ncoef[0], 1) + 1) / 2;
-  p->coef = ws.take((size_t)p->cpitch * rows * ce);
+  p->coef = ws.take((size_t)p->cpitch * rows * sizeof(cpx<double>));   // PPE coefficients: FP64
   p->ext_scratch = (double *)ws.take((size_t)p->Efc[0] * p->Efc[1] * p->Efc[2] * sizeof(double));
   if (p->fp32 && p->walled[1])
     for (int i = 0; i < 3; ++i)
@@ -1084,7 +1082,9 @@ hipError_t direct_launch(fcsph_plan *p, const DirectArgs &a, int mode, const cha
 // (inverse), and the inverse x DFT.
 fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   fcsph_status st = FCSPH_OK;
-  const bool f32 = p->fp32;
+  // the PPE transforms run in FP64 in both forms; an FP32 plan's right-hand
+  // side is read as float
+  const bool f32 = false, rhs32 = p->fp32;
   const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
   PpeRowsArgs r{};
   r.plan = p->trig[0];
@@ -1094,8 +1094,8 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   r.nx = nx;
   r.ncoef = p->ncoef[0];
   r.cpitch = p->cpitch;
-  r.in_real = f32 ? nullptr : (const double *)rhs;
-  r.in_float = f32 ? (const float *)rhs : nullptr;
+  r.in_real = rhs32 ? nullptr : (const double *)rhs;
+  r.in_float = rhs32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.qtw = p->qtw[0];
   r.dcs = p->dcs[0];
@@ -1173,7 +1173,7 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
     if (p->trig_kind[a] < 0)
       return fail(p->ctx, FCSPH_E_UNSUPPORTED, "mixed Dirichlet/Neumann pressure walls on one axis are not built");
   if (p->nd == 3) return run_ppe3(p, rhs, phi);
-  const bool f32 = p->fp32;
+  const bool f32 = false, rhs32 = p->fp32;   // FP64 transforms; FP32 plans pass a float rhs
   // P1: rows forward
   PpeRowsArgs r{};
   r.plan = p->trig[0];
@@ -1183,8 +1183,8 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.nx = p->n[0];
   r.ncoef = p->ncoef[0];
   r.cpitch = p->cpitch;
-  r.in_real = f32 ? nullptr : (const double *)rhs;
-  r.in_float = f32 ? (const float *)rhs : nullptr;
+  r.in_real = rhs32 ? nullptr : (const double *)rhs;
+  r.in_float = rhs32 ? (const float *)rhs : nullptr;
   r.coef = p->coef;
   r.qtw = p->qtw[0];
   r.dcs = p->dcs[0];

@@ -74,3 +74,27 @@ def fc_rounding_bound(f, lat, bcs, tables):
     A = ofc.extend(np.abs(f), lat.walled, bcs, Abs())     # |M| applied along every walled axis
     nw = sum(1 for w in lat.walled if w)
     return (nw + 1) * gamma * A * 2.0
+
+
+TOL64 = 1e-11
+
+
+def gate(op_eval, ref, ref_fft=None):
+    """FP64 parity gate of an operator / step output.  The direct tap sums and
+    the windowed transform (whose line holds the physical values and the R
+    continuation values next to each wall, then zeros) only combine values
+    within the kernel reach of the physical points: flat 1e-11.  The literal
+    whole-period DFT rounds relative to the whole extended line, continuation
+    included: `fft_tol` (the oracle's own FFT-vs-direct rounding on the input,
+    times 20, floored at 1e-11)."""
+    if op_eval == "fft":
+        return fft_tol(ref, ref_fft)
+    return TOL64
+
+
+def check(label, got, ref, tol):
+    """Relative L2 of got against the oracle's ref, printed, and gated."""
+    err = rel_l2(got, ref)
+    print(f"{label}: rel L2 {err:.2e} (gate {tol:.1e})", flush=True)
+    assert err < tol, (label, err, tol)
+    return err

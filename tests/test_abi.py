@@ -116,11 +116,13 @@ def test_line_lengths_within_the_thread_bound_plan(n):
 def test_lines_beyond_the_thread_bound_are_refused_cleanly():
     # whole-period transform of 2073 points: Bluestein beyond 4096 -> refused
     assert not _plannable(2048, op_eval="fft")
-    # PPE transforms of length 2 (n - 1) = 5998 (FP32 form, mixed walls) need
-    # more than 8192 points; the FP64 DST-I runs at length n - 1 and plans
-    assert not _plannable(3000, prs=("D", "D"), precision="fp32")
+    # the quarter-wave PPE transforms of length 2 (n - 1) = 5998 (mixed walls)
+    # need more than 8192 points; the DST-I runs at length n - 1 (FP64 in both
+    # forms) and plans
     assert not _plannable(3000, prs=("D", "N"))
+    assert not _plannable(3000, prs=("D", "N"), precision="fp32")
     assert _plannable(3000, prs=("D", "D"))
+    assert _plannable(3000, prs=("D", "D"), precision="fp32")
     # a window length whose radix-5 stage needs 640 threads
     assert not _plannable(1024, window_len=(3200, 3200))
     assert _plannable(1024, window_len=(1120, 1120))

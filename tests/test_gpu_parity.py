@@ -4,18 +4,22 @@ Gates (FP64):
 * fc_extend: physical values bitwise; every continuation value within the
   element-wise rounding bound of the 2d-term FC dot products around an
   extended-precision evaluation of the same definition.
-* operators / step: relative L2 <= 1e-11, raised to 20x the rounding error an
-  FP64 FFT evaluation of the same convolution shows on the input when that is
-  larger (non-smooth inputs: the FFT rounds relative to the norm of the whole
-  extended line, which the continuation can make much larger than the field).
+* operators / step, direct tap sums and windowed transform: relative L2 <=
+  1e-11 (flat);
+* operators / step, whole-period DFT: 1e-11, raised to 20x the rounding error
+  an FP64 FFT evaluation of the same convolution shows on the input when that
+  is larger (non-smooth inputs: the FFT rounds relative to the norm of the
+  whole extended line, which the continuation can make much larger than the
+  field);
 * PPE: relative L2 <= 1e-11.
+Every test prints its measured errors.
 Sizes span several line lengths (direct radices and Bluestein), ragged row
 counts, odd and even extended lengths, and every wall type.
 """
 import numpy as np
 import pytest
 
-from gpu_helpers import fc_rounding_bound, fft_tol, lattice, problem, rel_l2, spec, to_dev, to_np
+from gpu_helpers import check, fc_rounding_bound, fft_tol, gate, lattice, problem, rel_l2, spec, to_dev, to_np
 from oracle import fc as ofc
 from oracle import operators, ppe, step
 from paper_2606_06247_amd import synth
@@ -75,24 +79,21 @@ def test_operators(ctx, fc_tables, s, op_eval):
     from paper_2606_06247_amd import api
     plan = api.Plan(ctx, problem(s, op_eval=op_eval))
     ops = operators.Operators(lattice(s), fc_tables)
-    opf = operators.Operators(lattice(s), fc_tables, mode="fft")
+    opf = operators.Operators(lattice(s), fc_tables, mode="fft") if op_eval == "fft" else None
     f = field(s, 2)
     g = field(s, 3)
     for fc_class, name in ((api.VELOCITY, "u"), (api.PRESSURE, "p")):
         got = [to_np(t) for t in plan.spectral_grad(to_dev(f), fc_class)]
         ref = ops.grad(f, name)
-        reff = opf.grad(f, name)
+        reff = opf.grad(f, name) if opf else [None] * 2
         for a in range(2):
-            tol = fft_tol(ref[a], reff[a])
-            assert rel_l2(got[a], ref[a]) < tol, (name, a, rel_l2(got[a], ref[a]), tol)
+            check(f"grad{a} {name} {op_eval}", got[a], ref[a], gate(op_eval, ref[a], reff[a]))
         lap = to_np(plan.spectral_lap(to_dev(f), fc_class))
         ref = ops.lap(f, name)
-        tol = fft_tol(ref, opf.lap(f, name))
-        assert rel_l2(lap, ref) < tol, (rel_l2(lap, ref), tol)
+        check(f"lap {name} {op_eval}", lap, ref, gate(op_eval, ref, opf.lap(f, name) if opf else None))
     div = to_np(plan.spectral_div([to_dev(f), to_dev(g)]))
     ref = ops.div([f, g])
-    tol = fft_tol(ref, opf.div([f, g]))
-    assert rel_l2(div, ref) < tol, (rel_l2(div, ref), tol)
+    check(f"div {op_eval}", div, ref, gate(op_eval, ref, opf.div([f, g]) if opf else None))
 
 
 PPE_CASES = [
@@ -117,7 +118,7 @@ def test_ppe_solve(ctx, s, eig):
     b = field(s, 4)
     got = to_np(plan.ppe_solve(to_dev(b)))
     ref = ppe.solve(b, lattice(s), family=eig)
-    assert rel_l2(got, ref) < TOL, rel_l2(got, ref)
+    check(f"ppe {eig}", got, ref, TOL)
 
 
 STEP_CASES = [
@@ -145,12 +146,41 @@ def test_project_step(ctx, fc_tables, s, op_eval):
     pd = torch.empty_like(ud[0])
     plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
     ref_u, ref_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
-    fft_u, fft_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+    fft_u, fft_p = (step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+                    if op_eval == "fft" else ([None] * 2, None))
     for a in range(2):
-        tol = fft_tol(ref_u[a], fft_u[a])
-        assert rel_l2(to_np(ud[a]), ref_u[a]) < tol, (a, rel_l2(to_np(ud[a]), ref_u[a]), tol)
-    tol = fft_tol(ref_p, fft_p)
-    assert rel_l2(to_np(pd), ref_p) < tol, (rel_l2(to_np(pd), ref_p), tol)
+        check(f"step u{a} {op_eval}", to_np(ud[a]), ref_u[a], gate(op_eval, ref_u[a], fft_u[a]))
+    check(f"step p {op_eval}", to_np(pd), ref_p, gate(op_eval, ref_p, fft_p))
+
+
+RANDOM_STEP_CASES = [
+    spec((33, 40), (True, True), vel=(("D", "N"), ("N", "D"))),            # ragged, mixed walls
+    spec((128, 96), (True, True), vel=(("N", "N"), ("D", "D"))),
+    spec((64, 64), (True, True)),
+]
+
+
+@pytest.mark.parametrize("op_eval", ["fft_window", "direct"])
+@pytest.mark.parametrize("s", RANDOM_STEP_CASES, ids=lambda s: f"{s['n']}-{s['vel']}")
+def test_project_step_random_inputs(ctx, fc_tables, s, op_eval):
+    """Random (non-smooth) velocity, forcing and wall data: the routes that
+    only combine values within the kernel reach keep the flat FP64 gate."""
+    import torch
+    from paper_2606_06247_amd import api
+    plan = api.Plan(ctx, problem(s, op_eval=op_eval))
+    lat = lattice(s)
+    shape = tuple(reversed(s["n"]))
+    u = [synth.random_field(shape, 60), synth.random_field(shape, 61)]
+    f = [synth.random_field(shape, 62), synth.random_field(shape, 63)]
+    w = [synth.random_field(shape, 64), synth.random_field(shape, 65)]
+    dt, nu = 1e-4, 1e-3
+    ud = [to_dev(c) for c in u]
+    pd = torch.empty_like(ud[0])
+    plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
+    ref_u, ref_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
+    for a in range(2):
+        check(f"random step u{a} {op_eval}", to_np(ud[a]), ref_u[a], TOL)
+    check(f"random step p {op_eval}", to_np(pd), ref_p, TOL)
 
 
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window", "direct"])
@@ -174,8 +204,8 @@ def test_decaying_flow_1024_one_step(ctx, fc_tables, op_eval):
     plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
     ref_u, ref_p = step.project_step(lattice(s), fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
     for a in range(2):
-        assert rel_l2(to_np(ud[a]), ref_u[a]) < TOL
-    assert rel_l2(to_np(pd), ref_p) < TOL
+        check(f"1024^2 step u{a} {op_eval}", to_np(ud[a]), ref_u[a], TOL)
+    check(f"1024^2 step p {op_eval}", to_np(pd), ref_p, TOL)
 
 
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window", "direct"])
@@ -202,13 +232,14 @@ def test_decaying_flow_trajectory_20_steps(ctx, fc_tables, op_eval):
         w = list(flow.velocity((k + 1) * dt))
         plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
         u, p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
-        uf, pf = step.project_step(lat, fc_tables, uf, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
-    # rounding differences grow with the scheme's corner mode (x1.46 per step),
-    # so the gate is the FP64 FFT-vs-direct trajectory difference of the oracle
+        if op_eval == "fft":
+            uf, pf = step.project_step(lat, fc_tables, uf, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+    # rounding differences grow with the scheme's corner mode (x1.46 per step);
+    # the whole-period route is gated by the oracle's own FFT-vs-direct
+    # trajectory difference, the other routes at the flat gate
     for a in range(2):
-        tol = fft_tol(u[a], uf[a])
-        assert rel_l2(to_np(ud[a]), u[a]) < tol, (rel_l2(to_np(ud[a]), u[a]), tol)
-    assert rel_l2(to_np(pd), p) < fft_tol(p, pf)
+        check(f"20-step u{a} {op_eval}", to_np(ud[a]), u[a], gate(op_eval, u[a], uf[a]))
+    check(f"20-step p {op_eval}", to_np(pd), p, gate(op_eval, p, pf if op_eval == "fft" else None))
 
 
 # ---------------------------------------------------------------- 3D channel
@@ -252,25 +283,22 @@ def test_operators_3d(ctx, fc_tables, s, op_eval):
     from paper_2606_06247_amd import api
     plan = api.Plan(ctx, problem(s, op_eval=op_eval))
     ops = operators.Operators(lattice(s), fc_tables)
-    opf = operators.Operators(lattice(s), fc_tables, mode="fft")
+    opf = operators.Operators(lattice(s), fc_tables, mode="fft") if op_eval == "fft" else None
     u = channel_fields(s, 30)
     r = synth.random_field(tuple(reversed(s["n"])), 6)
     for f in (u[0], r):
         for fc_class, name in ((api.VELOCITY, "u"), (api.PRESSURE, "p")):
             got = [to_np(t) for t in plan.spectral_grad(to_dev(f), fc_class)]
             ref = ops.grad(f, name)
-            reff = opf.grad(f, name)
+            reff = opf.grad(f, name) if opf else [None] * 3
             for a in range(3):
-                tol = fft_tol(ref[a], reff[a])
-                assert rel_l2(got[a], ref[a]) < tol, (name, a, rel_l2(got[a], ref[a]), tol)
+                check(f"3D grad{a} {name} {op_eval}", got[a], ref[a], gate(op_eval, ref[a], reff[a]))
             lap = to_np(plan.spectral_lap(to_dev(f), fc_class))
             ref = ops.lap(f, name)
-            tol = fft_tol(ref, opf.lap(f, name))
-            assert rel_l2(lap, ref) < tol, (rel_l2(lap, ref), tol)
+            check(f"3D lap {name} {op_eval}", lap, ref, gate(op_eval, ref, opf.lap(f, name) if opf else None))
     div = to_np(plan.spectral_div([to_dev(c) for c in u]))
     ref = ops.div(u)
-    tol = fft_tol(ref, opf.div(u))
-    assert rel_l2(div, ref) < tol, (rel_l2(div, ref), tol)
+    check(f"3D div {op_eval}", div, ref, gate(op_eval, ref, opf.div(u) if opf else None))
 
 
 @pytest.mark.parametrize("eig", ["spectral", "fd2"])
@@ -281,7 +309,7 @@ def test_ppe_solve_3d(ctx, s, eig):
     b = synth.random_field(tuple(reversed(s["n"])), 7)
     got = to_np(plan.ppe_solve(to_dev(b)))
     ref = ppe.solve(b, lattice(s), family=eig)
-    assert rel_l2(got, ref) < TOL, rel_l2(got, ref)
+    check(f"3D ppe {eig}", got, ref, TOL)
 
 
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window"])
@@ -299,30 +327,24 @@ def test_project_step_3d(ctx, fc_tables, s, op_eval):
     pd = torch.empty_like(ud[0])
     plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
     ref_u, ref_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
-    fft_u, fft_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+    fft_u, fft_p = (step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+                    if op_eval == "fft" else ([None] * 3, None))
     for a in range(3):
-        tol = fft_tol(ref_u[a], fft_u[a])
-        assert rel_l2(to_np(ud[a]), ref_u[a]) < tol, (a, rel_l2(to_np(ud[a]), ref_u[a]), tol)
-    tol = fft_tol(ref_p, fft_p)
-    assert rel_l2(to_np(pd), ref_p) < tol, (rel_l2(to_np(pd), ref_p), tol)
+        check(f"3D step u{a} {op_eval}", to_np(ud[a]), ref_u[a], gate(op_eval, ref_u[a], fft_u[a]))
+    check(f"3D step p {op_eval}", to_np(pd), ref_p, gate(op_eval, ref_p, fft_p))
 
 
 # ---------------------------------------------------------------- FP32-mixed form
 # FFT and operator passes in FP32; FC, the divergence that forms the PPE
 # right-hand side, the PPE divide / zero mode and the step accumulation in
-# FP64.  Gate: relative L2 <= 1e-5 against the FP64 oracle on manufactured
-# (smooth) fields for the windowed and direct evaluations; the measured error
-# is printed.  The whole-period FFT evaluation in FP32 rounds relative to the
-# norm of the whole extended line, which the continuation can make 10^2-10^3
-# times larger than the field (Neumann walls on data that is not
-# Neumann-compatible), so its gate is 1e-3 and its measured error is reported.
+# FP64.  Gate: relative L2 <= 1e-5 against the FP64 oracle on every route;
+# the measured error is printed.
 TOL32 = 1e-5
-TOL32_FULL_PERIOD = 1e-3
 FP32_EVALS = ["fft", "fft_window", "direct"]
 
 
 def tol32(op_eval):
-    return TOL32_FULL_PERIOD if op_eval == "fft" else TOL32
+    return TOL32
 
 
 FP32_CASES = [
@@ -337,8 +359,27 @@ def smooth2(s, seed):
     return synth.poly_trig_2d(s["n"], seed, dx=s["dx"])
 
 
-@pytest.mark.parametrize("op_eval", FP32_EVALS)
-@pytest.mark.parametrize("s", FP32_CASES, ids=lambda s: f"{s['n']}-{s['vel']}")
+# The FP32 form on the whole-period DFT misses the 1e-5 target where the
+# continuation of the input is much larger than the field (Neumann walls on
+# data that is not Neumann-compatible): the FP32 transform rounds relative to
+# the whole extended line.  Measured 2e-5 to 1.6e-4 (below); the windowed and
+# direct routes, which only use the continuation values within the kernel
+# reach, meet it.
+FP32_WHOLE_PERIOD_MISS = pytest.mark.xfail(
+    strict=True, reason="FP32 whole-period DFT rounds relative to the continuation (measured 2e-5 to 1.6e-4)")
+
+
+def fp32_op_cases():
+    out = []
+    for s in FP32_CASES:
+        for oe in FP32_EVALS:
+            miss = oe == "fft" and s["n"] != (64, 64)
+            out.append(pytest.param(s, oe, marks=FP32_WHOLE_PERIOD_MISS if miss else (),
+                                    id=f"{s['n']}-{s['vel']}-{oe}"))
+    return out
+
+
+@pytest.mark.parametrize("s,op_eval", fp32_op_cases())
 def test_fp32_operators_2d(ctx, fc_tables, s, op_eval):
     from paper_2606_06247_amd import api
     plan = api.Plan(ctx, problem(s, precision="fp32", op_eval=op_eval))
@@ -500,7 +541,7 @@ def test_ppe_3d_256_manufactured(ctx):
         phi += c * prod
         lap -= c * (kx * kx + ky * ky + kz * kz) * prod
     got = to_np(plan.ppe_solve(to_dev(lap)))
-    assert rel_l2(got, phi) < TOL, rel_l2(got, phi)
+    check("256^3 manufactured ppe", got, phi, TOL)
 
 
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window"])
@@ -518,3 +559,45 @@ def test_project_step_3d_256_walls(ctx, channel256, op_eval):
         assert torch.equal(u[q][:, -1, :], w[q][:, -1, :])
         assert bool(torch.isfinite(u[q]).all())
     assert bool(torch.isfinite(p).all())
+
+
+# ---------------------------------------------------------------- 3D whole step, element-wise
+# One whole step of the channel at 128^3 (extended 128 x 153 x 128): the
+# largest size whose oracle step (direct tap sums, dense per-axis PPE) runs
+# in seconds.  The same kernels and launch sequence as the 256^3 channel
+# (x passes, strided y and z passes, z symbol passes, PPE rows / y / z).
+N3S = 128
+
+
+@pytest.fixture(scope="module")
+def channel128_ref(fc_tables):
+    s = _spec3(N3S)
+    lat = lattice(s)
+    u = [np.ascontiguousarray(c) for c in synth.ChannelFlow3D((N3S,) * 3, 20, 21).u]
+    w = [np.zeros_like(u[0])] * 3
+    dx = s["dx"]
+    nu = 1e-3
+    dt = min(0.2 * dx, 0.1 * dx * dx / nu)
+    ref = step.project_step(lat, fc_tables, u, wall=w, dt=dt, nu=nu)
+    return s, u, w, dt, nu, ref
+
+
+@pytest.mark.parametrize("precision,op_eval", [("fp64", "fft_window"), ("fp64", "fft"), ("fp32", "fft_window")])
+def test_project_step_3d_128_full(ctx, fc_tables, channel128_ref, precision, op_eval):
+    import torch
+    from paper_2606_06247_amd import api
+    s, u, w, dt, nu, (ref_u, ref_p) = channel128_ref
+    plan = api.Plan(ctx, problem(s, precision=precision, op_eval=op_eval))
+    ud = [to_dev(c) for c in u]
+    pd = torch.empty_like(ud[0])
+    plan.project_step(ud, dt, nu, p_out=pd, force=None, wall=[to_dev(c) for c in w])
+    if precision == "fp32":
+        tols = [TOL32] * 4
+    elif op_eval == "fft":
+        fu, fp = step.project_step(lattice(s), fc_tables, u, wall=w, dt=dt, nu=nu, opmode="fft")
+        tols = [gate("fft", r, f) for r, f in zip(ref_u + [ref_p], fu + [fp])]
+    else:
+        tols = [TOL] * 4
+    for a, name in enumerate(("u", "v", "w")):
+        check(f"128^3 step {name} {precision} {op_eval}", to_np(ud[a]), ref_u[a], tols[a])
+    check(f"128^3 step p {precision} {op_eval}", to_np(pd), ref_p, tols[3])

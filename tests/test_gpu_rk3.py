@@ -4,7 +4,7 @@ velocity, the sub-step pressure and the stored F after every sub-step."""
 import numpy as np
 import pytest
 
-from gpu_helpers import fft_tol, lattice, problem, rel_l2, spec, to_dev, to_np
+from gpu_helpers import check, gate, lattice, problem, rel_l2, spec, to_dev, to_np
 from oracle import step
 from paper_2606_06247_amd import synth
 
@@ -49,8 +49,11 @@ def run_rk3(ctx, fc_tables, s, u, f, w, dt, nu, precision="fp64", op_eval="fft_w
         fr = f[k] if f is not None else None
         ref_u, ref_p, ref_F = step.rk3_substep(lat, fc_tables, ref_u, k, F_prev=ref_F, force=fr, wall=w[k],
                                                dt=dt, nu=nu)
-        fft_u, fft_p, fft_F = step.rk3_substep(lat, fc_tables, fft_u, k, F_prev=fft_F, force=fr, wall=w[k],
-                                               dt=dt, nu=nu, opmode="fft")
+        if op_eval == "fft":
+            fft_u, fft_p, fft_F = step.rk3_substep(lat, fc_tables, fft_u, k, F_prev=fft_F, force=fr, wall=w[k],
+                                                   dt=dt, nu=nu, opmode="fft")
+        else:
+            fft_u, fft_p, fft_F = [None] * nd, None, [None] * nd
         gpu = ([to_np(c) for c in ud], to_np(pd), [to_np(c) for c in Fd])
         out.append((gpu, (ref_u, ref_p, ref_F), (fft_u, fft_p, fft_F)))
     return out
@@ -66,12 +69,9 @@ def test_rk3_substeps_2d(ctx, fc_tables, s, op_eval):
     res = run_rk3(ctx, fc_tables, s, u, f, w, 1e-4, 1e-3, op_eval=op_eval)
     for k, ((gu, gp, gF), (ru, rp, rF), (fu, fp, fF)) in enumerate(res):
         for a in range(2):
-            tol = fft_tol(ru[a], fu[a])
-            assert rel_l2(gu[a], ru[a]) < tol, (k, a, rel_l2(gu[a], ru[a]), tol)
-            tol = fft_tol(rF[a], fF[a])
-            assert rel_l2(gF[a], rF[a]) < tol, (k, "F", a, rel_l2(gF[a], rF[a]), tol)
-        tol = fft_tol(rp, fp)
-        assert rel_l2(gp, rp) < tol, (k, rel_l2(gp, rp), tol)
+            check(f"RK3 {k} u{a} {op_eval}", gu[a], ru[a], gate(op_eval, ru[a], fu[a]))
+            check(f"RK3 {k} F{a} {op_eval}", gF[a], rF[a], gate(op_eval, rF[a], fF[a]))
+        check(f"RK3 {k} p {op_eval}", gp, rp, gate(op_eval, rp, fp))
 
 
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window"])
@@ -84,12 +84,9 @@ def test_rk3_substeps_3d_channel(ctx, fc_tables, op_eval):
     res = run_rk3(ctx, fc_tables, s, u, f, w, 1e-4, 1e-3, op_eval=op_eval)
     for k, ((gu, gp, gF), (ru, rp, rF), (fu, fp, fF)) in enumerate(res):
         for a in range(3):
-            tol = fft_tol(ru[a], fu[a])
-            assert rel_l2(gu[a], ru[a]) < tol, (k, a, rel_l2(gu[a], ru[a]), tol)
-            tol = fft_tol(rF[a], fF[a])
-            assert rel_l2(gF[a], rF[a]) < tol, (k, "F", a, rel_l2(gF[a], rF[a]), tol)
-        tol = fft_tol(rp, fp)
-        assert rel_l2(gp, rp) < tol, (k, rel_l2(gp, rp), tol)
+            check(f"RK3 3D {k} u{a} {op_eval}", gu[a], ru[a], gate(op_eval, ru[a], fu[a]))
+            check(f"RK3 3D {k} F{a} {op_eval}", gF[a], rF[a], gate(op_eval, rF[a], fF[a]))
+        check(f"RK3 3D {k} p {op_eval}", gp, rp, gate(op_eval, rp, fp))
 
 
 @pytest.mark.parametrize("op_eval", ["fft_window", "direct"])
@@ -99,21 +96,10 @@ def test_rk3_substeps_fp32(ctx, fc_tables, op_eval):
     u = [smooth(10), smooth(11)]
     w = [[c.copy() for c in u] for _ in range(3)]
     res = run_rk3(ctx, fc_tables, s, u, None, w, 1e-4, 1e-3, precision="fp32", op_eval=op_eval)
-    a = step.RK3_A
-    scale0 = a[0] * np.linalg.norm(res[0][1][1])       # |a_0 phi_0| of the oracle
     for k, ((gu, gp, gF), (ru, rp, rF), _) in enumerate(res):
-        errs = [rel_l2(gu[a_], ru[a_]) for a_ in range(2)] + [rel_l2(gp, rp)]
-        # The FP32 PPE transforms round relative to what they carry: the first
-        # sub-step projects this random, far from divergence-free input and
-        # leaves a residual divergence of that size times FP32 rounding, which
-        # the later sub-steps' much smaller pressure carries.  Their pressure is
-        # gated against the first sub-step's projection potential a_0 phi_0
-        # (plain relative errors measured 4.8e-5 and 4.2e-4 at sub-steps 1, 2;
-        # 5.7e-6 and 1.7e-6 on that scale); the velocity keeps the 1e-5 target.
-        perr = a[k] * np.linalg.norm(gp - rp) / scale0
-        print("fp32 RK3 sub-step", k, op_eval, [f"{e:.2e}" for e in errs], f"p vs a0 phi0 {perr:.2e}")
-        assert max(errs[:2]) < TOL32, (k, errs)
-        assert perr < TOL32, (k, perr, errs)
+        for a_ in range(2):
+            check(f"fp32 RK3 {k} u{a_} {op_eval}", gu[a_], ru[a_], TOL32)
+        check(f"fp32 RK3 {k} p {op_eval}", gp, rp, TOL32)
 
 
 def test_rk3_step_1024_decaying_flow(ctx, fc_tables):
@@ -130,17 +116,35 @@ def test_rk3_step_1024_decaying_flow(ctx, fc_tables):
     f = [list(flow.force(0.5 * (t[k] + t[k + 1]))) for k in range(3)]
     w = [list(flow.velocity(t[k + 1])) for k in range(3)]
     res = run_rk3(ctx, fc_tables, s, u, f, w, dt, nu, op_eval="fft_window")
-    for k, ((gu, gp, gF), (ru, rp, rF), (fu, fp, fF)) in enumerate(res):
+    for k, ((gu, gp, gF), (ru, rp, rF), _) in enumerate(res):
         for c in range(2):
-            assert rel_l2(gu[c], ru[c]) < TOL, (k, c, rel_l2(gu[c], ru[c]))
-            assert rel_l2(gF[c], rF[c]) < TOL, (k, "F", c, rel_l2(gF[c], rF[c]))
-        # sub-steps 1 and 2 project an almost divergence-free state, so the
-        # rounding of any FFT evaluation shows more in their small pressure:
-        # the FFT gate of the suite (20x the oracle's own FP64 FFT-vs-direct
-        # difference on this input, at least 1e-11)
-        tol = fft_tol(rp, fp)
-        print("RK3 1024^2 sub-step", k, "p rel L2", f"{rel_l2(gp, rp):.2e}", "gate", f"{tol:.2e}")
-        assert rel_l2(gp, rp) < tol, (k, rel_l2(gp, rp), tol)
+            check(f"RK3 1024^2 chained {k} u{c}", gu[c], ru[c], TOL)
+            check(f"RK3 1024^2 chained {k} F{c}", gF[c], rF[c], TOL)
+        if k == 0:
+            check(f"RK3 1024^2 chained {k} p", gp, rp, TOL)
+        else:
+            # the chained sub-step starts from the GPU's own previous velocity,
+            # whose rounding (~1e-14, white) the divergence amplifies by about
+            # 1 / dx against the small divergence of an almost projected state:
+            # reported, and the pressure is gated from a common input below
+            print(f"RK3 1024^2 chained {k} p: rel L2 {rel_l2(gp, rp):.2e} (reported)")
+    # sub-steps 1 and 2 from the oracle's state (u^k, F^{k-1}): one sub-step of
+    # parity at the flat gate, pressure included
+    import torch
+    from paper_2606_06247_amd import api
+    plan = api.Plan(ctx, problem(s, op_eval="fft_window"))
+    for k in (1, 2):
+        (_, _, _), (ru0, _, rF0), _ = res[k - 1]
+        (_, _, _), (ru, rp, rF), _ = res[k]
+        ud = [to_dev(c) for c in ru0]
+        Fd = [to_dev(c) for c in rF0]
+        pd = torch.empty_like(ud[0])
+        plan.rk3_substep(k, ud, Fd, dt, nu, p_out=pd, force=[to_dev(c) for c in f[k]],
+                         wall=[to_dev(c) for c in w[k]])
+        for c in range(2):
+            check(f"RK3 1024^2 from oracle state {k} u{c}", to_np(ud[c]), ru[c], TOL)
+            check(f"RK3 1024^2 from oracle state {k} F{c}", to_np(Fd[c]), rF[c], TOL)
+        check(f"RK3 1024^2 from oracle state {k} p", to_np(pd), rp, TOL)
 
 
 def test_rk3_rejects_bad_substep(ctx):
