@@ -201,6 +201,24 @@ fcsph_status fcsph_spectral_div(fcsph_plan *p, const double *const *u, void *div
 /* Spectral SPH Laplacian: f convolved with dV lap W (kernel Laplacian). */
 fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *lap);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Laplacian as fcsph_spectral_lap, same kernels and launch sequence, same
+ * arguments and output, but its intermediate spectra (x spectra, output
+ * spectra, the y-extended spectra in 3D, the FP64 boundary rows of FP32
+ * plans, the ghost values of the direct route) live in a fixed 64 MiB static
+ * device array instead of the plan's workspace.  Allocates nothing and calls
+ * no allocating routine.
+ * Limit: lattices whose intermediates need more than 64 MiB (for example
+ * 2D beyond about 1900^2 windowed FP64, 3D beyond about 128^3) return
+ * FCSPH_E_UNSUPPORTED with the needed size in the context's message.
+ * The array is one per GPU and shared by every call on that GPU: calls that
+ * overlap on one GPU (other contexts, streams or host threads) race on it;
+ * it keeps the last call's contents (every element a call reads it has
+ * written first, so nothing needs clearing).  FCSPH_E_HIP if the array's
+ * device address could not be obtained at context creation. */
+fcsph_status fcsph_spectral_lap_noalloc(fcsph_plan *p, int fc, const double *f, void *lap);
+
 /*
  * Spectral PPE on the physical lattice (pressure section, eqs. DCTI4PPE,
  * DCTDFT_PPE and division4PPE): per axis a DFT (periodic), DCT-I (Neumann

@@ -36,7 +36,7 @@ EXPORTS = [
     "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
     "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
     "fcsph_spectral_div",
-    "fcsph_spectral_lap", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
+    "fcsph_spectral_lap", "fcsph_spectral_lap_noalloc", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
     "fcsph_ctx_read_timing", "fcsph_ctx_set_timing_only", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
     "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_rk3_substep", "fcsph_batch_add_ppe", "fcsph_batch_launch",
     "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_spectral_grad.argtypes = [vp, i, vp, P(vp)]
     L.fcsph_spectral_div.argtypes = [vp, P(vp), vp]
     L.fcsph_spectral_lap.argtypes = [vp, i, vp, vp]
+    L.fcsph_spectral_lap_noalloc.argtypes = [vp, i, vp, vp]
     L.fcsph_ppe_solve.argtypes = [vp, vp, vp]
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
     L.fcsph_rk3_substep.argtypes = [vp, i, P(vp), vp, P(vp), P(vp), P(vp), d, d]
@@ -343,6 +344,14 @@ class Plan:
         out = self._new(self.out_dtype) if out is None else out
         _check(lib().fcsph_spectral_lap(self.handle, field, self._phys(f), self._phys(out, self.out_dtype)),
                self.ctx.handle, "fcsph_spectral_lap")
+        return out
+
+    def spectral_lap_noalloc(self, f, field: int = VELOCITY, out=None):
+        """fcsph_spectral_lap_noalloc: the Laplacian with its intermediates in
+        the library's static device scratch (no allocation by the library)."""
+        out = self._new(self.out_dtype) if out is None else out
+        _check(lib().fcsph_spectral_lap_noalloc(self.handle, field, self._phys(f), self._phys(out, self.out_dtype)),
+               self.ctx.handle, "fcsph_spectral_lap_noalloc")
         return out
 
     def ppe_solve(self, rhs, out=None):

@@ -67,6 +67,44 @@ struct LaunchTimer {
 };
 }  // namespace
 
+// ------------------------------------------------------ static device scratch
+// Scratch of the no-allocation entry point (fcsph_spectral_lap_noalloc): a
+// file-scope device array of fixed size, one copy per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it names a stand-in, not device memory): each device's address comes
+// from hipGetSymbolAddress, taken once per device with that device current
+// (at context creation) and kept in g_scratch.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// With `device` current: record this device's address of the scratch array.
+void register_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) g_scratch[device] = ptr;
+  else g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
+void *scratch_of(int device, hipError_t *err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  *err = g_scratch[device] ? hipSuccess : g_scratch_err[device];
+  return g_scratch[device];
+}
+}  // namespace
+
 namespace {
 
 typedef long double LD;
@@ -1233,6 +1271,39 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   return FCSPH_OK;
 }
 
+// Scratch of one Laplacian evaluation: x spectra (S), y-extended spectra (Y,
+// 3D), output spectra (O), the FP64 boundary rows of FP32 plans (edge) and
+// the ghost values of the direct tap sums (gx, gy).
+struct LapBufs {
+  void *S, *Y, *O, *edge;
+  double *gx, *gy;
+};
+
+// Carve the buffers of one Laplacian evaluation out of a bump region (the
+// static scratch of the no-allocation entry point); dry run with a null base.
+void lap_scratch_layout(const fcsph_plan *p, Bump &ws, LapBufs &b) {
+  const size_t sb64 = p->spec_elems * sizeof(cpx<double>);
+  b.S = ws.take(sb64);
+  b.O = ws.take(sb64);
+  b.Y = p->nd == 3 ? ws.take(sb64) : nullptr;
+  b.edge = (p->fp32 && p->walled[1] && p->nd == 2)
+               ? ws.take((size_t)2 * p->n[2] * p->d.fc_d * p->H * sizeof(double2))
+               : nullptr;
+  if (p->direct) {
+    b.gx = (double *)ws.take((size_t)p->n[1] * p->n[2] * 2 * kSymR * sizeof(double));
+    b.gy = (double *)ws.take((size_t)2 * kSymR * (p->n[0] + 2 * kSymR) * p->n[2] * sizeof(double));
+  } else {
+    b.gx = b.gy = nullptr;
+  }
+}
+
+size_t lap_scratch_bytes(const fcsph_plan *p) {
+  Bump dry;
+  LapBufs b{};
+  lap_scratch_layout(p, dry, b);
+  return dry.off;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1263,6 +1334,7 @@ fcsph_status fcsph_ctx_create(int device, void *hip_stream, fcsph_ctx **out) {
     delete c;
     return FCSPH_E_HIP;
   }
+  register_scratch(device);
   *out = c;
   return FCSPH_OK;
 }
@@ -1474,40 +1546,70 @@ fcsph_status fcsph_spectral_grad(fcsph_plan *p, int fc, const double *f, void *c
   return FCSPH_OK;
 }
 
-fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *lap) {
-  if (!p) return FCSPH_E_INVALID;
-  if (!f || !lap) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+static fcsph_status lap_impl(fcsph_plan *p, int fc, const double *f, void *lap, const LapBufs &b) {
   fcsph_status st = FCSPH_OK;
   if (p->nd == 3) {
-    if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
-    if (!chk(p, y_fwd(p, 1, &p->S[0], &p->Y[0], fc, &f), "lap y", st)) return st;
+    if (!chk(p, x_fwd_single(p, f, fc, b.S), "lap x", st)) return st;
+    void *Sv = b.S, *Yv = b.Y, *Ov = b.O;
+    if (!chk(p, y_fwd(p, 1, &Sv, &Yv, fc, &f), "lap y", st)) return st;
     ColsArgs c = z_pass_args(p, COLS_OP);
-    c.in[0] = p->Y[0];
-    c.out[0][0] = p->O[0];
+    c.in[0] = b.Y;
+    c.out[0][0] = b.O;
     c.sym[0] = SYM_LAP;
     c.nout = 1;
     if (!chk(p, cols_launch(p, c, 1, "cols_z_op"), "lap z", st)) return st;
-    if (!chk(p, y_inv(p, 1, &p->O[0]), "lap y inv", st)) return st;
-    if (!chk(p, x_inv_store(p, p->O[0], nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
+    if (!chk(p, y_inv(p, 1, &Ov), "lap y inv", st)) return st;
+    if (!chk(p, x_inv_store(p, b.O, nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
     return FCSPH_OK;
   }
   if (p->direct) {
     DirectArgs a = direct_base(p, fc);
+    a.gx[0] = b.gx;
+    a.gy[0] = b.gy;
     a.in[0] = f;
     a.out[3] = lap;
     if (!chk(p, direct_launch(p, a, DIR_OPS, "direct_ops"), "lap", st)) return st;
     return FCSPH_OK;
   }
-  if (!chk(p, x_fwd_single(p, f, fc, p->S[0]), "lap x", st)) return st;
+  if (!chk(p, x_fwd_single(p, f, fc, b.S), "lap x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, fc);
-  if (!chk(p, set_edges(p, c, 1, &f, fc), "lap edges", st)) return st;
-  c.in[0] = p->S[0];
-  c.out[0][0] = p->O[0];
+  if (p->fp32 && b.edge && c.fc.on) {
+    if (!chk(p, edge_fwd(p, f, fc, b.edge), "lap edges", st)) return st;
+    c.edge[0] = (const double2 *)b.edge;
+  }
+  c.in[0] = b.S;
+  c.out[0][0] = b.O;
   c.nout = 1;
   c.sym[0] = SYM_LAP;
   if (!chk(p, cols_launch(p, c, 1, "cols_op"), "lap y", st)) return st;
-  if (!chk(p, x_inv_store(p, p->O[0], nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
+  if (!chk(p, x_inv_store(p, b.O, nullptr, lap, nullptr, !p->fp32, 1.0), "lap x inv", st)) return st;
   return FCSPH_OK;
+}
+
+fcsph_status fcsph_spectral_lap(fcsph_plan *p, int fc, const double *f, void *lap) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!f || !lap) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  if (fc != FCSPH_FIELD_VELOCITY && fc != FCSPH_FIELD_PRESSURE) return fail(p->ctx, FCSPH_E_INVALID, "bad field class");
+  return lap_impl(p, fc, f, lap, LapBufs{p->S[0], p->Y[0], p->O[0], p->edge[0], p->ghx[0], p->ghy[0]});
+}
+
+fcsph_status fcsph_spectral_lap_noalloc(fcsph_plan *p, int fc, const double *f, void *lap) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!f || !lap) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  if (fc != FCSPH_FIELD_VELOCITY && fc != FCSPH_FIELD_PRESSURE) return fail(p->ctx, FCSPH_E_INVALID, "bad field class");
+  const size_t need = lap_scratch_bytes(p);
+  if (need > kStaticScratchBytes)
+    return fail(p->ctx, FCSPH_E_UNSUPPORTED,
+                "lattice too large for the static scratch: needs " + std::to_string(need) + " bytes, the maximum is " +
+                    std::to_string(kStaticScratchBytes));
+  hipError_t e = hipSuccess;
+  char *base = static_cast<char *>(scratch_of(p->ctx->device, &e));
+  if (!base) return hip_fail(p->ctx, e, "static scratch address");
+  Bump bb;
+  bb.base = base;
+  LapBufs b{};
+  lap_scratch_layout(p, bb, b);
+  return lap_impl(p, fc, f, lap, b);
 }
 
 static fcsph_status div3_impl(fcsph_plan *p, const double *const *u, void *out, bool out_double, double scale) {
