@@ -86,7 +86,26 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *              FC(Gram) and the paper's blended polynomial FC are); copied at
  *              plan creation
  *  kernel, h_over_dx   SPH kernel and smoothing length h / dx
- *  prec        fcsph_precision;  ppe_domain  fcsph_ppe_domain;  eig  fcsph_eig
+ *  prec        fcsph_precision
+ *  ppe_domain  fcsph_ppe_domain.  FCSPH_PPE_PHYSICAL (the paper's solver): the
+ *              PPE on the physical lattice by per-axis transforms (section on
+ *              the spatial discretisation of pressure).  FCSPH_PPE_EXTENDED
+ *              (the fully periodic alternative named at the end of the section
+ *              integrating FC into the solver): the projection of u* on the
+ *              extended periodic lattice in its spectrum, phi_hat = (rho/dt)
+ *              sum_a S_a e_a / sum_a S_a^2 with e_a = DFT(FC(u*_a)) and S_a
+ *              the gradient symbols (modes where the sum vanishes get zero),
+ *              u <- IDFT(e_a - (dt/rho) S_a phi_hat) restricted, walls reset;
+ *              there the corrected spectrum has zero SPH divergence.  Needs
+ *              op_eval FCSPH_OPS_FFT and FP64 (else FCSPH_E_UNSUPPORTED); it
+ *              changes fcsph_project_step only (fcsph_ppe_solve keeps the
+ *              physical-domain PPE; fcsph_rk3_substep refuses such plans).
+ *  eig         fcsph_eig, the eigenvalues of the PPE division (eq.
+ *              division4PPE): SPECTRAL, the exact wavenumbers of each axis
+ *              transform; FD2, second-order finite differences; SPH, sum_a
+ *              sigma_a(k)^2 with S_a = i sigma_a the gradient symbols (then
+ *              the PPE inverts div o grad of the method exactly), for 2D
+ *              lattices periodic on every axis and the FFT routes only
  *  rho         fluid density
  *  op_eval     fcsph_op_eval
  *  window_len[a], lines_per_group   schedule hints (0 = the library's

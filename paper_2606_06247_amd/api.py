@@ -133,8 +133,9 @@ class Problem:
     prs_bc: tuple = None
     h_over_dx: float = 1.3
     precision: str = "fp64"       # 'fp64' | 'fp32'
-    eig: str = "spectral"         # 'spectral' | 'fd2'
+    eig: str = "spectral"         # 'spectral' | 'fd2' | 'sph' (2D, every axis periodic)
     rho: float = 1.0
+    ppe_domain: str = "physical"  # 'physical' | 'extended' (projection on the extended lattice)
     op_eval: str = "fft"          # 'fft' | 'fft_window' | 'direct'
     fc_d: int = 5
     fc_C: int = 25
@@ -235,7 +236,7 @@ def make_desc(prob: "Problem"):
     d.kernel = KERNEL_WENDLAND_C2
     d.h_over_dx = prob.h_over_dx
     d.prec = FP32_MIXED if prob.precision == "fp32" else FP64
-    d.ppe_domain = PPE_PHYSICAL
+    d.ppe_domain = {"physical": PPE_PHYSICAL, "extended": PPE_EXTENDED}[prob.ppe_domain]
     d.eig = {"spectral": EIG_SPECTRAL, "fd2": EIG_FD2, "sph": EIG_SPH}[prob.eig]
     d.rho = prob.rho
     d.op_eval = {"fft": OPS_FFT, "direct": OPS_DIRECT, "fft_window": OPS_FFT_WINDOW}[prob.op_eval]

@@ -458,6 +458,10 @@ struct fcsph_plan {
   double *ghx[3] = {}, *ghy[3] = {};    // FC ghost values of up to 3 direct-pass inputs
   const Tap *taps = nullptr;
   int ntaps = 0, reach = 0;
+  // upper bound of sum_a sigma_a(k)^2 over every wavenumber (sum over the axes
+  // of the squared l1 norm of the gradient taps), for the zero-mode tolerance
+  // of the SPH family and the EXTENDED projection
+  double sigma2_bound = 0.0;
   size_t ws_bytes = 0;
 };
 
@@ -515,8 +519,21 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
     return FCSPH_E_INVALID;
   }
   if (d->op_eval == FCSPH_OPS_DIRECT && d->ndim != 2) { msg = "direct evaluation is built for 2D"; return FCSPH_E_UNSUPPORTED; }
-  if (d->ppe_domain != FCSPH_PPE_PHYSICAL) { msg = "only the physical-domain PPE is built"; return FCSPH_E_UNSUPPORTED; }
-  if (d->eig != FCSPH_EIG_SPECTRAL && d->eig != FCSPH_EIG_FD2) { msg = "eigenvalue family not built"; return FCSPH_E_UNSUPPORTED; }
+  if (d->ppe_domain != FCSPH_PPE_PHYSICAL && d->ppe_domain != FCSPH_PPE_EXTENDED) { msg = "bad PPE domain"; return FCSPH_E_INVALID; }
+  if (d->ppe_domain == FCSPH_PPE_EXTENDED && (d->op_eval != FCSPH_OPS_FFT || d->prec != FCSPH_FP64)) {
+    msg = "the EXTENDED projection is a division in the spectrum of the whole extended period: it needs "
+          "op_eval FCSPH_OPS_FFT and FP64";
+    return FCSPH_E_UNSUPPORTED;
+  }
+  if (d->eig != FCSPH_EIG_SPECTRAL && d->eig != FCSPH_EIG_FD2 && d->eig != FCSPH_EIG_SPH) { msg = "bad eigenvalue family"; return FCSPH_E_INVALID; }
+  if (d->eig == FCSPH_EIG_SPH) {
+    bool periodic = d->ndim == 2;
+    for (int a = 0; a < d->ndim; ++a) periodic = periodic && d->axis[a] == FCSPH_AXIS_PERIODIC;
+    if (!periodic || d->op_eval == FCSPH_OPS_DIRECT) {
+      msg = "the SPH eigenvalue family diagonalises the PPE on 2D lattices periodic on every axis (FFT routes)";
+      return FCSPH_E_UNSUPPORTED;
+    }
+  }
   if (!(d->rho > 0.0)) { msg = "rho must be positive"; return FCSPH_E_INVALID; }
   if (d->lines_per_group < 0 || d->lines_per_group > 16) { msg = "lines_per_group must be in 0..16"; return FCSPH_E_INVALID; }
   bool any_wall = false;
@@ -619,6 +636,10 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     u.dst = ws.take(u.data.size());
     p->taps = (const Tap *)u.dst;
     p->ntaps = (int)tl.size();
+    double l1[3] = {0.0, 0.0, 0.0};
+    for (const Tap &t : tl)
+      for (int a = 0; a < 3; ++a) l1[a] += std::fabs(t.w[a]);
+    p->sigma2_bound = l1[0] * l1[0] + l1[1] * l1[1] + l1[2] * l1[2];
     up.push_back(std::move(u));
     if (p->nd == 2)
       for (const Tap &t : tl) {
@@ -1059,6 +1080,7 @@ ColsArgs z_pass_args(fcsph_plan *p, int mode) {
 
 // y forward of nf spectra (FC along y with the field class's walls)
 hipError_t y_fwd(fcsph_plan *p, int nf, void *const *in, void *const *out, int fc, const double *const *fields) {
+  if (nf < 1 || nf > 3) return hipErrorInvalidValue;
   ColsArgs c = y_pass_args(p, COLS_FWD, fc);
   hipError_t e = set_edges(p, c, nf, fields, fc);
   if (e != hipSuccess) return e;
@@ -1072,6 +1094,7 @@ hipError_t y_fwd(fcsph_plan *p, int nf, void *const *in, void *const *out, int f
 
 // y inverse of nf spectra in place (y-extended layout), restricted to ny rows
 hipError_t y_inv(fcsph_plan *p, int nf, void *const *buf) {
+  if (nf < 1 || nf > 3) return hipErrorInvalidValue;
   ColsArgs c = y_pass_args(p, COLS_INV, FCSPH_FIELD_VELOCITY);
   for (int f = 0; f < nf; ++f) {
     c.in[f] = buf[f];
@@ -1254,6 +1277,16 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   c.dcs = p->dcs[1];
   c.B = pick_B(c.plan, f32, p->want_B, 1, ppe_line_len(p, 1));
   c.ldsM = padded_len(ppe_line_len(p, 1), c.plan.pad);
+  if (p->d.eig == FCSPH_EIG_SPH) {
+    // every axis periodic: the PPE's DFT wavenumbers are those of the symbol
+    // tables (E = n), whose weights carry 1 / (E_x E_y)
+    c.sph = 1;
+    c.symR = p->symR2;
+    c.sym_ninner = p->H;
+    c.ph_line = p->st.ph[1];
+    c.sph_norm = (double)p->E[0] * (double)p->E[1];
+    c.mu_tol = 1e-14 * p->sigma2_bound;
+  }
   {
     LaunchTimer t(p->ctx, "ppe_cols_solve");
     if (!chk(p, launch_ppe_cols(c, f32, p->ctx->stream), "ppe cols", st)) return st;
@@ -1675,6 +1708,83 @@ fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi) {
   return run_ppe(p, rhs, phi);
 }
 
+// EXTENDED PPE domain: the projection of u* on the extended periodic lattice
+// (its alternative to the physical-domain PPE in the section integrating FC
+// into the spectral ISPH solver): e_a = DFT(FC(u*_a)), phi_hat =
+// (rho/dt) sum_a S_a e_a / sum_a S_a^2 (zero where the sum vanishes),
+// u_a <- restriction of IDFT(e_a - (dt/rho) S_a phi_hat), Dirichlet walls
+// reset; p_out <- restriction of IDFT(phi_hat).
+static fcsph_status project_extended(fcsph_plan *p, double *const *u, double *p_out,
+                                     const double *const *wall_vel, double dt_proj) {
+  fcsph_status st = FCSPH_OK;
+  hipStream_t s = p->ctx->stream;
+  double *phi = p_out ? p_out : p->phi;
+  double norm = 1.0;
+  for (int a = 0; a < p->nd; ++a) norm *= (double)p->E[a];
+  ColsArgs c = p->nd == 2 ? cols_base(p, COLS_PROJ, FCSPH_FIELD_VELOCITY) : z_pass_args(p, COLS_PROJ);
+  c.B = 1;
+  c.proj_dtr = dt_proj / p->d.rho;
+  c.proj_tol = 1e-14 * p->sigma2_bound / (norm * norm);
+  c.proj_inv_norm = 1.0 / norm;
+  c.nout = p->nd + 1;
+  for (int q = 0; q < p->nd; ++q) c.sym[q] = q;     // SYM_GX, SYM_GY, SYM_GZ
+  RowsInvArgs r{};
+  r.plan = p->op[0];
+  r.nrows = p->n[1] * p->n[2];
+  r.nx = p->n[0];
+  r.E = p->E[0];
+  r.H = p->H;
+  r.B = 1;
+  r.ldsM = padded_len(r.plan.M, r.plan.pad);
+  r.spec_pitch = p->H;
+  r.rpp = p->n[1];
+  r.prow = p->nd == 3 ? p->E[1] : p->n[1];
+  for (int q = 0; q < p->nd; ++q) {
+    r.wall[q] = wall_vel ? wall_vel[q] : nullptr;
+    r.unew[q] = u[q];
+  }
+  r.assign = 1;
+  r.wi = wall_info(p);
+  if (p->nd == 2) {
+    if (!chk(p, x_fwd_pair(p, p->ustar[0], p->ustar[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "proj x", st))
+      return st;
+    c.in[0] = p->S[0];
+    c.in[1] = p->S[1];
+    for (int q = 0; q < 3; ++q) c.out[0][q] = p->O[q];
+    if (!chk(p, cols_launch(p, c, 1, "cols_proj"), "proj y", st)) return st;
+    r.spec[0] = p->O[0];
+    r.spec[1] = p->O[1];
+    {
+      LaunchTimer t(p->ctx, "rows_inv_proj");
+      if (!chk(p, launch_rows_inv(r, EPI_STEP_D2, false, s), "proj x inv", st)) return st;
+    }
+    if (!chk(p, x_inv_store(p, p->O[2], nullptr, phi, nullptr, true, 1.0), "proj phi x inv", st)) return st;
+    return FCSPH_OK;
+  }
+  if (!chk(p, x_fwd_pair(p, p->ustar[0], p->ustar[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "proj3 x", st))
+    return st;
+  if (!chk(p, x_fwd_single(p, p->ustar[2], FCSPH_FIELD_VELOCITY, p->S[2]), "proj3 x", st)) return st;
+  {
+    const double *us[3] = {p->ustar[0], p->ustar[1], p->ustar[2]};
+    if (!chk(p, y_fwd(p, 3, &p->S[0], &p->Y[0], FCSPH_FIELD_VELOCITY, us), "proj3 y", st)) return st;
+  }
+  for (int q = 0; q < 3; ++q) c.in[q] = p->Y[q];
+  for (int q = 0; q < 4; ++q) c.out[0][q] = p->O[q];
+  if (!chk(p, cols_launch(p, c, 1, "cols_z_proj"), "proj3 z", st)) return st;
+  // y inverse of the four outputs (a strided pass takes at most three fields)
+  if (!chk(p, y_inv(p, 3, &p->O[0]), "proj3 y inv", st)) return st;
+  if (!chk(p, y_inv(p, 1, &p->O[3]), "proj3 y inv", st)) return st;
+  r.spec[0] = p->O[0];
+  r.spec[1] = p->O[1];
+  r.spec[2] = p->O[2];
+  {
+    LaunchTimer t(p->ctx, "rows_inv_proj3");
+    if (!chk(p, launch_rows_inv(r, EPI_STEP_D3, false, s), "proj3 x inv", st)) return st;
+  }
+  if (!chk(p, x_inv_store(p, p->O[3], nullptr, phi, nullptr, true, 1.0), "proj3 phi x inv", st)) return st;
+  return FCSPH_OK;
+}
+
 // One projection step or RK3 sub-step.  u* uses dt and the RK terms; the
 // PPE right-hand side is (rho / dt_proj) div u* and the correction
 // u* - (dt_proj / rho) grad phi (eqs. PPE and u^n+1 with dt_proj = a_k dt;
@@ -1688,6 +1798,8 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
     if (!u[a]) return fail(p->ctx, FCSPH_E_INVALID, "null velocity component");
   if (!(dt > 0.0) || !std::isfinite(dt) || !(nu >= 0.0) || !std::isfinite(nu))
     return fail(p->ctx, FCSPH_E_INVALID, "dt must be positive and nu non-negative");
+  if (rk.on && p->d.ppe_domain == FCSPH_PPE_EXTENDED)
+    return fail(p->ctx, FCSPH_E_UNSUPPORTED, "RK3 sub-steps are built for the physical-domain PPE");
   fcsph_status st = FCSPH_OK;
   hipStream_t s = p->ctx->stream;
   const bool f32 = p->fp32;
@@ -1738,6 +1850,7 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
       LaunchTimer t(p->ctx, "rows_inv_step_a3");
       if (!chk(p, launch_rows_inv(r, EPI_STEP_A3, f32, s), "step3 A x inv", st)) return st;
     }
+    if (p->d.ppe_domain == FCSPH_PPE_EXTENDED) return project_extended(p, u, p_out, wall_vel, dt_proj);
     // B (FP64 transforms in both forms), C
     {
       Fp64Passes g64(p);
@@ -1856,6 +1969,7 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
     LaunchTimer t(p->ctx, "rows_inv_step_a");
     if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;
   }
+  if (p->d.ppe_domain == FCSPH_PPE_EXTENDED) return project_extended(p, u, p_out, wall_vel, dt_proj);
   // B: b = (rho/dt) div u*, FP64 transforms in both forms
   {
     Fp64Passes g64(p);

@@ -184,10 +184,17 @@ struct RowsInvArgs {
   double dt, nu, dt_over_rho;
   RkTerms rk;
   WallInfo wi;
+  // EPI_STEP_D2 / D3: 1 = the transformed values are the new velocity
+  // (EXTENDED projection, no u* read), 0 = u* - (dt/rho) times them
+  int assign;
 };
 
 // ---------------------------------------------------------------- strided passes
-enum ColsMode { COLS_FWD = 0, COLS_OP = 1, COLS_INV = 2, COLS_DIV = 3 };
+// COLS_PROJ: projection on the extended periodic lattice (EXTENDED PPE
+// domain): forward transforms of every velocity component, the pressure
+// spectrum phi = (rho/dt) sum_a S_a e_a / sum_a S_a^2, corrected spectra
+// e_a - (dt/rho) S_a phi, and inverse transforms of all of them.
+enum ColsMode { COLS_FWD = 0, COLS_OP = 1, COLS_INV = 2, COLS_DIV = 3, COLS_PROJ = 4 };
 
 struct ColsArgs {
   LinePlan plan;
@@ -224,6 +231,12 @@ struct ColsArgs {
   // whole (f, panel) tasks; each later workgroup runs one output of one of
   // the remaining tasks (gridDim.y == 1, see launch_cols)
   int nfull;
+  // COLS_PROJ (one line per workgroup): dt/rho; the modes whose symbol sum
+  // |sum_a S_a^2| (table units) is at most proj_tol get a zero pressure; the
+  // corrected spectra are scaled by proj_inv_norm and the pressure spectrum by
+  // proj_inv_norm^2 (the transforms are unnormalised, the symbol tables carry
+  // 1 / prod E)
+  double proj_dtr, proj_tol, proj_inv_norm;
 };
 
 // ---------------------------------------------------------------- PPE passes
@@ -279,6 +292,15 @@ struct PpeColsArgs {
   const double2 *dcs;  // DCT1 at length N, as for the rows
   void *data;          // cpx<T>, in place
   int B, ldsM;
+  // SPH eigenvalue family (2D, every axis periodic): mu = sum_a sigma_a^2,
+  // sigma_a = sph_norm Im S_a(inner, line) from the plan's symbol tables
+  // (line coefficients symR per inner wavenumber, phase table ph_line); modes
+  // with mu <= mu_tol get zero
+  int sph;
+  const double2 *symR;
+  int sym_ninner;
+  const double2 *ph_line;
+  double sph_norm, mu_tol;
 };
 
 // ---------------------------------------------------------------- direct tap sums
@@ -407,7 +429,9 @@ inline hipError_t issue(KS ks, KG kg, const A &a, dim3 grid, dim3 block, size_t 
 
 // LDS lines per column of the strided pass: OP and DIV keep a second line
 // (the forward spectrum / the divergence accumulator).
-inline int cols_lines_per_column(int mode) { return (mode == COLS_OP || mode == COLS_DIV) ? 2 : 1; }
+inline int cols_lines_per_column(int mode, int ndim = 2) {
+  return mode == COLS_PROJ ? ndim + 2 : (mode == COLS_OP || mode == COLS_DIV) ? 2 : 1;
+}
 
 // launchers (kernels.hip); return hipError_t
 hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s);

@@ -193,8 +193,8 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
     if (!ok) return;
     const size_t ro = (size_t)row * a.nx;
     for (int x = lt; x < a.nx; x += TL) {
-      double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)buf[x].r;
-      double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)(-buf[x].i);
+      double un = a.assign ? (double)buf[x].r : a.ustar[0][ro + x] - a.dt_over_rho * (double)buf[x].r;
+      double vn = a.assign ? (double)(-buf[x].i) : a.ustar[1][ro + x] - a.dt_over_rho * (double)(-buf[x].i);
       if (is_dirichlet_point(a.wi, x, row, 0)) {
         un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
         vn = a.wall[1] ? a.wall[1][ro + x] : 0.0;
@@ -280,9 +280,9 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
       const Line<T> b0{smem}, b1{smem + a.ldsM};
       const int y = row % a.wi.n[1], z = row / a.wi.n[1];
       for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
-        double un = a.ustar[0][ro + x] - a.dt_over_rho * (double)b0[x].r;
-        double vn = a.ustar[1][ro + x] - a.dt_over_rho * (double)(-b0[x].i);
-        double wn = a.ustar[2][ro + x] - a.dt_over_rho * (double)b1[x].r;
+        double un = a.assign ? (double)b0[x].r : a.ustar[0][ro + x] - a.dt_over_rho * (double)b0[x].r;
+        double vn = a.assign ? (double)(-b0[x].i) : a.ustar[1][ro + x] - a.dt_over_rho * (double)(-b0[x].i);
+        double wn = a.assign ? (double)b1[x].r : a.ustar[2][ro + x] - a.dt_over_rho * (double)b1[x].r;
         if (is_dirichlet_point(a.wi, x, y, z)) {
           un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
           vn = a.wall[1] ? a.wall[1][ro + x] : 0.0;
@@ -488,6 +488,73 @@ k_cols(KArg<ColsArgs, G> ka) {
       if (pass > 0)
         cols_store<T, true>(a, smem + (size_t)a.B * a.ldsM, static_cast<cpx<T> *>(a.out[f][pass - 1]), c0,
                             obase_out, a.nstore);
+    }
+  } else if constexpr (MODE == COLS_PROJ) {
+    // One column per workgroup (B == 1).  Lines 0..nin-1: the spectra e_a of
+    // the velocity components (FC along the line); line nin: the pressure
+    // spectrum; line nin + 1: the divergence D = sum_a S_a e_a.
+    const int nin = a.st.ndim;
+    const int cc = c < a.ninner ? c : 0;
+    Line<T> P{smem + (size_t)nin * a.ldsM}, D{smem + (size_t)(nin + 1) * a.ldsM};
+    for (int f = 0; f < nin; ++f) {
+      Line<T> Lf{smem + (size_t)f * a.ldsM};
+      cols_load<T>(a, smem + (size_t)f * a.ldsM, static_cast<const cpx<T> *>(a.in[f]), c0, obase_in, a.nload);
+      __syncthreads();
+      if (a.fc.on) {
+        cols_fc<T>(a, Lf, lt, TL, f, c, o);
+        __syncthreads();
+      }
+      line_dft<T>(Lf, a.plan, lt, TL, false, false);
+    }
+    // D and sum_a S_a^2 (real part of the squares: the symbols are odd, so
+    // purely imaginary up to rounding), accumulated symbol by symbol
+    for (int f = 0; f < nin; ++f) {
+      double2 R[kSymW];
+      line_coeffs(a, a.sym[f], cc, o, R);
+      const Line<T> Lf{smem + (size_t)f * a.ldsM};
+      for (int k = lt; k < E; k += TL) {
+        const double2 sv = sym_eval(R, ph_line, k);
+        const cpx<T> e = Lf[k];
+        const cpx<T> t = cmul(to_cpx<T>(sv.x, sv.y), e);
+        const T sq = T(sv.x * sv.x - sv.y * sv.y);
+        if (f == 0) {
+          D[k] = t;
+          P[k] = {sq, T(0)};
+        } else {
+          D[k] = cadd(D[k], t);
+          P[k].r += sq;
+        }
+      }
+    }
+    // phi = D / (dt/rho sum S^2) (table units), zero where the sum vanishes
+    for (int k = lt; k < E; k += TL) {
+      const T sq = P[k].r;
+      const cpx<T> d = D[k];
+      const bool ok = fabs((double)sq) > a.proj_tol;
+      const T den = T(a.proj_dtr) * (ok ? sq : T(1));
+      P[k] = ok ? cpx<T>{d.r / den, d.i / den} : cpx<T>{T(0), T(0)};
+    }
+    // corrected spectra e_a - (dt/rho) S_a phi; the inverse transforms are
+    // conj(DFT(conj(.))), the input conjugation folded in here
+    const T s1 = T(a.proj_inv_norm);
+    for (int f = 0; f < nin; ++f) {
+      double2 R[kSymW];
+      line_coeffs(a, a.sym[f], cc, o, R);
+      Line<T> Lf{smem + (size_t)f * a.ldsM};
+      for (int k = lt; k < E; k += TL) {
+        const double2 sv = sym_eval(R, ph_line, k);
+        const cpx<T> corr = cmul(to_cpx<T>(sv.x, sv.y), P[k]);
+        const cpx<T> e = Lf[k];
+        const cpx<T> v = {e.r - T(a.proj_dtr) * corr.r, e.i - T(a.proj_dtr) * corr.i};
+        Lf[k] = cconj(cscale(v, s1));
+      }
+    }
+    for (int k = lt; k < E; k += TL) P[k] = cconj(cscale(P[k], T(a.proj_inv_norm * a.proj_inv_norm)));
+    __syncthreads();
+    for (int f = 0; f <= nin; ++f) {
+      line_dft<T>(Line<T>{smem + (size_t)f * a.ldsM}, a.plan, lt, TL, false, false);
+      cols_store<T, true>(a, smem + (size_t)f * a.ldsM, static_cast<cpx<T> *>(a.out[0][f]), c0, obase_out,
+                          a.nstore);
     }
   } else {
     // COLS_DIV: out = sum_f S_f DFT(FC(in_f)), one output; passes 0..nin-1
@@ -916,15 +983,36 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
           mir = mii = a.mu_inner[c];
         }
       }
-      for (int k = lt; k < n; k += TL) {
-        const bool valid = a.kind == TRIG_DST1 ? (k >= 1 && k <= n - 2)
-                           : (a.kind == TRIG_QWS || a.kind == TRIG_QWC) ? k < n - 1 : true;
-        const double ml = valid ? a.mu_line[k] + mo : 0.0;
-        const double sr = mir + ml, si = mii + ml;
-        const cpx<T> v = buf[k];
-        const double vr = (valid && sr != 0.0) ? -(double)v.r / sr : 0.0;
-        const double vi = (valid && si != 0.0) ? -(double)v.i / si : 0.0;
-        buf[k] = to_cpx<T>(vr * a.scale, vi * a.scale);
+      if (a.sph) {
+        // SPH family: mu = sum_a sigma_a^2 at (inner, line) wavenumbers
+        double2 Rx[kSymW], Ry[kSymW];
+        const int ci = c < a.ninner ? c : 0;
+#pragma unroll
+        for (int q = 0; q < kSymW; ++q) {
+          Rx[q] = a.symR[((size_t)SYM_GX * a.sym_ninner + ci) * kSymW + q];
+          Ry[q] = a.symR[((size_t)SYM_GY * a.sym_ninner + ci) * kSymW + q];
+        }
+        for (int k = lt; k < n; k += TL) {
+          const double sx = a.sph_norm * sym_eval(Rx, a.ph_line, k).y;
+          const double sy = a.sph_norm * sym_eval(Ry, a.ph_line, k).y;
+          const double mu = sx * sx + sy * sy;
+          const cpx<T> v = buf[k];
+          const bool ok = mu > a.mu_tol;
+          const double vr = ok ? -(double)v.r / mu : 0.0;
+          const double vi = ok ? -(double)v.i / mu : 0.0;
+          buf[k] = to_cpx<T>(vr * a.scale, vi * a.scale);
+        }
+      } else {
+        for (int k = lt; k < n; k += TL) {
+          const bool valid = a.kind == TRIG_DST1 ? (k >= 1 && k <= n - 2)
+                             : (a.kind == TRIG_QWS || a.kind == TRIG_QWC) ? k < n - 1 : true;
+          const double ml = valid ? a.mu_line[k] + mo : 0.0;
+          const double sr = mir + ml, si = mii + ml;
+          const cpx<T> v = buf[k];
+          const double vr = (valid && sr != 0.0) ? -(double)v.r / sr : 0.0;
+          const double vi = (valid && si != 0.0) ? -(double)v.i / si : 0.0;
+          buf[k] = to_cpx<T>(vr * a.scale, vi * a.scale);
+        }
       }
       __syncthreads();
     }
@@ -1037,6 +1125,7 @@ static hipError_t cols_dispatch(const ColsArgs &a, dim3 grid, dim3 block, size_t
     case COLS_INV: return cols_t<T, COLS_INV>(a, grid, block, lds, s);
     case COLS_OP: return cols_t<T, COLS_OP>(a, grid, block, lds, s);
     case COLS_DIV: return cols_t<T, COLS_DIV>(a, grid, block, lds, s);
+    case COLS_PROJ: return cols_t<T, COLS_PROJ>(a, grid, block, lds, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1066,8 +1155,9 @@ static int cols_op_slots(int block, size_t lds) {
 hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s) {
   const int npanel = (a.ninner + a.B - 1) / a.B;
   const dim3 grid(npanel * a.nouter, ngrid_y), block(a.B * a.plan.TL);
-  const size_t lds = lds_bytes(a.B * cols_lines_per_column(a.mode), a.ldsM, fp32);
+  const size_t lds = lds_bytes(a.B * cols_lines_per_column(a.mode, a.st.ndim), a.ldsM, fp32);
   if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+  if (a.mode == COLS_PROJ && (a.B != 1 || !a.symR)) return hipErrorInvalidValue;
   // the symbol passes read their line coefficients from the plan's table
   if ((a.mode == COLS_OP || a.mode == COLS_DIV) && !a.symR) return hipErrorInvalidValue;
   if (a.nfull != 0) return hipErrorInvalidValue;

@@ -25,10 +25,10 @@ def lattice(s) -> Lattice:
                    h_over_dx=s["h"])
 
 
-def problem(s, precision="fp64", eig="spectral", op_eval="fft"):
+def problem(s, precision="fp64", eig="spectral", op_eval="fft", ppe_domain="physical"):
     from paper_2606_06247_amd.api import Problem
     return Problem(n=s["n"], walled=s["walled"], dx=s["dx"], vel_bc=s["vel"], prs_bc=s["prs"],
-                   h_over_dx=s["h"], precision=precision, eig=eig, op_eval=op_eval)
+                   h_over_dx=s["h"], precision=precision, eig=eig, op_eval=op_eval, ppe_domain=ppe_domain)
 
 
 def rel_l2(got, ref) -> float:

@@ -126,3 +126,31 @@ def test_lines_beyond_the_thread_bound_are_refused_cleanly():
     # a window length whose radix-5 stage needs 640 threads
     assert not _plannable(1024, window_len=(3200, 3200))
     assert _plannable(1024, window_len=(1120, 1120))
+
+
+def test_extended_domain_and_sph_family_validation():
+    """Where the EXTENDED projection and the SPH eigenvalue family are built
+    (descriptor checks are host-side, no GPU)."""
+    from paper_2606_06247_amd import api
+
+    def plannable(**kw):
+        base = dict(n=(40, 33), walled=(True, True), dx=1.0 / 39, vel_bc=(("D", "D"), ("D", "D")),
+                    prs_bc=(("N", "N"), ("N", "N")))
+        base.update(kw)
+        try:
+            api.workspace_bytes(api.Problem(**base))
+            return True
+        except api.FcsphError as e:
+            assert "unsupported" in str(e), e
+            return False
+    assert plannable(op_eval="fft", ppe_domain="extended")
+    assert not plannable(op_eval="fft_window", ppe_domain="extended")
+    assert not plannable(op_eval="direct", ppe_domain="extended")
+    assert not plannable(op_eval="fft", ppe_domain="extended", precision="fp32")
+    assert not plannable(eig="sph")                                    # walls
+    per = dict(n=(20, 16), walled=(False, False), dx=0.05, vel_bc=None, prs_bc=None)
+    assert plannable(eig="sph", **per)
+    assert plannable(eig="sph", op_eval="fft", ppe_domain="extended", **per)
+    assert not plannable(eig="sph", op_eval="direct", **per)
+    assert plannable(n=(32, 40, 24), walled=(False, True, False), dx=1.0 / 39, vel_bc=(None, ("D", "D"), None),
+                     prs_bc=(None, ("N", "N"), None), op_eval="fft", ppe_domain="extended")

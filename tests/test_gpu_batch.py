@@ -25,7 +25,9 @@ def random_walls(rng):
 
 
 def instances(seed=7):
-    """(spec, precision, op_eval, kind) for a mixed batch; repeated shapes form groups."""
+    """(spec, precision, op_eval, kind) for a mixed batch; repeated shapes form
+    groups; op_eval "fft+extended" is the whole-period route with the EXTENDED
+    projection."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(14):
@@ -40,7 +42,15 @@ def instances(seed=7):
     out.append((spec((32, 40, 24), (False, True, False)), "fp32", "fft", "step"))
     out.append((spec((96, 96), (True, True), vel=(("N", "D"), ("D", "D"))), "fp64", "fft_window", "ppe"))
     out.append((spec((96, 96), (True, True), vel=(("N", "D"), ("D", "D"))), "fp64", "fft_window", "ppe"))
+    out.append((spec((64, 64), (True, True), vel=(("D", "N"), ("D", "D"))), "fp64", "fft+extended", "step"))
+    out.append((spec((24, 33, 16), (False, True, False)), "fp64", "fft+extended", "step"))
     return out
+
+
+def make_problem(s, prec, oe):
+    if oe == "fft+extended":
+        return problem(s, precision=prec, op_eval="fft", ppe_domain="extended")
+    return problem(s, precision=prec, op_eval=oe)
 
 
 def make_inputs(s, seed):
@@ -55,7 +65,7 @@ def test_batch_matches_plain_calls_bitwise(ctx):
     import torch
     from paper_2606_06247_amd import api
     items = instances()
-    plans = [api.Plan(ctx, problem(s, precision=prec, op_eval=oe)) for s, prec, oe, _ in items]
+    plans = [api.Plan(ctx, make_problem(s, prec, oe)) for s, prec, oe, _ in items]
     dt, nu = 1e-4, 1e-3
     plain, batched, walls = [], [], []
     for i, (s, prec, oe, kind) in enumerate(items):
