@@ -25,6 +25,7 @@ class Lattice:
     h_over_dx: float = 1.3
     C: int = 25
     d: int = 5
+    kernel: str = "wendland_c2"    # or "g2", "g4", "g6", "g8", "g10" (Gaussian family)
 
     @property
     def ndim(self) -> int:

@@ -17,9 +17,15 @@ Outputs are restricted to the physical lattice (wall points included).
 symbols = DFT of the sampled, corner-wrapped taps); it exists only as the timed
 CPU baseline and is cross-checked against the direct mode in tests.
 
+Kernels: Wendland C2 (compact, ``oracle.kernels``) or the Gaussian family
+(``oracle.gaussian``: infinite support, every offset of the extended lattice
+at its minimum image).
+
 Parity: pinned by brute-force O(E^2) pair sums with explicit minimum image
 (P-OP1), the Fourier eigen-test (P-OP2), closed-form lattice sums at interior
-points (P-OP3) and antisymmetry (P-OP4) in ``tests/test_oracle_operators.py``.
+points (P-OP3) and antisymmetry (P-OP4) in ``tests/test_oracle_operators.py``;
+with the Gaussian kernels by pair sums and 4th-order convergence in
+``tests/test_oracle_gaussian.py``.
 """
 from __future__ import annotations
 
@@ -68,7 +74,13 @@ class Operators:
         self.lat = lat
         self.tables = tables
         self.mode = mode
-        tl = kernels.taps(lat.ndim, lat.dx, lat.h_over_dx)
+        if lat.kernel == "wendland_c2":
+            tl = kernels.taps(lat.ndim, lat.dx, lat.h_over_dx)
+        else:
+            # Gaussian family: every offset of the extended lattice (minimum image)
+            from . import gaussian
+            kern = gaussian.GaussianKernel(int(lat.kernel[1:]), lat.ndim, lat.h_over_dx * lat.dx)
+            tl = gaussian.taps(kern, lat.dx, lat.ext)
         self.grad_taps = [[(s, float(g[a])) for s, g, _ in tl] for a in range(lat.ndim)]
         self.lap_taps = [(s, lap) for s, _, lap in tl]
 
