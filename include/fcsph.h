@@ -49,7 +49,24 @@ typedef enum { FCSPH_FIELD_VELOCITY = 0, FCSPH_FIELD_PRESSURE = 1 } fcsph_field_
 typedef enum { FCSPH_FP64 = 0, FCSPH_FP32_MIXED = 1 } fcsph_precision;
 typedef enum { FCSPH_PPE_PHYSICAL = 0, FCSPH_PPE_EXTENDED = 1 } fcsph_ppe_domain;
 typedef enum { FCSPH_EIG_SPECTRAL = 0, FCSPH_EIG_FD2 = 1, FCSPH_EIG_SPH = 2 } fcsph_eig;
-typedef enum { FCSPH_KERNEL_WENDLAND_C2 = 0 } fcsph_kernel;
+/* SPH kernels.  Wendland C2 (compact support 2h).  The Gaussian family of
+ * the section on high-order Gaussian kernel functions and its appendix:
+ * W_2n = (1/(pi h^2)) P_n(q^2) exp(-q^2) with P_n from the moment conditions
+ * (G4 = 2 - q^2, G6 = 3 - 3q^2 + q^4/2, G8 = 4 - 6q^2 + 2q^4 - q^6/6; G10 as the
+ * conditions give it, 5 - 10q^2 + 5q^4 - 5q^6/6 + q^8/24, where the printed
+ * formula violates them); infinite support, sampled at the minimum-image
+ * displacement over the whole extended lattice (an offset of exactly half a
+ * period averages its two images).  The Gaussians are built for 2D lattices
+ * on the whole-period route (FCSPH_OPS_FFT): the windowed and direct routes
+ * rely on a compact support. */
+typedef enum {
+  FCSPH_KERNEL_WENDLAND_C2 = 0,
+  FCSPH_KERNEL_GAUSSIAN_G2 = 2,
+  FCSPH_KERNEL_GAUSSIAN_G4 = 4,
+  FCSPH_KERNEL_GAUSSIAN_G6 = 6,
+  FCSPH_KERNEL_GAUSSIAN_G8 = 8,
+  FCSPH_KERNEL_GAUSSIAN_G10 = 10
+} fcsph_kernel;
 /* How the circular convolutions of the operators (period n + C on a walled
  * axis) are evaluated; all three give the same result up to rounding:
  *  FCSPH_OPS_FFT         DFT of the whole FC-extended line (length n + C,
@@ -85,7 +102,9 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *              mirrored values, so a map must be of that symmetric form, as
  *              FC(Gram) and the paper's blended polynomial FC are); copied at
  *              plan creation
- *  kernel, h_over_dx   SPH kernel and smoothing length h / dx
+ *  kernel, h_over_dx   SPH kernel (fcsph_kernel) and smoothing length h / dx
+ *              (1.3 for Wendland C2 in the configured workloads, 8 for the
+ *              Gaussians as printed)
  *  prec        fcsph_precision
  *  ppe_domain  fcsph_ppe_domain.  FCSPH_PPE_PHYSICAL (the paper's solver): the
  *              PPE on the physical lattice by per-axis transforms (section on

@@ -29,6 +29,7 @@ FP64, FP32_MIXED = 0, 1
 PPE_PHYSICAL, PPE_EXTENDED = 0, 1
 EIG_SPECTRAL, EIG_FD2, EIG_SPH = 0, 1, 2
 KERNEL_WENDLAND_C2 = 0
+KERNELS = {"wendland_c2": 0, "g2": 2, "g4": 4, "g6": 6, "g8": 8, "g10": 10}
 OPS_FFT, OPS_DIRECT, OPS_FFT_WINDOW = 0, 1, 2
 
 EXPORTS = [
@@ -132,6 +133,7 @@ class Problem:
     vel_bc: tuple = None          # per axis ('D'|'N', 'D'|'N')
     prs_bc: tuple = None
     h_over_dx: float = 1.3
+    kernel: str = "wendland_c2"   # or the Gaussian family 'g2' .. 'g10' (2D, op_eval 'fft')
     precision: str = "fp64"       # 'fp64' | 'fp32'
     eig: str = "spectral"         # 'spectral' | 'fd2' | 'sph' (2D, every axis periodic)
     rho: float = 1.0
@@ -233,7 +235,7 @@ def make_desc(prob: "Problem"):
     d.fc_d, d.fc_C = prob.fc_d, prob.fc_C
     d.fc_M_dir = mdir.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     d.fc_M_neu = mneu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    d.kernel = KERNEL_WENDLAND_C2
+    d.kernel = KERNELS[prob.kernel]
     d.h_over_dx = prob.h_over_dx
     d.prec = FP32_MIXED if prob.precision == "fp32" else FP64
     d.ppe_domain = {"physical": PPE_PHYSICAL, "extended": PPE_EXTENDED}[prob.ppe_domain]

@@ -349,6 +349,150 @@ int pick_B(const LinePlan &p, bool fp32, int want, int nbuf = 1, int len = 0) {
   return B;
 }
 
+bool is_gaussian(int k) {
+  return k == FCSPH_KERNEL_GAUSSIAN_G2 || k == FCSPH_KERNEL_GAUSSIAN_G4 || k == FCSPH_KERNEL_GAUSSIAN_G6 ||
+         k == FCSPH_KERNEL_GAUSSIAN_G8 || k == FCSPH_KERNEL_GAUSSIAN_G10;
+}
+
+// ----------------------------------------------------------------- Gaussian symbols
+// The Gaussian of order 2n (2D): W = (1/(pi h^2)) P(s) exp(-s), s = q^2, with
+// P(s) = sum_{m<n} A_m s^m solving sum_m A_m m+j! = delta_{j0}, j < n (the
+// moment conditions with I_k = k!).  Its taps (dV times the gradient and the
+// Laplacian at the minimum-image displacement x, y) are
+//   d_x W = (2 a / h^2) x Q1(s) e^-s,   lap W = (4 a / h^2) Q3(s) e^-s,
+//   Q1 = P' - P,  Q3 = s (P'' - 2 P' + P) + Q1,  a = 1 / (pi h^2),
+// and with s = u + v (u = x^2/h^2, v = y^2/h^2), s^m = sum_i C(m,i) u^i v^(m-i):
+// every symbol (the DFT of the sampled taps over the extended lattice) is a
+// sum of products of one-dimensional DFTs of x^e u^i e^-u (e = 0, 1).  An
+// offset at exactly half a period averages its two images: the odd factors
+// vanish there, the even ones keep their value.
+std::vector<LD> gaussian_coeffs(int order) {
+  const int n = order / 2;
+  std::vector<std::vector<LD>> M(n, std::vector<LD>(n + 1, 0.0L));
+  auto fact = [](int k) {
+    LD f = 1.0L;
+    for (int i = 2; i <= k; ++i) f *= (LD)i;
+    return f;
+  };
+  for (int j = 0; j < n; ++j) {
+    for (int m = 0; m < n; ++m) M[j][m] = fact(m + j);
+    M[j][n] = j == 0 ? 1.0L : 0.0L;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabsl(M[r][c]) > fabsl(M[piv][c])) piv = r;
+    std::swap(M[c], M[piv]);
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        const LD f = M[r][c] / M[c][c];
+        for (int q = c; q <= n; ++q) M[r][q] -= f * M[c][q];
+      }
+  }
+  std::vector<LD> A(n);
+  for (int i = 0; i < n; ++i) A[i] = M[i][n] / M[i][i];
+  return A;
+}
+
+// 1D DFTs over the minimum-image offsets of a period-E axis (spacing dx,
+// smoothing length h): F[e][i][k] = sum_s g(s dx) exp(-2 pi i k s / E),
+// g(x) = x^e (x^2/h^2)^i exp(-x^2/h^2), e = 0, 1, i = 0..imax.
+void gaussian_axis_dfts(int E, LD dx, LD h, int imax, std::vector<std::vector<std::vector<std::pair<LD, LD>>>> &F) {
+  F.assign(2, std::vector<std::vector<std::pair<LD, LD>>>(imax + 1, std::vector<std::pair<LD, LD>>(E, {0.0L, 0.0L})));
+  std::vector<LD> ct(E), st(E);
+  for (int t = 0; t < E; ++t) {
+    const LD ang = -2.0L * kPi * (LD)t / (LD)E;
+    ct[t] = cosl(ang);
+    st[t] = sinl(ang);
+  }
+  for (int s = -((E - 1) / 2); s <= E / 2; ++s) {
+    const bool tie = 2 * s == E;
+    const LD x = (LD)s * dx, u = x * x / (h * h), g0 = expl(-u);
+    LD up = 1.0L;
+    for (int i = 0; i <= imax; ++i) {
+      const LD ev = up * g0, od = tie ? 0.0L : x * up * g0;
+      const int sm = ((s % E) + E) % E;
+      long long idx = 0;
+      for (int k = 0; k < E; ++k) {
+        F[0][i][k].first += ev * ct[idx];
+        F[0][i][k].second += ev * st[idx];
+        F[1][i][k].first += od * ct[idx];
+        F[1][i][k].second += od * st[idx];
+        idx += sm;
+        if (idx >= E) idx -= E;
+      }
+      up *= u;
+    }
+  }
+}
+
+// Full symbol table symF[q][kx][ky] (q = SYM_GX, SYM_GY, unused, SYM_LAP;
+// kx < Ex/2 + 1, ky < Ey), in the library's convention of weights divided by
+// Ex Ey.  Also returns max_k sum_a sigma_a(k)^2 (unnormalised).
+std::vector<double2> gaussian_symbols_2d(int order, double dx_, double hod, int Ex, int Ey, double &sig2max) {
+  const LD dx = dx_, h = (LD)hod * dx;
+  const std::vector<LD> A = gaussian_coeffs(order);
+  const int n = (int)A.size();
+  // P, P', P'' coefficients; Q1 = P' - P, Q3 = s (P'' - 2P' + P) + Q1 (degree <= n)
+  std::vector<LD> P(n + 2, 0.0L), dP(n + 2, 0.0L), ddP(n + 2, 0.0L);
+  for (int m = 0; m < n; ++m) P[m] = A[m];
+  for (int m = 1; m < n; ++m) dP[m - 1] = (LD)m * A[m];
+  for (int m = 2; m < n; ++m) ddP[m - 2] = (LD)m * (LD)(m - 1) * A[m];
+  std::vector<LD> Q1(n + 2, 0.0L), Q3(n + 2, 0.0L);
+  for (int m = 0; m <= n; ++m) Q1[m] = dP[m] - P[m];
+  for (int m = 0; m <= n; ++m) {
+    const LD q2 = ddP[m] - 2.0L * dP[m] + P[m];
+    Q3[m + 1] += q2;
+    Q3[m] += Q1[m];
+  }
+  const LD a = 1.0L / (kPi * h * h), dV = dx * dx;
+  const LD K1 = dV * 2.0L * a / (h * h), K3 = dV * 4.0L * a / (h * h);
+  std::vector<std::vector<std::vector<std::pair<LD, LD>>>> FX, FY;
+  gaussian_axis_dfts(Ex, dx, h, n + 1, FX);
+  gaussian_axis_dfts(Ey, dx, h, n + 1, FY);
+  std::vector<LD> binom((n + 2) * (n + 2), 0.0L);
+  for (int m = 0; m <= n + 1; ++m) {
+    binom[m * (n + 2)] = 1.0L;
+    for (int i = 1; i <= m; ++i) binom[m * (n + 2) + i] = binom[(m - 1) * (n + 2) + i - 1] + (i <= m - 1 ? binom[(m - 1) * (n + 2) + i] : 0.0L);
+  }
+  const int Hx = Ex / 2 + 1;
+  const LD norm = (LD)Ex * (LD)Ey;
+  std::vector<double2> out((size_t)4 * Hx * Ey, make_double2(0.0, 0.0));
+  LD s2max = 0.0L;
+  auto cm = [](std::pair<LD, LD> p, std::pair<LD, LD> q) {
+    return std::make_pair(p.first * q.first - p.second * q.second, p.first * q.second + p.second * q.first);
+  };
+  for (int kx = 0; kx < Hx; ++kx)
+    for (int ky = 0; ky < Ey; ++ky) {
+      std::pair<LD, LD> gx{0.0L, 0.0L}, gy{0.0L, 0.0L}, lp{0.0L, 0.0L};
+      for (int m = 0; m <= n; ++m)
+        for (int i = 0; i <= m; ++i) {
+          const LD b = binom[m * (n + 2) + i];
+          if (Q1[m] != 0.0L) {
+            const auto tx = cm(FX[1][i][kx], FY[0][m - i][ky]);
+            const auto ty = cm(FX[0][i][kx], FY[1][m - i][ky]);
+            gx.first += K1 * Q1[m] * b * tx.first;
+            gx.second += K1 * Q1[m] * b * tx.second;
+            gy.first += K1 * Q1[m] * b * ty.first;
+            gy.second += K1 * Q1[m] * b * ty.second;
+          }
+          if (Q3[m] != 0.0L) {
+            const auto tl = cm(FX[0][i][kx], FY[0][m - i][ky]);
+            lp.first += K3 * Q3[m] * b * tl.first;
+            lp.second += K3 * Q3[m] * b * tl.second;
+          }
+        }
+      const size_t base = (size_t)kx * Ey + ky;
+      out[(size_t)SYM_GX * Hx * Ey + base] = make_double2((double)(gx.first / norm), (double)(gx.second / norm));
+      out[(size_t)SYM_GY * Hx * Ey + base] = make_double2((double)(gy.first / norm), (double)(gy.second / norm));
+      out[(size_t)SYM_LAP * Hx * Ey + base] = make_double2((double)(lp.first / norm), (double)(lp.second / norm));
+      const LD s2 = gx.second * gx.second + gy.second * gy.second;
+      if (s2 > s2max) s2max = s2;
+    }
+  sig2max = (double)s2max;
+  return out;
+}
+
 // ----------------------------------------------------------------- kernel taps
 // Wendland C2 (q = r/h, s = 1 - q/2):  grad W = -(5 alpha/h^2) s^3 x,
 // lap W = -(5 alpha/h^2) s^2 (2 - 5q/2) in 2D, (3 - 3q) in 3D.
@@ -439,6 +583,7 @@ struct fcsph_plan {
   const double2 *dcs[3] = {nullptr, nullptr, nullptr};  // DCT-I at length N: (cos, sin)(pi j / N)
   const double2 *symR2 = nullptr;   // 2D: tabulated symbol line coefficients (y lines)
   const double2 *symR3 = nullptr;   // 3D: the same for the z lines (inner x, outer y)
+  const double2 *symF2 = nullptr;   // 2D Gaussian kernels: the full symbols [q][kx][ky]
   // symbols
   SymTables st{};
   // scratch
@@ -508,8 +653,16 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
   if (!d) { msg = "null descriptor"; return FCSPH_E_INVALID; }
   if (d->ndim != 2 && d->ndim != 3) { msg = "ndim must be 2 or 3"; return FCSPH_E_INVALID; }
   if (!(d->dx > 0.0) || !std::isfinite(d->dx)) { msg = "dx must be positive"; return FCSPH_E_INVALID; }
-  if (d->kernel != FCSPH_KERNEL_WENDLAND_C2) { msg = "unknown kernel"; return FCSPH_E_INVALID; }
-  if (!(d->h_over_dx > 0.0) || 2.0 * d->h_over_dx >= kSymR + 1) {
+  const bool gauss = is_gaussian(d->kernel);
+  if (d->kernel != FCSPH_KERNEL_WENDLAND_C2 && !gauss) { msg = "unknown kernel"; return FCSPH_E_INVALID; }
+  if (gauss) {
+    if (!(d->h_over_dx > 0.0) || !std::isfinite(d->h_over_dx)) { msg = "h_over_dx must be positive"; return FCSPH_E_INVALID; }
+    if (d->ndim != 2 || d->op_eval != FCSPH_OPS_FFT || d->eig == FCSPH_EIG_SPH) {
+      msg = "the Gaussian kernels (unbounded support) are built for 2D lattices on the whole-period route "
+            "(op_eval FCSPH_OPS_FFT) with the SPECTRAL or FD2 PPE";
+      return FCSPH_E_UNSUPPORTED;
+    }
+  } else if (!(d->h_over_dx > 0.0) || 2.0 * d->h_over_dx >= kSymR + 1) {
     msg = "h_over_dx must be in (0, " + std::to_string((kSymR + 1) / 2.0) + ")";
     return FCSPH_E_UNSUPPORTED;
   }
@@ -551,7 +704,10 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
       }
     }
     const int E = d->n[a] + (d->axis[a] == FCSPH_AXIS_WALLED ? d->fc_C : 0);
-    if (2.0 * 2.0 * d->h_over_dx >= (double)E) { msg = "kernel support exceeds half the extended period"; return FCSPH_E_INVALID; }
+    if (!gauss && 2.0 * 2.0 * d->h_over_dx >= (double)E) {
+      msg = "kernel support exceeds half the extended period";
+      return FCSPH_E_INVALID;
+    }
   }
   if (any_wall) {
     if (d->fc_d < 1 || d->fc_C < 2 || d->fc_d > 16 || d->fc_C > 4096) { msg = "bad FC sizes"; return FCSPH_E_INVALID; }
@@ -696,6 +852,16 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       u.dst = ws.take(u.data.size());
       p->symR2 = (const double2 *)u.dst;
       up.push_back(std::move(u));
+      if (is_gaussian(d->kernel)) {
+        double s2 = 0.0;
+        std::vector<double2> tab = gaussian_symbols_2d(d->kernel, d->dx, d->h_over_dx, p->E[0], p->E[1], s2);
+        Upload g;
+        g.data.assign((const char *)tab.data(), (const char *)(tab.data() + tab.size()));
+        g.dst = ws.take(g.data.size());
+        p->symF2 = (const double2 *)g.dst;
+        up.push_back(std::move(g));
+        p->sigma2_bound = s2;
+      }
     }
     if (p->nd == 3) {
       // z lines: R[sl] = sum_{sy, sx} W[sl][sy][sx] exp(-2 pi i (k sx / E_x + o sy / E_y))
@@ -941,6 +1107,7 @@ ColsArgs cols_base(fcsph_plan *p, int mode, int fc) {
   c.inner_axis = 0;
   c.outer_axis = -1;
   c.symR = p->symR2;
+  c.symF = p->symF2;
   c.B = pick_B(c.plan, p->fp32, p->want_B, cols_lines_per_column(mode));
   c.ldsM = padded_len(c.plan.M, c.plan.pad);
   return c;

@@ -227,6 +227,9 @@ struct ColsArgs {
   // inner and outer wavenumber, symR[((q * ninner + k) * nouter + o) * kSymW
   // + sl + R], tabulated at plan creation (2D: one outer index)
   const double2 *symR;
+  // kernels of unbounded support (Gaussian family): the symbols themselves,
+  // symF[((q * ninner + c) * nouter + o) * plan.n + k]; when set, symR is not used
+  const double2 *symF;
   // COLS_OP, one problem per launch: 0, or the number of workgroups that run
   // whole (f, panel) tasks; each later workgroup runs one output of one of
   // the remaining tasks (gridDim.y == 1, see launch_cols)

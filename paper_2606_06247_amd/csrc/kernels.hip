@@ -331,6 +331,19 @@ __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_
 }
 
 
+// Symbol q at inner wavenumber c, outer index o and line wavenumber k: from
+// the plan's full table (kernels of unbounded support) or from the line
+// coefficients R of the compact kernel.
+__device__ __forceinline__ double2 sym_value(const ColsArgs &a, int q, int c, int o, const double2 *R,
+                                             const double2 *ph_line, int k) {
+  if (a.symF) return a.symF[(((size_t)q * a.ninner + c) * a.nouter + (o < 0 ? 0 : o)) * a.plan.n + k];
+  return sym_eval(R, ph_line, k);
+}
+
+__device__ __forceinline__ void line_coeffs_if(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
+  if (!a.symF) line_coeffs(a, q, kin, kout, R);
+}
+
 // CONJ loads the complex conjugate (the input conjugation of an inverse
 // transform computed as conj(DFT(conj(x))), folded into the load).
 template <typename T, bool CONJ = false>
@@ -474,12 +487,13 @@ k_cols(KArg<ColsArgs, G> ka) {
         }
       } else {
         double2 R[kSymW];
-        line_coeffs(a, a.sym[pass - 1], c < a.ninner ? c : 0, o, R);
+        const int cq = c < a.ninner ? c : 0;
+        line_coeffs_if(a, a.sym[pass - 1], cq, o, R);
         __syncthreads();   // the previous output's store has finished reading xb
         // the inverse DFT is conj(DFT(conj(.))): the input conjugation is
         // folded into the symbol product, the output one into the store
         for (int k = lt; k < E; k += TL) {
-          const double2 sv = sym_eval(R, ph_line, k);
+          const double2 sv = sym_value(a, a.sym[pass - 1], cq, o, R, ph_line, k);
           xb[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
         }
         __syncthreads();
@@ -510,10 +524,10 @@ k_cols(KArg<ColsArgs, G> ka) {
     // purely imaginary up to rounding), accumulated symbol by symbol
     for (int f = 0; f < nin; ++f) {
       double2 R[kSymW];
-      line_coeffs(a, a.sym[f], cc, o, R);
+      line_coeffs_if(a, a.sym[f], cc, o, R);
       const Line<T> Lf{smem + (size_t)f * a.ldsM};
       for (int k = lt; k < E; k += TL) {
-        const double2 sv = sym_eval(R, ph_line, k);
+        const double2 sv = sym_value(a, a.sym[f], cc, o, R, ph_line, k);
         const cpx<T> e = Lf[k];
         const cpx<T> t = cmul(to_cpx<T>(sv.x, sv.y), e);
         const T sq = T(sv.x * sv.x - sv.y * sv.y);
@@ -539,10 +553,10 @@ k_cols(KArg<ColsArgs, G> ka) {
     const T s1 = T(a.proj_inv_norm);
     for (int f = 0; f < nin; ++f) {
       double2 R[kSymW];
-      line_coeffs(a, a.sym[f], cc, o, R);
+      line_coeffs_if(a, a.sym[f], cc, o, R);
       Line<T> Lf{smem + (size_t)f * a.ldsM};
       for (int k = lt; k < E; k += TL) {
-        const double2 sv = sym_eval(R, ph_line, k);
+        const double2 sv = sym_value(a, a.sym[f], cc, o, R, ph_line, k);
         const cpx<T> corr = cmul(to_cpx<T>(sv.x, sv.y), P[k]);
         const cpx<T> e = Lf[k];
         const cpx<T> v = {e.r - T(a.proj_dtr) * corr.r, e.i - T(a.proj_dtr) * corr.i};
@@ -580,9 +594,10 @@ k_cols(KArg<ColsArgs, G> ka) {
       line_dft<T>(buf, a.plan, lt, TL, false, false);
       if (pass < nin) {
         double2 R[kSymW];
-        line_coeffs(a, a.sym[pass], c < a.ninner ? c : 0, o, R);
+        const int cq = c < a.ninner ? c : 0;
+        line_coeffs_if(a, a.sym[pass], cq, o, R);
         for (int k = lt; k < E; k += TL) {
-          const double2 sv = sym_eval(R, ph_line, k);
+          const double2 sv = sym_value(a, a.sym[pass], cq, o, R, ph_line, k);
           acc[k] = cadd(acc[k], cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
         }
       }
@@ -1157,9 +1172,9 @@ hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s)
   const dim3 grid(npanel * a.nouter, ngrid_y), block(a.B * a.plan.TL);
   const size_t lds = lds_bytes(a.B * cols_lines_per_column(a.mode, a.st.ndim), a.ldsM, fp32);
   if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
-  if (a.mode == COLS_PROJ && (a.B != 1 || !a.symR)) return hipErrorInvalidValue;
+  if (a.mode == COLS_PROJ && (a.B != 1 || (!a.symR && !a.symF))) return hipErrorInvalidValue;
   // the symbol passes read their line coefficients from the plan's table
-  if ((a.mode == COLS_OP || a.mode == COLS_DIV) && !a.symR) return hipErrorInvalidValue;
+  if ((a.mode == COLS_OP || a.mode == COLS_DIV) && !a.symR && !a.symF) return hipErrorInvalidValue;
   if (a.nfull != 0) return hipErrorInvalidValue;
   // the inverse pass conjugates on load: it must load every line position
   if (a.mode == COLS_INV && a.nload != a.plan.n) return hipErrorInvalidValue;

@@ -7,7 +7,7 @@ import numpy as np
 from oracle.lattice import Lattice
 
 
-def spec(n, walled, vel=None, prs=None, dx=None, h=1.3):
+def spec(n, walled, vel=None, prs=None, dx=None, h=1.3, kernel="wendland_c2"):
     """n, walled in lattice order; vel / prs per axis ('D'|'N', 'D'|'N') or None."""
     nd = len(n)
     vel = tuple(vel) if vel else tuple(("D", "D") if w else None for w in walled)
@@ -17,18 +17,19 @@ def spec(n, walled, vel=None, prs=None, dx=None, h=1.3):
     if dx is None:
         wn = [k for k, w in zip(n, walled) if w]
         dx = 1.0 / (wn[0] - 1) if wn else 1.0 / n[0]
-    return dict(n=tuple(n), walled=tuple(walled), vel=tuple(vel), prs=tuple(prs), dx=dx, h=h, nd=nd)
+    return dict(n=tuple(n), walled=tuple(walled), vel=tuple(vel), prs=tuple(prs), dx=dx, h=h, nd=nd, kernel=kernel)
 
 
 def lattice(s) -> Lattice:
     return Lattice(n=s["n"], walled=s["walled"], dx=s["dx"], vel_bc=s["vel"], prs_bc=s["prs"],
-                   h_over_dx=s["h"])
+                   h_over_dx=s["h"], kernel=s.get("kernel", "wendland_c2"))
 
 
 def problem(s, precision="fp64", eig="spectral", op_eval="fft", ppe_domain="physical"):
     from paper_2606_06247_amd.api import Problem
     return Problem(n=s["n"], walled=s["walled"], dx=s["dx"], vel_bc=s["vel"], prs_bc=s["prs"],
-                   h_over_dx=s["h"], precision=precision, eig=eig, op_eval=op_eval, ppe_domain=ppe_domain)
+                   h_over_dx=s["h"], precision=precision, eig=eig, op_eval=op_eval, ppe_domain=ppe_domain,
+                   kernel=s.get("kernel", "wendland_c2"))
 
 
 def rel_l2(got, ref) -> float:

@@ -154,3 +154,27 @@ def test_extended_domain_and_sph_family_validation():
     assert not plannable(eig="sph", op_eval="direct", **per)
     assert plannable(n=(32, 40, 24), walled=(False, True, False), dx=1.0 / 39, vel_bc=(None, ("D", "D"), None),
                      prs_bc=(None, ("N", "N"), None), op_eval="fft", ppe_domain="extended")
+
+
+def test_gaussian_kernel_validation():
+    """The Gaussian kernels (unbounded support) plan on 2D lattices on the
+    whole-period route only (host-side descriptor checks, no GPU)."""
+    from paper_2606_06247_amd import api
+
+    def plannable(**kw):
+        base = dict(n=(40, 33), walled=(True, True), dx=1.0 / 39, vel_bc=(("D", "D"), ("D", "D")),
+                    prs_bc=(("N", "N"), ("N", "N")), h_over_dx=8.0, kernel="g4", op_eval="fft")
+        base.update(kw)
+        try:
+            api.workspace_bytes(api.Problem(**base))
+            return True
+        except api.FcsphError as e:
+            assert "unsupported" in str(e), e
+            return False
+    for k in ("g2", "g4", "g6", "g8", "g10"):
+        assert plannable(kernel=k)
+    assert not plannable(op_eval="fft_window")
+    assert not plannable(op_eval="direct")
+    assert not plannable(n=(32, 40, 24), walled=(False, True, False), vel_bc=(None, ("D", "D"), None),
+                         prs_bc=(None, ("N", "N"), None))
+    assert plannable(op_eval="fft", ppe_domain="extended")
