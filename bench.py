@@ -65,7 +65,9 @@ def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0, rk3: bool = Fal
     out = {
         "rows_fwd_pair": 2 * R + 2 * S,
         "cols_op_step_a": 2 * S + 6 * S,
-        "rows_inv_step_a": 6 * S + 4 * R + 2 * R,
+        # FP64: the epilogue also writes the x spectra of (u*, v*) (the fused
+        # first pass of the divergence; the separate rows forward goes away)
+        "rows_inv_step_a": 6 * S + 4 * R + 2 * R + (0 if fp32 else 2 * S),
         "cols_div": 2 * S + S,
         "rows_inv_store": S + Rt,
         "ppe_rows_fwd": Rt + P * ce // 2,

@@ -1830,8 +1830,10 @@ static fcsph_status div3_impl(fcsph_plan *p, const double *const *u, void *out, 
   return FCSPH_OK;
 }
 
+// spectra_ready: the x forward pass of (u0, u1) into S[0], S[1] was done by
+// the pass that produced them (the fused u* epilogue of a step)
 static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, void *out, bool out_double,
-                             double scale) {
+                             double scale, bool spectra_ready = false) {
   fcsph_status st = FCSPH_OK;
   if (p->direct) {
     DirectArgs a = direct_base(p, FCSPH_FIELD_VELOCITY);
@@ -1843,7 +1845,8 @@ static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, 
     if (!chk(p, direct_launch(p, a, DIR_DIV, "direct_div"), "div", st)) return st;
     return FCSPH_OK;
   }
-  if (!chk(p, x_fwd_pair(p, u0, u1, FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
+  if (!spectra_ready)
+    if (!chk(p, x_fwd_pair(p, u0, u1, FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "div x", st)) return st;
   ColsArgs c = cols_base(p, COLS_DIV, FCSPH_FIELD_VELOCITY);
   {
     const double *uu[2] = {u0, u1};
@@ -1882,7 +1885,7 @@ fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi) {
 // u_a <- restriction of IDFT(e_a - (dt/rho) S_a phi_hat), Dirichlet walls
 // reset; p_out <- restriction of IDFT(phi_hat).
 static fcsph_status project_extended(fcsph_plan *p, double *const *u, double *p_out,
-                                     const double *const *wall_vel, double dt_proj) {
+                                     const double *const *wall_vel, double dt_proj, bool spectra_ready = false) {
   fcsph_status st = FCSPH_OK;
   hipStream_t s = p->ctx->stream;
   double *phi = p_out ? p_out : p->phi;
@@ -1913,7 +1916,8 @@ static fcsph_status project_extended(fcsph_plan *p, double *const *u, double *p_
   r.assign = 1;
   r.wi = wall_info(p);
   if (p->nd == 2) {
-    if (!chk(p, x_fwd_pair(p, p->ustar[0], p->ustar[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "proj x", st))
+    if (!spectra_ready &&
+        !chk(p, x_fwd_pair(p, p->ustar[0], p->ustar[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "proj x", st))
       return st;
     c.in[0] = p->S[0];
     c.in[1] = p->S[1];
@@ -2132,15 +2136,24 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
   r.wi = wall_info(p);
   if (3ull * r.ldsM * (f32 ? 8 : 16) > (size_t)kMaxLds)
     return fail(p->ctx, FCSPH_E_UNSUPPORTED, "x line too long for the fused step kernel");
+  // FP64 plans: the epilogue also runs the x forward pass of (u*, v*) that
+  // the divergence (or the EXTENDED projection) starts with
+  const bool fused = !f32;
+  if (fused) {
+    r.fwd_fused = 1;
+    r.fwd_fc = walls_for(p, 0, FCSPH_FIELD_VELOCITY);
+    r.fwd_out[0] = p->S[0];
+    r.fwd_out[1] = p->S[1];
+  }
   {
     LaunchTimer t(p->ctx, "rows_inv_step_a");
     if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;
   }
-  if (p->d.ppe_domain == FCSPH_PPE_EXTENDED) return project_extended(p, u, p_out, wall_vel, dt_proj);
+  if (p->d.ppe_domain == FCSPH_PPE_EXTENDED) return project_extended(p, u, p_out, wall_vel, dt_proj, fused);
   // B: b = (rho/dt) div u*, FP64 transforms in both forms
   {
     Fp64Passes g64(p);
-    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt_proj);
+    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt_proj, fused);
   }
   if (st != FCSPH_OK) return st;
   // C: PPE

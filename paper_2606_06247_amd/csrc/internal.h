@@ -187,6 +187,14 @@ struct RowsInvArgs {
   // EPI_STEP_D2 / D3: 1 = the transformed values are the new velocity
   // (EXTENDED projection, no u* read), 0 = u* - (dt/rho) times them
   int assign;
+  // EPI_STEP_A2 (T = double): 1 = the row's u* and v* also go through the x
+  // forward pass of the divergence that follows (FC along x with fwd_fc, the
+  // packed real-to-complex DFT of the same plan) into the half-spectrum rows
+  // fwd_out[0], fwd_out[1] (row pitch H), as a separate rows-forward launch
+  // would write them
+  int fwd_fused;
+  FcWalls fwd_fc;
+  void *fwd_out[2];
 };
 
 // ---------------------------------------------------------------- strided passes

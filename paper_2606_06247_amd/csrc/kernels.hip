@@ -249,6 +249,36 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
         }
         a.ustar[0][ro + x] = us;
         a.ustar[1][ro + x] = vs;
+        if constexpr (sizeof(T) == 8) {
+          // position x of line 0 was read above by this thread only
+          if (a.fwd_fused) b0[x] = to_cpx<T>(us, vs);
+        }
+      }
+      if constexpr (sizeof(T) == 8) {
+        if (a.fwd_fused) {
+          // the x forward pass of (u*, v*): FC along x, packed DFT, half spectra
+          __syncthreads();
+          for (int j = a.nx + threadIdx.x; j < a.E; j += blockDim.x) {
+            const int i = fc_slot(a.fwd_fc, a.nx, a.E, j);
+            double ra = 0.0, rb = 0.0;
+            if (a.fwd_fc.on && i >= 0) {
+              ra = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)b0[q].r; });
+              rb = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)b0[q].i; });
+            }
+            b0[j] = to_cpx<T>(ra, rb);
+          }
+          __syncthreads();
+          line_dft<T>(b0, a.plan, lt, TL, false, false, g == 0);
+          cpx<T> *oa = static_cast<cpx<T> *>(a.fwd_out[0]) + (size_t)row * a.H;
+          cpx<T> *ob = static_cast<cpx<T> *>(a.fwd_out[1]) + (size_t)row * a.H;
+          const T half = T(0.5);
+          for (int k = threadIdx.x; k < a.H; k += blockDim.x) {
+            const cpx<T> z = b0[k];
+            const cpx<T> zc = cconj(b0[k == 0 ? 0 : a.E - k]);
+            oa[k] = cscale(cadd(z, zc), half);
+            ob[k] = cscale(cmi(csub(z, zc)), half);
+          }
+        }
       }
     } else if constexpr (EPI == EPI_STEP_A3) {
       Line<T> b[6];
@@ -297,10 +327,6 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
 }
 
 // ============================================================= strided passes
-__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 // Coefficients R[s] (s = -kSymR..kSymR along the line axis) of the symbol of
 // operator q at fixed wavenumbers of the transverse axes,
 //   S(k) = sum_s R[s] exp(-2 pi i k_line s / E_line),
@@ -314,11 +340,12 @@ __device__ __forceinline__ void line_coeffs(const ColsArgs &a, int q, int kin, i
 }
 
 __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
-  // exp(-2 pi i k s / E) for s = 1 from the table, s = 2, 3 by products
+  // exp(-2 pi i k s / E), s = 1..3, from the plan's phase table (each entry
+  // rounded once from extended precision; loads instead of products)
   double2 p[kSymR + 1];
-  p[1] = ph_line[(size_t)k * (kSymR + 1) + 1];
+  const double2 *row = ph_line + (size_t)k * (kSymR + 1);
 #pragma unroll
-  for (int s = 2; s <= kSymR; ++s) p[s] = zmul(p[s - 1], p[1]);
+  for (int s = 1; s <= kSymR; ++s) p[s] = row[s];
   double2 acc = R[kSymR];
 #pragma unroll
   for (int s = 1; s <= kSymR; ++s) {
@@ -334,14 +361,18 @@ __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_
 // Symbol q at inner wavenumber c, outer index o and line wavenumber k: from
 // the plan's full table (kernels of unbounded support) or from the line
 // coefficients R of the compact kernel.
+// SF: the kernel instantiation that reads full symbol tables (kept separate,
+// so the compact-kernel instantiations carry no extra registers for it).
+template <bool SF>
 __device__ __forceinline__ double2 sym_value(const ColsArgs &a, int q, int c, int o, const double2 *R,
                                              const double2 *ph_line, int k) {
-  if (a.symF) return a.symF[(((size_t)q * a.ninner + c) * a.nouter + (o < 0 ? 0 : o)) * a.plan.n + k];
-  return sym_eval(R, ph_line, k);
+  if constexpr (SF) return a.symF[(((size_t)q * a.ninner + c) * a.nouter + (o < 0 ? 0 : o)) * a.plan.n + k];
+  else return sym_eval(R, ph_line, k);
 }
 
+template <bool SF>
 __device__ __forceinline__ void line_coeffs_if(const ColsArgs &a, int q, int kin, int kout, double2 *R) {
-  if (!a.symF) line_coeffs(a, q, kin, kout, R);
+  if constexpr (!SF) line_coeffs(a, q, kin, kout, R);
 }
 
 // CONJ loads the complex conjugate (the input conjugation of an inverse
@@ -418,7 +449,7 @@ __device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, 
 // the plan's table the column kernels need 105-137; capped, only the FP64
 // operator form spills (12 B per lane), and the 1024^2 step gains 1 %, the
 // 256^3 step 2.5 % (four 4-wave workgroups per CU, as the LDS allows).
-template <typename T, int MODE, bool G>
+template <typename T, int MODE, bool G, bool SF = false>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_cols(KArg<ColsArgs, G> ka) {
   const ColsArgs &a = ka.get();
@@ -488,12 +519,12 @@ k_cols(KArg<ColsArgs, G> ka) {
       } else {
         double2 R[kSymW];
         const int cq = c < a.ninner ? c : 0;
-        line_coeffs_if(a, a.sym[pass - 1], cq, o, R);
+        line_coeffs_if<SF>(a, a.sym[pass - 1], cq, o, R);
         __syncthreads();   // the previous output's store has finished reading xb
         // the inverse DFT is conj(DFT(conj(.))): the input conjugation is
         // folded into the symbol product, the output one into the store
         for (int k = lt; k < E; k += TL) {
-          const double2 sv = sym_value(a, a.sym[pass - 1], cq, o, R, ph_line, k);
+          const double2 sv = sym_value<SF>(a, a.sym[pass - 1], cq, o, R, ph_line, k);
           xb[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
         }
         __syncthreads();
@@ -524,10 +555,10 @@ k_cols(KArg<ColsArgs, G> ka) {
     // purely imaginary up to rounding), accumulated symbol by symbol
     for (int f = 0; f < nin; ++f) {
       double2 R[kSymW];
-      line_coeffs_if(a, a.sym[f], cc, o, R);
+      line_coeffs_if<SF>(a, a.sym[f], cc, o, R);
       const Line<T> Lf{smem + (size_t)f * a.ldsM};
       for (int k = lt; k < E; k += TL) {
-        const double2 sv = sym_value(a, a.sym[f], cc, o, R, ph_line, k);
+        const double2 sv = sym_value<SF>(a, a.sym[f], cc, o, R, ph_line, k);
         const cpx<T> e = Lf[k];
         const cpx<T> t = cmul(to_cpx<T>(sv.x, sv.y), e);
         const T sq = T(sv.x * sv.x - sv.y * sv.y);
@@ -553,10 +584,10 @@ k_cols(KArg<ColsArgs, G> ka) {
     const T s1 = T(a.proj_inv_norm);
     for (int f = 0; f < nin; ++f) {
       double2 R[kSymW];
-      line_coeffs_if(a, a.sym[f], cc, o, R);
+      line_coeffs_if<SF>(a, a.sym[f], cc, o, R);
       Line<T> Lf{smem + (size_t)f * a.ldsM};
       for (int k = lt; k < E; k += TL) {
-        const double2 sv = sym_value(a, a.sym[f], cc, o, R, ph_line, k);
+        const double2 sv = sym_value<SF>(a, a.sym[f], cc, o, R, ph_line, k);
         const cpx<T> corr = cmul(to_cpx<T>(sv.x, sv.y), P[k]);
         const cpx<T> e = Lf[k];
         const cpx<T> v = {e.r - T(a.proj_dtr) * corr.r, e.i - T(a.proj_dtr) * corr.i};
@@ -595,9 +626,9 @@ k_cols(KArg<ColsArgs, G> ka) {
       if (pass < nin) {
         double2 R[kSymW];
         const int cq = c < a.ninner ? c : 0;
-        line_coeffs_if(a, a.sym[pass], cq, o, R);
+        line_coeffs_if<SF>(a, a.sym[pass], cq, o, R);
         for (int k = lt; k < E; k += TL) {
-          const double2 sv = sym_value(a, a.sym[pass], cq, o, R, ph_line, k);
+          const double2 sv = sym_value<SF>(a, a.sym[pass], cq, o, R, ph_line, k);
           acc[k] = cadd(acc[k], cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
         }
       }
@@ -1130,6 +1161,10 @@ hipError_t launch_rows_inv(const RowsInvArgs &a, int epi, bool fp32, hipStream_t
 
 template <typename T, int MODE>
 static hipError_t cols_t(const ColsArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  constexpr bool SYM = MODE == COLS_OP || MODE == COLS_DIV || MODE == COLS_PROJ;
+  if constexpr (SYM) {
+    if (a.symF) return issue(k_cols<T, MODE, false, true>, k_cols<T, MODE, true, true>, a, grid, block, lds, s);
+  }
   return issue(k_cols<T, MODE, false>, k_cols<T, MODE, true>, a, grid, block, lds, s);
 }
 
@@ -1184,7 +1219,7 @@ hipError_t launch_cols(const ColsArgs &a, int ngrid_y, bool fp32, hipStream_t s)
   // inverse transforms).  Their outputs go to separate workgroups instead
   // (forward + one inverse each), which fill one round after the first.
   // The 1024^2 stage-A pass has 1122 tasks for 1024 resident workgroups.
-  if (a.mode == COLS_OP && a.nout > 1 && !active_recorder()) {
+  if (a.mode == COLS_OP && a.nout > 1 && !active_recorder() && !a.symF) {
     const long tasks = (long)grid.x * ngrid_y;
     const int slots = fp32 ? cols_op_slots<float>(block.x, lds) : cols_op_slots<double>(block.x, lds);
     const long rest = tasks - slots;
