@@ -726,8 +726,8 @@ def main() -> int:
                             "25% 3D channel n ~ logU(64, 192), sizes in multiples of 16; HBM budget 200 GB; "
                             f"at most {args.serve_requests} requests or {args.serve_window} s of arrivals per rate; "
                             "4 lanes, batches of one class: up to 16 2D or 2 3D requests",
-                "rates": run_serving(prec, (50, 100, 200, 500, 1000, 2000), args.serve_requests, args.serve_window,
-                                     plain_lams=(50, 500, 2000))}
+                "rates": run_serving(prec, (50, 100, 200, 500, 1000, 2000, 5000, 10000), args.serve_requests,
+                                     args.serve_window, plain_lams=(50, 500, 2000, 5000, 10000))}
         full["variants"] = var
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -269,6 +269,16 @@ fcsph_status fcsph_spectral_lap_noalloc(fcsph_plan *p, int fc, const double *f, 
 fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi);
 
 /*
+ * Finiteness check of a device FP64 array of n values (a served request's
+ * output, a state before the next step): counts the NaN and infinite values
+ * on the device (a counter in the plan's workspace, cleared by a kernel), then
+ * waits for the plan's context stream.  *count (host) receives the count;
+ * returns FCSPH_E_NONFINITE when it is nonzero, FCSPH_OK otherwise.  The
+ * paper states no such check; it is the error path of the served form.
+ */
+fcsph_status fcsph_check_finite(fcsph_plan *p, const double *x, size_t n, unsigned long long *count);
+
+/*
  * One first-order projection step (eqs. uStarRK3 and rhsMomtem with
  * a = g = 1, z = 0; eqs. PPE and u^n+1):
  *   u*  = u - dt [ (u . grad) u - nu lap u - force ],  Dirichlet walls <- wall_vel

@@ -37,7 +37,7 @@ EXPORTS = [
     "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
     "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
     "fcsph_spectral_div",
-    "fcsph_spectral_lap", "fcsph_spectral_lap_noalloc", "fcsph_ppe_solve", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
+    "fcsph_spectral_lap", "fcsph_spectral_lap_noalloc", "fcsph_ppe_solve", "fcsph_check_finite", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
     "fcsph_ctx_read_timing", "fcsph_ctx_set_timing_only", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
     "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_rk3_substep", "fcsph_batch_add_ppe", "fcsph_batch_launch",
     "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_spectral_lap.argtypes = [vp, i, vp, vp]
     L.fcsph_spectral_lap_noalloc.argtypes = [vp, i, vp, vp]
     L.fcsph_ppe_solve.argtypes = [vp, vp, vp]
+    L.fcsph_check_finite.argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_ulonglong)]
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
     L.fcsph_rk3_substep.argtypes = [vp, i, P(vp), vp, P(vp), P(vp), P(vp), d, d]
     L.fcsph_ctx_set_timing.argtypes = [vp, i]
@@ -356,6 +357,16 @@ class Plan:
         _check(lib().fcsph_spectral_lap_noalloc(self.handle, field, self._phys(f), self._phys(out, self.out_dtype)),
                self.ctx.handle, "fcsph_spectral_lap_noalloc")
         return out
+
+    def nonfinite_count(self, x) -> int:
+        """fcsph_check_finite: the number of NaN / infinite values of an FP64
+        device tensor (counted by the library's kernel; waits for the stream)."""
+        t = self._t(x)
+        cnt = ctypes.c_ulonglong(0)
+        st = lib().fcsph_check_finite(self.handle, ctypes.c_void_p(t.data_ptr()), t.numel(), ctypes.byref(cnt))
+        if st not in (OK, E_NONFINITE):
+            _check(st, self.ctx.handle, "fcsph_check_finite")
+        return int(cnt.value)
 
     def ppe_solve(self, rhs, out=None):
         out = self._new() if out is None else out

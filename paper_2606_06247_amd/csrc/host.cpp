@@ -607,6 +607,7 @@ struct fcsph_plan {
   // of the squared l1 norm of the gradient taps), for the zero-mode tolerance
   // of the SPH family and the EXTENDED projection
   double sigma2_bound = 0.0;
+  unsigned long long *counter = nullptr;   // device counter of fcsph_check_finite
   size_t ws_bytes = 0;
 };
 
@@ -998,6 +999,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   for (int a = 0; a < p->nd; ++a) p->ustar[a] = (double *)ws.take(P * sizeof(double));
   p->rhs = ws.take(P * te);
   p->phi = (double *)ws.take(P * sizeof(double));
+  p->counter = (unsigned long long *)ws.take(256);
   p->cpitch = p->trig_kind[0] == TRIG_DFT ? p->ncoef[0] : (std::max(p->ncoef[0], 1) + 1) / 2;
   p->coef = ws.take((size_t)p->cpitch * rows * sizeof(cpx<double>));   // PPE coefficients: FP64
   p->ext_scratch = (double *)ws.take((size_t)p->Efc[0] * p->Efc[1] * p->Efc[2] * sizeof(double));
@@ -1870,6 +1872,20 @@ fcsph_status fcsph_spectral_div(fcsph_plan *p, const double *const *u, void *div
     if (!u[a]) return fail(p->ctx, FCSPH_E_INVALID, "null input");
   if (p->nd == 3) return div3_impl(p, u, div, !p->fp32, 1.0);
   return div_impl(p, u[0], u[1], div, !p->fp32, 1.0);
+}
+
+fcsph_status fcsph_check_finite(fcsph_plan *p, const double *x, size_t n, unsigned long long *count) {
+  if (!p) return FCSPH_E_INVALID;
+  if ((!x && n) || !count) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  fcsph_status st = FCSPH_OK;
+  if (!chk(p, launch_count_nonfinite(x, n, p->counter, p->ctx->stream), "finiteness count", st)) return st;
+  unsigned long long c = 0;
+  if (!chk(p, hipMemcpyAsync(&c, p->counter, sizeof(c), hipMemcpyDeviceToHost, p->ctx->stream), "copy count", st))
+    return st;
+  if (!chk(p, hipStreamSynchronize(p->ctx->stream), "finiteness sync", st)) return st;
+  *count = c;
+  if (c) return fail(p->ctx, FCSPH_E_NONFINITE, std::to_string(c) + " non-finite values");
+  return FCSPH_OK;
 }
 
 fcsph_status fcsph_ppe_solve(fcsph_plan *p, const void *rhs, double *phi) {

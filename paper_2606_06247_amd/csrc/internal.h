@@ -450,6 +450,7 @@ hipError_t launch_rows_inv(const RowsInvArgs &a, int epi, bool fp32, hipStream_t
 hipError_t launch_cols(const ColsArgs &a, int ninputs_grid, bool fp32, hipStream_t s);
 hipError_t launch_ppe_rows(const PpeRowsArgs &a, bool fp32, hipStream_t s);
 hipError_t launch_ppe_cols(const PpeColsArgs &a, bool fp32, hipStream_t s);
+hipError_t launch_count_nonfinite(const double *x, size_t n, unsigned long long *counter, hipStream_t s);
 hipError_t launch_fc_extend_axis(const double *in, double *out, int ndim, const int *shape_in,
                                  int axis, const FcWalls &fc, hipStream_t s);
 

@@ -1097,6 +1097,33 @@ __global__ void k_fc_extend(const double *in, double *out, long outer, int len, 
   }
 }
 
+// ============================================================= finiteness check
+// counter[0] <- 0 (a kernel, not a memset: safe under graph capture), then
+// counter[0] += the number of NaN / infinite values of x[0..n).
+__global__ void k_zero_counter(unsigned long long *counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counter[0] = 0ull;
+}
+
+__global__ void __launch_bounds__(256) k_count_nonfinite(const double *x, size_t n, unsigned long long *counter) {
+  unsigned int c = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    c += isfinite(x[i]) ? 0u : 1u;
+  // wave reduction, one atomic per wave
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_down(c, d, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(counter, (unsigned long long)c);
+}
+
+hipError_t launch_count_nonfinite(const double *x, size_t n, unsigned long long *counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  size_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)nb), dim3(256), 0, s, x, n, counter);
+  return hipGetLastError();
+}
+
 // ============================================================= launchers
 Recorder *&active_recorder() {
   static thread_local Recorder *r = nullptr;

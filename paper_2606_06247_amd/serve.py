@@ -14,6 +14,19 @@ observed by polling an event per batch; latency = completion - arrival.
 Every result equals the plain call on the same plan bitwise (the batch
 launches the same kernels on the same data), so a request gives the same
 output alone and in the mix.
+
+Failure handling (each request ends with a status):
+* "ok";
+* "nonfinite": with check_finite set, every output is checked by the
+  library's finiteness count when its batch completes; a request whose
+  inputs or outputs hold NaN / infinities fails alone (batch items share no
+  data, so the others in its batch are unaffected);
+* "rejected": a request whose plan workspace and buffers exceed the whole HBM
+  budget can never be admitted and is refused on arrival;
+* "timeout": not admitted within its deadline (seconds after arrival);
+* "cancelled": cancelled (Server.cancel, or its cancel_at time) while still
+  queued; work already issued to the device runs to completion.
+Latency statistics cover the "ok" requests.
 """
 from __future__ import annotations
 
@@ -37,6 +50,10 @@ class Request:
     seed: int
     t_done: float = math.nan
     out: list = field(default_factory=list)
+    status: str = "pending"
+    deadline: float = math.inf     # admission deadline, seconds after arrival
+    cancel_at: float = math.inf    # cancelled if still queued at this time (from the stream start)
+    poison: bool = False           # inputs carry a NaN (failure-path tests)
 
 
 def make_requests(lam: float, count: int, seed: int = 40, p_step: float = 0.5, p_2d: float = 0.75,
@@ -75,9 +92,11 @@ def problem_for(dims: int, n: int, precision: str, op_eval: str = "fft_window") 
 class Server:
     def __init__(self, precision: str = "fp64", hbm_budget: float = 200e9, max_batch: int = 16,
                  lanes: int = 4, op_eval: str = "fft_window", dt: float = 1e-4, nu: float = 1e-3,
-                 max_batch_3d: int = 2):
+                 max_batch_3d: int = 2, check_finite: bool = False):
         import torch
         self.precision, self.op_eval = precision, op_eval
+        self.check_finite = check_finite
+        self.cancelled: set = set()
         self.budget = hbm_budget
         self.max_batch = max_batch
         self.max_batch_3d = max(1, min(max_batch_3d, max_batch))
@@ -89,6 +108,7 @@ class Server:
         self.pool: dict = {}                    # shape key -> idle plans
         self.count: dict = {}                   # shape key -> plan instances
         self.used = 0.0                         # bytes: plan workspaces + request buffers in flight
+        self.resident = 0.0                     # bytes: plan workspaces (resident until the server ends)
         self.templates: dict = {}
         self.plan_ctx = api.Context(0)
         self.stats = {"plans_created": 0, "admitted": 0, "max_queue": 0, "batches": 0}
@@ -112,6 +132,7 @@ class Server:
         plan = api.Plan(self.plan_ctx, problem_for(dims, n, self.precision, self.op_eval))
         self.plan_ctx.sync()           # tables resident before any lane stream uses the plan
         self.used += plan.workspace.numel()
+        self.resident += plan.workspace.numel()
         self.stats["plans_created"] += 1
         return plan
 
@@ -126,6 +147,20 @@ class Server:
     def _request_bytes(self, r: Request) -> int:
         pts = r.n ** r.dims
         return pts * 8 * (2 * r.dims + 1 if r.kind == "step" else 2)
+
+    def cancel(self, rid: int):
+        """Cancel a request that is still queued (no effect once issued)."""
+        self.cancelled.add(rid)
+
+    def _never_fits(self, r: Request) -> bool:
+        """Resident plans are never evicted, so the room a request can ever get
+        is the budget less every plan workspace."""
+        room = self.budget - self.resident
+        need = self._request_bytes(r)
+        if self.count.get(self._key(r), 0) > 0:
+            return need > room
+        ws = api.workspace_bytes(problem_for(r.dims, r.n, self.precision, self.op_eval))
+        return ws + need > room
 
     def _acquire(self, r: Request):
         idle = self.pool.setdefault(self._key(r), [])
@@ -151,9 +186,13 @@ class Server:
         if r.kind == "step":
             u = [(c * s).contiguous() for c in tpl]
             wall = [c.clone() for c in u]
+            if r.poison:
+                u[0][tuple(k // 2 for k in u[0].shape)] = float("nan")   # an interior point
             p = torch.empty_like(u[0])
             return {"u": u, "wall": wall, "p": p}
         rhs = (tpl[0] * s).contiguous()
+        if r.poison:
+            rhs[tuple(k // 2 for k in rhs.shape)] = float("nan")     # an interior point
         if self.precision == "fp32":
             rhs = rhs.float()
         return {"rhs": rhs, "phi": torch.empty_like(tpl[0])}
@@ -166,8 +205,14 @@ class Server:
                 continue
             t = now_fn()
             for r, plan, bufs in fl[1]:
-                r.t_done = t
                 r.out = [bufs["u"], bufs["p"]] if r.kind == "step" else [bufs["phi"]]
+                r.status = "ok"
+                if self.check_finite:
+                    outs = (bufs["u"] + [bufs["p"]]) if r.kind == "step" else [bufs["phi"]]
+                    if any(plan.nonfinite_count(o) for o in outs):
+                        r.status = "nonfinite"
+                    t = now_fn()
+                r.t_done = t
                 self.pool[self._key(r)].append(plan)
                 self.used -= self._request_bytes(r)
                 done += 1
@@ -203,10 +248,31 @@ class Server:
         def now():
             return time.perf_counter() - t0
         remaining = len(requests)
+        for r in requests:
+            r.status = "pending"
+
+        def finish(r, status):
+            r.status, r.t_done = status, now()
+            return 1
         while remaining:
             t = now()
             while pending and pending[0].t_arrival <= t:
-                queue.append(pending.popleft())
+                r = pending.popleft()
+                if self._never_fits(r):
+                    remaining -= finish(r, "rejected")
+                else:
+                    queue.append(r)
+            # queued requests past their deadline or cancelled leave the queue
+            if queue:
+                keep = deque()
+                for r in queue:
+                    if r.rid in self.cancelled or t >= r.cancel_at:
+                        remaining -= finish(r, "cancelled")
+                    elif t - r.t_arrival >= r.deadline:
+                        remaining -= finish(r, "timeout")
+                    else:
+                        keep.append(r)
+                queue = keep
             self.stats["max_queue"] = max(self.stats["max_queue"], len(queue))
             remaining -= self._poll(now)
             free = [k for k, fl in enumerate(self.inflight) if fl is None]
@@ -235,14 +301,19 @@ class Server:
             if not free or not queue:
                 time.sleep(0.0002)
         wall = now()
-        lat = np.array([r.t_done - r.t_arrival for r in requests])
+        ok = [r for r in requests if r.status == "ok"]
+        lat = np.array([r.t_done - r.t_arrival for r in ok]) if ok else np.array([math.nan])
         if not keep_outputs:
             for r in requests:
                 r.out = []
+        status = {}
+        for r in requests:
+            status[r.status] = status.get(r.status, 0) + 1
         return {"requests": len(requests), "wall_s": round(wall, 3),
-                "solves_per_s": round(len(requests) / wall, 1),
+                "solves_per_s": round(len(ok) / wall, 1),
                 "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                "status": status,
                 "plans_created": self.stats["plans_created"], "batches": self.stats["batches"],
                 "max_queue": self.stats["max_queue"], "hbm_used_GB": round(self.used / 1e9, 2)}
 
