@@ -292,6 +292,29 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out,
                                 double dt, double nu);
 
 /*
+ * Linear advection of a scalar with inflow / outflow walls (the Gaussian
+ * vortex convection section, eq. linearAdvection, read with C_y du/dy as the
+ * second term): sub-step k (0, 1, 2) of the low-storage RK3 of the temporal
+ * discretisation section,
+ *   F = c[0] du/dx + c[1] du/dy,   u <- u - dt (g_k F + z_k F_prev),
+ * with the spectral SPH gradient of the FC-extended u.  The scalar has no wall
+ * condition of its own: every wall uses the plain continuation map (the
+ * Dirichlet-wall map fc_M_dir, values only); inflow walls (c . n < 0, n the
+ * outward normal) take `inflow` (physical array: the exact or imposed values
+ * at the end of the sub-step; NULL: zero), outflow walls keep the computed
+ * values.  u: physical FP64 device array, updated in place; F_store: physical
+ * FP64 device array (caller-owned), holds F of sub-step k - 1 on entry (read
+ * when k > 0) and F on exit; c: host array of the two velocity components
+ * (x, y); dt: the whole RK3 step; inflow: physical FP64 device array or NULL.
+ * A full step is the three calls k = 0, 1, 2 in order on the same F_store.
+ * Errors: FCSPH_E_INVALID for a NULL u, F_store or c, k outside 0..2 or a
+ * non-positive dt; FCSPH_E_UNSUPPORTED unless the plan is FP64, 2D and on an
+ * FFT route (not FCSPH_OPS_DIRECT).
+ */
+fcsph_status fcsph_advect_rk3_substep(fcsph_plan *p, int k, double *u, double *F_store, const double *c, double dt,
+                                      const double *inflow);
+
+/*
  * Sub-step k (0, 1, 2) of the low-storage third-order Runge-Kutta scheme
  * (temporal discretisation section: eqs. uStarRK3, rhsMomtem, PPE and u^n+1
  * with the RK3 coefficients a = (8/15, 2/15, 1/3), g = (8/15, 5/12, 3/4),

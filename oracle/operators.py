@@ -29,6 +29,8 @@ with the Gaussian kernels by pair sums and 4th-order convergence in
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 from . import fc as fcmod
@@ -64,6 +66,14 @@ def conv_fft(e: np.ndarray, tap_list, workers: int = -1) -> np.ndarray:
                        s=e.shape, workers=workers)
 
 
+@functools.lru_cache(maxsize=8)
+def _gaussian_taps(order, ndim, h_over_dx, dx, ext):
+    """The Gaussian tap list of one lattice, built once (it is the same for
+    every operator call on that lattice)."""
+    from . import gaussian
+    return gaussian.taps(gaussian.GaussianKernel(order, ndim, h_over_dx * dx), dx, ext)
+
+
 class Operators:
     """Gradient / divergence / Laplacian on one lattice.
 
@@ -78,9 +88,7 @@ class Operators:
             tl = kernels.taps(lat.ndim, lat.dx, lat.h_over_dx)
         else:
             # Gaussian family: every offset of the extended lattice (minimum image)
-            from . import gaussian
-            kern = gaussian.GaussianKernel(int(lat.kernel[1:]), lat.ndim, lat.h_over_dx * lat.dx)
-            tl = gaussian.taps(kern, lat.dx, lat.ext)
+            tl = _gaussian_taps(int(lat.kernel[1:]), lat.ndim, lat.h_over_dx, lat.dx, tuple(lat.ext))
         self.grad_taps = [[(s, float(g[a])) for s, g, _ in tl] for a in range(lat.ndim)]
         self.lap_taps = [(s, lap) for s, _, lap in tl]
 

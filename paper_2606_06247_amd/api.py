@@ -37,7 +37,7 @@ EXPORTS = [
     "fcsph_ctx_last_error", "fcsph_plan_workspace_bytes", "fcsph_plan_create",
     "fcsph_plan_destroy", "fcsph_plan_transform_lengths", "fcsph_fc_extend", "fcsph_spectral_grad",
     "fcsph_spectral_div",
-    "fcsph_spectral_lap", "fcsph_spectral_lap_noalloc", "fcsph_ppe_solve", "fcsph_check_finite", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_ctx_set_timing",
+    "fcsph_spectral_lap", "fcsph_spectral_lap_noalloc", "fcsph_ppe_solve", "fcsph_check_finite", "fcsph_project_step", "fcsph_rk3_substep", "fcsph_advect_rk3_substep", "fcsph_ctx_set_timing",
     "fcsph_ctx_read_timing", "fcsph_ctx_set_timing_only", "fcsph_batch_workspace_bytes", "fcsph_batch_create", "fcsph_batch_destroy",
     "fcsph_batch_clear", "fcsph_batch_add_step", "fcsph_batch_add_rk3_substep", "fcsph_batch_add_ppe", "fcsph_batch_launch",
     "fcsph_batch_capture", "fcsph_batch_replay", "fcsph_batch_info",
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
     L.fcsph_check_finite.argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_ulonglong)]
     L.fcsph_project_step.argtypes = [vp, P(vp), vp, P(vp), P(vp), d, d]
     L.fcsph_rk3_substep.argtypes = [vp, i, P(vp), vp, P(vp), P(vp), P(vp), d, d]
+    L.fcsph_advect_rk3_substep.argtypes = [vp, i, vp, vp, P(d), d, vp]
     L.fcsph_ctx_set_timing.argtypes = [vp, i]
     L.fcsph_ctx_set_timing_only.argtypes = [vp, ctypes.c_char_p]
     L.fcsph_ctx_read_timing.argtypes = [vp, i, ctypes.c_char_p, P(i), P(d), P(i)]
@@ -383,6 +384,16 @@ class Plan:
         _check(lib().fcsph_project_step(self.handle, up, pp, fp, wp, float(dt), float(nu)),
                self.ctx.handle, "fcsph_project_step")
         return u, p_out
+
+    def advect_rk3_substep(self, k: int, u, F, c, dt: float, inflow=None):
+        """fcsph_advect_rk3_substep: RK3 sub-step k of linear advection of the
+        scalar u (in place) with velocity c; F holds F of the previous
+        sub-step and receives this one's; inflow: wall values of the inflow walls."""
+        cc = (ctypes.c_double * 2)(*[float(x) for x in c])
+        _check(lib().fcsph_advect_rk3_substep(self.handle, int(k), self._phys(u), self._phys(F), cc, float(dt),
+                                              self._phys(inflow) if inflow is not None else None),
+               self.ctx.handle, "fcsph_advect_rk3_substep")
+        return u
 
     def rk3_substep(self, k: int, u, F, dt: float, nu: float, p_out=None, force=None, wall=None):
         """RK3 sub-step k (0, 1, 2) of the whole step dt; u (list of tensors) is

@@ -631,6 +631,9 @@ fcsph_status hip_fail(fcsph_ctx *c, hipError_t e, const char *where) {
   return fail(c, FCSPH_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// Field class of a transported scalar (FC with the value map on every wall).
+constexpr int kFieldScalar = 2;
+
 FcWalls walls_for(const fcsph_plan *p, int axis, int fc) {
   FcWalls w{};
   w.on = p->walled[axis];
@@ -642,7 +645,10 @@ FcWalls walls_for(const fcsph_plan *p, int axis, int fc) {
     w.head = p->reach;
     w.tail = p->reach;
   }
-  if (w.on) {
+  if (w.on && fc == kFieldScalar) {
+    // a transported scalar: the plain (value) continuation on every wall
+    w.Mlo = w.Mhi = p->M_dir;
+  } else if (w.on) {
     const int(*bc)[2] = fc == FCSPH_FIELD_VELOCITY ? p->d.vel_bc : p->d.prs_bc;
     w.Mlo = bc[axis][0] == FCSPH_BC_NEUMANN ? p->M_neu : p->M_dir;
     w.Mhi = bc[axis][1] == FCSPH_BC_NEUMANN ? p->M_neu : p->M_dir;
@@ -2213,6 +2219,61 @@ fcsph_status fcsph_project_step(fcsph_plan *p, double *const *u, double *p_out, 
                                 const double *const *wall_vel, double dt, double nu) {
   RkTerms rk{};
   return step_impl(p, u, p_out, force, wall_vel, dt, nu, dt, rk);
+}
+
+fcsph_status fcsph_advect_rk3_substep(fcsph_plan *p, int k, double *u, double *F_store, const double *c, double dt,
+                                      const double *inflow) {
+  if (!p) return FCSPH_E_INVALID;
+  if (!u || !F_store || !c) return fail(p->ctx, FCSPH_E_INVALID, "null pointer");
+  if (k < 0 || k > 2) return fail(p->ctx, FCSPH_E_INVALID, "RK3 sub-step index must be 0, 1 or 2");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p->ctx, FCSPH_E_INVALID, "dt must be positive");
+  if (p->nd != 2 || p->direct || p->fp32)
+    return fail(p->ctx, FCSPH_E_UNSUPPORTED, "linear advection is built for FP64 2D plans on the FFT routes");
+  static const double kg[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+  static const double kz[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+  fcsph_status st = FCSPH_OK;
+  if (!chk(p, x_fwd_single(p, u, kFieldScalar, p->S[0]), "advect x", st)) return st;
+  ColsArgs cc = cols_base(p, COLS_OP, kFieldScalar);
+  if (!chk(p, set_edges(p, cc, 1, (const double *const *)&u, kFieldScalar), "advect edges", st)) return st;
+  cc.in[0] = p->S[0];
+  cc.out[0][0] = p->O[0];
+  cc.out[0][1] = p->O[1];
+  cc.nout = 2;
+  cc.sym[0] = SYM_GX;
+  cc.sym[1] = SYM_GY;
+  if (!chk(p, cols_launch(p, cc, 1, "cols_op_advect"), "advect y", st)) return st;
+  RowsInvArgs r{};
+  r.plan = p->op[0];
+  r.nrows = p->n[1];
+  r.nx = p->n[0];
+  r.E = p->E[0];
+  r.H = p->H;
+  r.B = pick_B(r.plan, p->fp32, p->want_B);
+  r.ldsM = padded_len(r.plan.M, r.plan.pad);
+  r.spec[0] = p->O[0];
+  r.spec[1] = p->O[1];
+  r.spec_pitch = p->H;
+  r.rpp = p->n[1];
+  r.prow = p->n[1];
+  r.u[0] = u;
+  r.unew[0] = u;
+  r.wall[0] = inflow;
+  r.dt = dt;
+  r.rk.on = 1;
+  r.rk.g = kg[k];
+  r.rk.z = kz[k];
+  r.rk.F[0] = F_store;
+  r.adv_c[0] = c[0];
+  r.adv_c[1] = c[1];
+  // inflow walls (C . n < 0) take the caller's data; outflow walls are free
+  r.wi = wall_info(p);
+  for (int a = 0; a < 2; ++a) {
+    r.wi.dir[a][0] = p->walled[a] && c[a] > 0.0;
+    r.wi.dir[a][1] = p->walled[a] && c[a] < 0.0;
+  }
+  LaunchTimer t(p->ctx, "rows_inv_advect");
+  if (!chk(p, launch_rows_inv(r, EPI_ADVECT2, p->fp32, p->ctx->stream), "advect x inv", st)) return st;
+  return FCSPH_OK;
 }
 
 fcsph_status fcsph_rk3_substep(fcsph_plan *p, int k, double *const *u, double *p_out, const double *const *force,

@@ -127,7 +127,8 @@ enum RowsEpi {
   EPI_STEP_A2 = 1,     // 2D: u* from (Gx u, Gy u), (Gx v, Gy v), (L u, L v)
   EPI_STEP_D2 = 2,     // 2D: projection from (Gx phi, Gy phi)
   EPI_STEP_A3 = 3,     // 3D: u* from 12 derivatives in 6 packed lines
-  EPI_STEP_D3 = 4      // 3D: projection from 3 gradients in 2 packed lines
+  EPI_STEP_D3 = 4,     // 3D: projection from 3 gradients in 2 packed lines
+  EPI_ADVECT2 = 5      // 2D: RK3 sub-step of linear advection from (Gx u, Gy u)
 };
 
 struct WallInfo {
@@ -195,6 +196,10 @@ struct RowsInvArgs {
   int fwd_fused;
   FcWalls fwd_fc;
   void *fwd_out[2];
+  // EPI_ADVECT2: F = adv_c[0] Gx u + adv_c[1] Gy u, u <- u - dt (g F + z F_prev)
+  // (rk.g, rk.z, rk.F[0]: F_prev in, F out), u[0] read and unew[0] written;
+  // wall points flagged in wi.dir take wall[0]
+  double adv_c[2];
 };
 
 // ---------------------------------------------------------------- strided passes

@@ -182,6 +182,25 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
         if (okB) static_cast<float *>(a.out[oB])[(size_t)rB * a.nx + x] = (float)(a.scale * (double)(-z.i));
       }
     }
+  } else if constexpr (EPI == EPI_ADVECT2) {
+    const int row = blockIdx.x * a.B + g;
+    const bool ok = row < a.nrows;
+    const cpx<T> *sA = ok ? static_cast<const cpx<T> *>(a.spec[0]) + spec_row(a, row) : nullptr;
+    const cpx<T> *sB = ok ? static_cast<const cpx<T> *>(a.spec[1]) + spec_row(a, row) : nullptr;
+    load_packed_c2r<T, true>(buf, sA, sB, a.E, a.H, lt, TL);
+    __syncthreads();
+    line_dft<T>(buf, a.plan, lt, TL, false, false);   // conjugated output
+    if (!ok) return;
+    const size_t ro = (size_t)row * a.nx;
+    for (int x = lt; x < a.nx; x += TL) {
+      const double gx = (double)buf[x].r, gy = (double)(-buf[x].i);
+      const double F = a.adv_c[0] * gx + a.adv_c[1] * gy;
+      const double Fp = a.rk.z != 0.0 ? a.rk.F[0][ro + x] : 0.0;
+      a.rk.F[0][ro + x] = F;
+      double un = a.u[0][ro + x] - a.dt * (a.rk.g * F + a.rk.z * Fp);
+      if (is_dirichlet_point(a.wi, x, row, 0)) un = a.wall[0] ? a.wall[0][ro + x] : 0.0;
+      a.unew[0][ro + x] = un;
+    }
   } else if constexpr (EPI == EPI_STEP_D2) {
     const int row = blockIdx.x * a.B + g;
     const bool ok = row < a.nrows;
@@ -1165,6 +1184,11 @@ static hipError_t rows_inv_dispatch(const RowsInvArgs &a, int epi, hipStream_t s
       block = dim3(a.B * TL);
       lds = lds_bytes(a.B, a.ldsM, sizeof(T) == 4);
       return rows_inv_t<T, EPI_STEP_D2>(a, grid, block, lds, s);
+    case EPI_ADVECT2:
+      grid = dim3((a.nrows + a.B - 1) / a.B);
+      block = dim3(a.B * TL);
+      lds = lds_bytes(a.B, a.ldsM, sizeof(T) == 4);
+      return rows_inv_t<T, EPI_ADVECT2>(a, grid, block, lds, s);
     case EPI_STEP_A2:
     case EPI_STEP_A3:
     case EPI_STEP_D3: {

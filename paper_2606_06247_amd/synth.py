@@ -185,3 +185,13 @@ class ChannelFlow3D:
                     comps[2] += a * dY * X * Z
         s = 1.0 / np.sqrt(np.max(comps[0] ** 2 + comps[1] ** 2 + comps[2] ** 2))
         self.u = [c * s for c in comps]
+
+
+def gaussian_vortex(n, dx, t, alpha=100.0, x0=0.5, y0=0.5, cx=1.0, cy=0.5):
+    """The convected Gaussian of the vortex-convection workload: the initial
+    field exp(-alpha r^2) about (x0, y0) translated by (cx t, cy t) (the exact
+    solution of linear advection with that velocity).  n = (nx, ny)."""
+    nx, ny = n
+    x = (np.arange(nx) * dx)[None, :]
+    y = (np.arange(ny) * dx)[:, None]
+    return np.exp(-alpha * ((x - (x0 + cx * t)) ** 2 + (y - (y0 + cy * t)) ** 2))
