@@ -132,6 +132,13 @@ struct Upload {
 bool factor_direct(int n, std::vector<int> &rad, bool big = false) {
   rad.clear();
   int m = n;
+  if (big) {
+    // large odd primes (streamed stages) first, largest first: the first
+    // stage takes no twiddles
+    const int odd_big[] = {31, 29, 23, 19, 17, 13, 11};
+    for (int p : odd_big)
+      while (m % p == 0) { rad.push_back(p); m /= p; }
+  }
   while (m % 8 == 0 && m > 8) { rad.push_back(8); m /= 8; }
   if (m % 8 == 0) { rad.push_back(8); m /= 8; }
   while (m % 4 == 0) { rad.push_back(4); m /= 4; }
@@ -139,11 +146,6 @@ bool factor_direct(int n, std::vector<int> &rad, bool big = false) {
   const int odd[] = {3, 5, 7};
   for (int p : odd)
     while (m % p == 0) { rad.push_back(p); m /= p; }
-  if (big) {
-    const int odd_big[] = {11, 13, 17, 19, 23, 29, 31};
-    for (int p : odd_big)
-      while (m % p == 0) { rad.push_back(p); m /= p; }
-  }
   if (m != 1) return false;
   if (rad.empty()) rad.push_back(1);
   return (int)rad.size() <= kMaxStages;
@@ -162,6 +164,10 @@ int line_threads(int M, const std::vector<int> &rad, int min_TL = 64, bool wide 
   int tl = std::max(64, min_TL);
   for (int R : rad) {
     if (R <= 1) continue;
+    if (R >= kStreamRadix) {
+      tl = std::max(tl, stream_threads(M, R));   // streamed stage
+      continue;
+    }
     tl = std::max(tl, (M / R + nb_max(R, wide) - 1) / nb_max(R, wide));
   }
   tl = (tl + 63) / 64 * 64;
@@ -246,6 +252,11 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
   p.nstages = (int)rad.size();
   if (n == 1) p.nstages = 0;
   for (int s = 0; s < p.nstages; ++s) p.radix[s] = rad[s];
+  // streamed stages write to a second region of the line buffer, starting at
+  // a multiple of the LDS padding period
+  p.spare = 0;
+  for (int s = 0; s < p.nstages; ++s)
+    if (p.radix[s] >= kStreamRadix) p.spare = (M + 1 + 15) & ~15;
   p.TL = tl;
   // LDS padding (one slot every 16 elements): a sweep of 0..5 on the 1024^2
   // step put 3..5 ahead of none by 2-4 %; the device code uses the fixed shift
@@ -616,7 +627,8 @@ namespace {
 // length, plus the result and 8 partial-sum slots for the length-N DCT-I.
 int ppe_line_len(const fcsph_plan *p, int a) {
   const LinePlan &t = p->trig[a];
-  return p->dcs[a] ? t.M + 1 + t.n + 1 + 8 : t.M;
+  const int len = p->dcs[a] ? t.M + 1 + t.n + 1 + 8 : t.M;
+  return t.spare ? std::max(len, t.spare + t.M) : len;
 }
 }  // namespace
 
@@ -934,8 +946,8 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     const int minTL = (a == 0) ? 64 : 64;
     // the narrow butterfly rule where the line fits (more waves per SIMD),
     // else the wide one (longer lines per workgroup)
-    if (!make_line_plan(L, false, minTL, ws, up, p->trig[a], false, false) &&
-        !make_line_plan(L, false, minTL, ws, up, p->trig[a], false, true)) {
+    if (!make_line_plan(L, false, minTL, ws, up, p->trig[a], true, false) &&
+        !make_line_plan(L, false, minTL, ws, up, p->trig[a], true, true)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }

@@ -20,6 +20,16 @@ struct alignas(2 * sizeof(T)) cpx {
   T r, i;
 };
 
+// Odd prime radices from kStreamRadix up (PPE plans only) are streamed
+// through LDS between the line and a second region of its buffer, by
+// kStreamThreads waves per 64 butterflies (each thread holds a block of
+// output pairs, never the R inputs).  Such a stage needs one wave per block;
+// the waves loop over further chunks of 64 butterflies, so that it does not
+// widen the line group (a wider group fits fewer lines per CU).
+constexpr int kStreamRadix = 11;
+constexpr int kStreamThreads = 3;
+__host__ __device__ constexpr int stream_threads(int, int) { return kStreamThreads * 64; }
+
 // Largest number of butterflies per thread and stage for radix R; a line
 // group needs ceil(N / (R nb_max(R))) threads for a stage of radix R on N
 // points.  The stage keeps nb_max(R) butterflies in registers across its
@@ -65,6 +75,9 @@ struct LinePlan {
   int TL;          // threads per line the plan is sized for
   int pad;         // LDS padding shift of the line buffers (0: none)
   int wide;        // 1: sized for the wide butterfly rule (PPE kernels only)
+  int spare;       // > 0: streamed stages (radix >= kStreamRadix) alternate between
+                   // the line and positions [spare, spare + M) (a multiple of 16);
+                   // the line buffer must hold them (PPE kernels only)
   const void *tw;     // [M]  exp(-2 pi i t / M)
   const void *chirp;  // [n]  exp(-pi i (t^2 mod 2n) / n)        (Bluestein)
   const void *filt;   // [M]  DFT_M(wrapped conj chirp) / M       (Bluestein)

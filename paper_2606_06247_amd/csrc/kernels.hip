@@ -860,7 +860,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = trig1_pre<T>(buf, a.plan, a.dcs, a.kind == TRIG_DST1, lt, TL);
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
-  line_dft<T, false, W>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, true, W>(buf, a.plan, lt, TL, cj, cj);
   if (half) trig1_post<T>(buf, a.plan, z1, a.kind == TRIG_DST1, lt, TL);
 
   // ---- results
@@ -968,7 +968,7 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = trig1_pre<T>(buf, a.plan, a.dcs, a.kind == TRIG_DST1, lt, TL);
   const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
-  line_dft<T, false, W>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, true, W>(buf, a.plan, lt, TL, cj, cj);
   if (half) trig1_post<T>(buf, a.plan, z1, a.kind == TRIG_DST1, lt, TL);
   if (qw && !is_values) {
     // F = 2i W (QWS), 2 W (QWC); position N holds no mode

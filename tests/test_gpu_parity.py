@@ -107,6 +107,14 @@ PPE_CASES = [
     spec((48, 37), (False, True), vel=(None, ("D", "N"))),                 # P x ND
     spec((40, 41), (True, True), vel=(("D", "N"), ("D", "D"))),            # ND x NN
     spec((64, 64), (True, True), vel=(("N", "D"), ("N", "N"))),            # DN x DD
+    # transform lengths with the streamed odd radices 11 .. 31 (first and later
+    # stages, several chunks of butterflies): 143 = 13 x 11, 69 = 23 x 3,
+    # 58 = 29 x 2, 323 = 19 x 17, 961 = 31 x 31, 23 (one stage), 286 = 13 x 11 x 2
+    spec((144, 70), (True, True)),
+    spec((59, 324), (True, True), vel=(("N", "N"), ("N", "N"))),           # DST-I pressure
+    spec((962, 24), (True, True)),
+    spec((286, 40), (False, True)),                                        # periodic x: DFT rows
+    spec((12, 45), (True, True), vel=(("D", "N"), ("N", "D"))),            # quarter-wave: 2 x 11, 4 x 11
 ]
 
 
