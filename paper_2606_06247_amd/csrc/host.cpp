@@ -944,10 +944,19 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
     p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : qw ? nn - 1 : nn - 2);
     const int minTL = (a == 0) ? 64 : 64;
+    // Streamed large radices (instead of Bluestein) only while every line pair
+    // of the axis fits on the chip at once (1024 SIMDs at the PPE kernels' two
+    // waves each): there the pass is bound by one line's serial chain, which
+    // they shorten; with more lines it is bound by throughput, and their
+    // three waves per line (mostly idle for short lines) cost more than the
+    // Bluestein transform's work (256^3 channel, N = 255: 617 against 291 us
+    // per y pass).
+    const long pairs = (long)((size_t)p->n[0] * p->n[1] * p->n[2] / nn + 1) / 2;
+    const bool stream = pairs * stream_threads(L, 0) <= 1024L * 2 * 64;
     // the narrow butterfly rule where the line fits (more waves per SIMD),
     // else the wide one (longer lines per workgroup)
-    if (!make_line_plan(L, false, minTL, ws, up, p->trig[a], true, false) &&
-        !make_line_plan(L, false, minTL, ws, up, p->trig[a], true, true)) {
+    if (!make_line_plan(L, false, minTL, ws, up, p->trig[a], stream, false) &&
+        !make_line_plan(L, false, minTL, ws, up, p->trig[a], stream, true)) {
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }
