@@ -1148,9 +1148,37 @@ hipError_t cols_launch(fcsph_plan *p, const ColsArgs &c, int gy, const char *nam
 }
 
 // FP32 plans: FP64 x spectra of the fc_d first and fc_d last rows of every
-// z plane of field f (FC_x fused as in the x pass), the FP64 inputs of FC_y.
+// z plane of a field (FC_x fused as in the x pass), the FP64 inputs of FC_y.
+// 2D: the boundary rows of both walls of one field f (g null: packed in row
+// pairs) or of two fields f, g (one row of each per line) in one launch;
+// logical rows d .. 2d-1 map to the high wall's rows n_y - d .. n_y - 1 and
+// land after the low wall's in the edge arrays.
+hipError_t edge_fwd_2d(fcsph_plan *p, const double *f, const double *g, int fc, void *edge_f, void *edge_g) {
+  const int d = p->d.fc_d;
+  RowsFwdArgs a{};
+  a.plan = p->op64[0];
+  a.nlines = g ? 2 * d : d;
+  a.nx = p->n[0];
+  a.E = p->E[0];
+  a.H = p->H;
+  a.fc = walls_for(p, 0, fc);
+  a.inA = f;
+  a.inB = g;
+  a.nB = a.nlines;
+  a.map_per = d;
+  a.map_plane = (long)(p->n[1] - d) * p->n[0];
+  a.outA = edge_f;
+  a.outB = g ? edge_g : (void *)((double2 *)edge_f + p->H);
+  a.ostrideA = a.ostrideB = g ? (long)p->H : 2L * p->H;
+  a.B = pick_B(a.plan, false, p->want_B);
+  a.ldsM = padded_len(a.plan.M, a.plan.pad);
+  LaunchTimer t(p->ctx, "rows_fwd_edge");
+  return launch_rows_fwd(a, false, p->ctx->stream);
+}
+
 hipError_t edge_fwd(fcsph_plan *p, const double *f, int fc, void *edge) {
   const int d = p->d.fc_d, nz = p->n[2], rows = nz * d;
+  if (nz == 1) return edge_fwd_2d(p, f, nullptr, fc, edge, nullptr);
   for (int h = 0; h < 2; ++h) {
     RowsFwdArgs a{};
     a.plan = p->op64[0];
@@ -1180,6 +1208,13 @@ hipError_t edge_fwd(fcsph_plan *p, const double *f, int fc, void *edge) {
 hipError_t set_edges(fcsph_plan *p, ColsArgs &c, int nf, const double *const *fields, int fc) {
   for (int f = 0; f < 3; ++f) c.edge[f] = nullptr;
   if (!p->fp32 || !p->edge[0] || !c.fc.on || c.line_axis != 1) return hipSuccess;
+  if (p->n[2] == 1 && nf == 2) {
+    hipError_t e = edge_fwd_2d(p, fields[0], fields[1], fc, p->edge[0], p->edge[1]);
+    if (e != hipSuccess) return e;
+    c.edge[0] = (const double2 *)p->edge[0];
+    c.edge[1] = (const double2 *)p->edge[1];
+    return hipSuccess;
+  }
   for (int f = 0; f < nf; ++f) {
     hipError_t e = edge_fwd(p, fields[f], fc, p->edge[f]);
     if (e != hipSuccess) return e;

@@ -129,8 +129,9 @@ struct RowsFwdArgs {
   long ostrideA, ostrideB;   // complex elements between consecutive lines
   int B;               // line groups per workgroup
   int ldsM;            // complex slots per line buffer
-  // map_per > 0: line l packs logical rows 2l, 2l+1 of inA, logical row r at
-  // inA + (r / map_per) * map_plane + (r % map_per) * nx (boundary-row blocks)
+  // map_per > 0: line l packs logical rows 2l, 2l+1 of inA, or (inB set)
+  // logical row l of inA and of inB; logical row r of a field at
+  // field + (r / map_per) * map_plane + (r % map_per) * nx (boundary-row blocks)
   int map_per;
   long map_plane;
 };

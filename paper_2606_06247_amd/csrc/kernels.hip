@@ -65,9 +65,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(KArg<RowsFwdArgs, G> k
   const bool active = line < a.nlines;
   const double *pa, *pb;
   if (a.map_per > 0) {
-    const int rA = 2 * line, rB = 2 * line + 1;
+    // rows 2l, 2l+1 of inA, or (inB set) row l of inA and row l of inB
+    const int rA = a.inB ? line : 2 * line, rB = a.inB ? line : 2 * line + 1;
+    const double *srcB = a.inB ? a.inB : a.inA;
     pa = active ? a.inA + (size_t)(rA / a.map_per) * a.map_plane + (size_t)(rA % a.map_per) * a.nx : nullptr;
-    pb = (active && line < a.nB) ? a.inA + (size_t)(rB / a.map_per) * a.map_plane + (size_t)(rB % a.map_per) * a.nx
+    pb = (active && line < a.nB) ? srcB + (size_t)(rB / a.map_per) * a.map_plane + (size_t)(rB % a.map_per) * a.nx
                                  : nullptr;
   } else {
     pa = active ? a.inA + (size_t)line * a.strideA : nullptr;
