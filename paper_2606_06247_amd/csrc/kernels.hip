@@ -360,13 +360,16 @@ __device__ __forceinline__ void line_coeffs(const ColsArgs &a, int q, int kin, i
   for (int s = 0; s < kSymW; ++s) R[s] = t[s];
 }
 
-__device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
-  // exp(-2 pi i k s / E), s = 1..3, from the plan's phase table (each entry
-  // rounded once from extended precision; loads instead of products)
+// The symbol from the line coefficients R and the first phase factor
+// p1 = exp(-2 pi i k / E) of line wavenumber k (from the plan's phase table,
+// rounded once from extended precision); the powers s = 2, 3 by products (a
+// few ulp on the symbol).
+__device__ __forceinline__ double2 sym_from_phase(const double2 *R, double2 p1) {
   double2 p[kSymR + 1];
-  const double2 *row = ph_line + (size_t)k * (kSymR + 1);
+  p[1] = p1;
 #pragma unroll
-  for (int s = 1; s <= kSymR; ++s) p[s] = row[s];
+  for (int s = 2; s <= kSymR; ++s)
+    p[s] = make_double2(p[s - 1].x * p[1].x - p[s - 1].y * p[1].y, p[s - 1].x * p[1].y + p[s - 1].y * p[1].x);
   double2 acc = R[kSymR];
 #pragma unroll
   for (int s = 1; s <= kSymR; ++s) {
@@ -376,6 +379,14 @@ __device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_
     acc.y += (rp.x - rm.x) * p[s].y + (rp.y + rm.y) * p[s].x;
   }
   return acc;
+}
+
+__device__ __forceinline__ double2 line_phase(const double2 *ph_line, int k) {
+  return ph_line[(size_t)k * (kSymR + 1) + 1];
+}
+
+__device__ __forceinline__ double2 sym_eval(const double2 *R, const double2 *ph_line, int k) {
+  return sym_from_phase(R, line_phase(ph_line, k));
 }
 
 
@@ -389,6 +400,18 @@ __device__ __forceinline__ double2 sym_value(const ColsArgs &a, int q, int c, in
                                              const double2 *ph_line, int k) {
   if constexpr (SF) return a.symF[(((size_t)q * a.ninner + c) * a.nouter + (o < 0 ? 0 : o)) * a.plan.n + k];
   else return sym_eval(R, ph_line, k);
+}
+// The same in two steps, so that a loop can issue the loads of several
+// wavenumbers before it uses them: sym_load (one table read) and sym_finish.
+template <bool SF>
+__device__ __forceinline__ double2 sym_load(const ColsArgs &a, int q, int c, int o, const double2 *ph_line, int k) {
+  if constexpr (SF) return a.symF[(((size_t)q * a.ninner + c) * a.nouter + (o < 0 ? 0 : o)) * a.plan.n + k];
+  else return line_phase(ph_line, k);
+}
+template <bool SF>
+__device__ __forceinline__ double2 sym_finish(const double2 *R, double2 v) {
+  if constexpr (SF) return v;
+  else return sym_from_phase(R, v);
 }
 
 template <bool SF>
@@ -469,9 +492,15 @@ __device__ __forceinline__ void cols_fc(const ColsArgs &a, Line<T> buf, int lt, 
 // At most 128 VGPRs (4 waves per SIMD): with the symbol coefficients read from
 // the plan's table the column kernels need 105-137; capped, only the FP64
 // operator form spills (12 B per lane), and the 1024^2 step gains 1 %, the
-// 256^3 step 2.5 % (four 4-wave workgroups per CU, as the LDS allows).
+// 256^3 step 2.5 % (four 4-wave workgroups per CU, as the LDS allows).  The
+// FP32 operator form (single-problem launch) is held to 96 VGPRs, 5 waves per
+// SIMD: its two FP32 lines of LDS per workgroup let five workgroups share a
+// CU, so the 1122 (field, column) tasks of the 1024^2 stage-A pass run in one
+// round instead of two (no spill; the grouped batch form would spill and
+// keeps 4).
 template <typename T, int MODE, bool G, bool SF = false>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kMaxThreads)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MODE == COLS_OP && !G) ? 5 : 4)))
 k_cols(KArg<ColsArgs, G> ka) {
   const ColsArgs &a = ka.get();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -544,10 +573,12 @@ k_cols(KArg<ColsArgs, G> ka) {
         __syncthreads();   // the previous output's store has finished reading xb
         // the inverse DFT is conj(DFT(conj(.))): the input conjugation is
         // folded into the symbol product, the output one into the store
-        for (int k = lt; k < E; k += TL) {
-          const double2 sv = sym_value<SF>(a, a.sym[pass - 1], cq, o, R, ph_line, k);
-          xb[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
-        }
+        const int q = a.sym[pass - 1];
+        batched<5, double2>(lt, E, TL, [&](int k) { return sym_load<SF>(a, q, cq, o, ph_line, k); },
+                            [&](int k, double2 v) {
+                              const double2 sv = sym_finish<SF>(R, v);
+                              xb[k] = cconj(cmul(to_cpx<T>(sv.x, sv.y), buf[k]));
+                            });
         __syncthreads();
       }
       line_dft<T>(pass == 0 ? buf : xb, a.plan, lt, TL, false, false);
