@@ -484,7 +484,8 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
         wl = sch.get("window_len", 0)
         prob = api.Problem(n=(n, n), walled=(True, True), dx=1.0 / (n - 1), vel_bc=vel,
                            prs_bc=_complement(vel), precision=precision, op_eval="fft_window",
-                           window_len=(wl, wl) if wl else (), lines_per_group=sch.get("lines_per_group", 0))
+                           window_len=(wl, wl) if wl else (), lines_per_group=sch.get("lines_per_group", 0),
+                           batched=True)
         plans.append(api.Plan(ctx, prob))
         u = [synth.poly_trig_2d(n, 1000 + 2 * i), synth.poly_trig_2d(n, 1001 + 2 * i)]
         states.append([torch.from_numpy(c).cuda() for c in u])

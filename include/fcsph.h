@@ -134,6 +134,13 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *              bound on lines per workgroup of the line kernels (1..16;
  *              default 1).  They change speed, never the result beyond
  *              rounding.
+ *  batched     1: the plan will also run in batches (fcsph_batch_add_*).
+ *              Its PPE transforms then never use the streamed radix stages
+ *              (odd primes 11..31), which only the single-problem kernels
+ *              carry; 0 (default): a PPE axis of few, long lines may use
+ *              them, and the batch calls refuse such a plan
+ *              (FCSPH_E_UNSUPPORTED).  Plain calls of a batched plan give
+ *              bitwise the results of its batch items.
  */
 typedef struct {
   int ndim;
@@ -154,6 +161,7 @@ typedef struct {
   int op_eval;
   int window_len[3];
   int lines_per_group;
+  int batched;
 } fcsph_desc;
 
 typedef struct fcsph_ctx fcsph_ctx;

@@ -587,6 +587,7 @@ struct fcsph_plan {
   LinePlan op[3];       // operator DFT along each axis (length E[a])
   LinePlan op64[3];     // FP32-mixed plans: FP64 twins for the PPE right-hand side
   LinePlan trig[3];     // PPE transform along each axis
+  bool ppe_streamed = false;   // some trig plan has streamed stages (no batches)
   int trig_kind[3] = {0, 0, 0};
   int ncoef[3] = {0, 0, 0};
   const double *mu[3] = {nullptr, nullptr, nullptr};
@@ -708,6 +709,7 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
   }
   if (!(d->rho > 0.0)) { msg = "rho must be positive"; return FCSPH_E_INVALID; }
   if (d->lines_per_group < 0 || d->lines_per_group > 16) { msg = "lines_per_group must be in 0..16"; return FCSPH_E_INVALID; }
+  if (d->batched != 0 && d->batched != 1) { msg = "batched must be 0 or 1"; return FCSPH_E_INVALID; }
   bool any_wall = false;
   for (int a = 0; a < d->ndim; ++a) {
     if (d->n[a] < 2) { msg = "n must be >= 2"; return FCSPH_E_INVALID; }
@@ -952,7 +954,8 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     // Bluestein transform's work (256^3 channel, N = 255: 617 against 291 us
     // per y pass).
     const long pairs = (long)((size_t)p->n[0] * p->n[1] * p->n[2] / nn + 1) / 2;
-    const bool stream = pairs * stream_threads(L, 0) <= 1024L * 2 * 64;
+    // (batched plans: never; the grouped kernels carry no streamed stages)
+    const bool stream = !d->batched && pairs * stream_threads(L, 0) <= 1024L * 2 * 64;
     // the narrow butterfly rule where the line fits (more waves per SIMD),
     // else the wide one (longer lines per workgroup)
     if (!make_line_plan(L, false, minTL, ws, up, p->trig[a], stream, false) &&
@@ -960,6 +963,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
       msg = "cannot plan a PPE transform of length " + std::to_string(L);
       return FCSPH_E_UNSUPPORTED;
     }
+    if (p->trig[a].spare > 0) p->ppe_streamed = true;
     // eigenvalues indexed by storage position
     std::vector<double> mu(nn, 0.0);
     const LD dx = d->dx;
@@ -2504,6 +2508,9 @@ fcsph_status fcsph_batch_clear(fcsph_batch *b) {
 
 static fcsph_status batch_add(fcsph_batch *b, fcsph_plan *p, int kind) {
   if ((int)b->items.size() >= b->max_items) return batch_fail(b, FCSPH_E_INVALID, "batch is full");
+  if (p->ppe_streamed)
+    return batch_fail(b, FCSPH_E_UNSUPPORTED,
+                      "the plan's PPE uses streamed radix stages (single launches only): create it with batched = 1");
   for (const fcsph_batch::Item &it : b->items)
     if (it.p == p) return batch_fail(b, FCSPH_E_INVALID, "a plan may appear once per batch (its scratch is shared)");
   b->items.push_back({p, kind, Recorder{}});

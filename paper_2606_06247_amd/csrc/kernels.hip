@@ -893,7 +893,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = trig1_pre<T>(buf, a.plan, a.dcs, a.kind == TRIG_DST1, lt, TL);
   const bool cj = a.inverse && (a.kind == TRIG_DFT || qw);
-  line_dft<T, true, W>(buf, a.plan, lt, TL, cj, cj);
+  // streamed radix stages in the single-problem kernel only (batched plans
+  // never use them), which keeps the grouped kernel's registers
+  line_dft<T, !G, W>(buf, a.plan, lt, TL, cj, cj);
   if (half) trig1_post<T>(buf, a.plan, z1, a.kind == TRIG_DST1, lt, TL);
 
   // ---- results
@@ -965,7 +967,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
 // ============================================================= PPE strided pass
 // Symmetric extension of buf[0..n) to length L and transform.  Coefficients
 // (is_values = false) or values (true) of the complex line end up in buf[0..n).
-template <typename T, bool W>
+template <typename T, bool W, bool BIG>
 __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArgs &a, int lt, int TL,
                                                    bool is_values) {
   // extension / twiddle before, one transform, mode extraction after
@@ -1001,7 +1003,7 @@ __device__ __forceinline__ void ppe_line_transform(Line<T> buf, const PpeColsArg
   cpx<T> z1 = {T(0), T(0)};
   if (half) z1 = trig1_pre<T>(buf, a.plan, a.dcs, a.kind == TRIG_DST1, lt, TL);
   const bool cj = (a.kind == TRIG_DFT || qw) && is_values;
-  line_dft<T, true, W>(buf, a.plan, lt, TL, cj, cj);
+  line_dft<T, BIG, W>(buf, a.plan, lt, TL, cj, cj);
   if (half) trig1_post<T>(buf, a.plan, z1, a.kind == TRIG_DST1, lt, TL);
   if (qw && !is_values) {
     // F = 2i W (QWS), 2 W (QWC); position N holds no mode
@@ -1067,7 +1069,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_cols(KArg<PpeColsArgs, G> k
   const int npass = a.solve == 1 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const bool values = a.solve == 2 || pass == 1;
-    ppe_line_transform<T, W>(buf, a, lt, TL, values);
+    ppe_line_transform<T, W, !G>(buf, a, lt, TL, values);
     if (a.solve == 1 && pass == 0) {
       // divide by -(mu_inner + mu_line + mu_outer) in FP64; a vanishing sum
       // (the constant mode) gives zero

@@ -83,10 +83,10 @@ def problem_for(dims: int, n: int, precision: str, op_eval: str = "fft_window") 
     if dims == 2:
         return api.Problem(n=(n, n), walled=(True, True), dx=1.0 / (n - 1),
                            vel_bc=(("D", "D"), ("D", "D")), prs_bc=(("D", "D"), ("D", "D")),
-                           precision=precision, op_eval=op_eval)
+                           precision=precision, op_eval=op_eval, batched=True)
     return api.Problem(n=(n, n, n), walled=(False, True, False), dx=1.0 / (n - 1),
                        vel_bc=(None, ("D", "D"), None), prs_bc=(None, ("N", "N"), None),
-                       precision=precision, op_eval=op_eval)
+                       precision=precision, op_eval=op_eval, batched=True)
 
 
 class Server:

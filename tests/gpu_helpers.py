@@ -25,11 +25,11 @@ def lattice(s) -> Lattice:
                    h_over_dx=s["h"], kernel=s.get("kernel", "wendland_c2"))
 
 
-def problem(s, precision="fp64", eig="spectral", op_eval="fft", ppe_domain="physical"):
+def problem(s, precision="fp64", eig="spectral", op_eval="fft", ppe_domain="physical", batched=False):
     from paper_2606_06247_amd.api import Problem
     return Problem(n=s["n"], walled=s["walled"], dx=s["dx"], vel_bc=s["vel"], prs_bc=s["prs"],
                    h_over_dx=s["h"], precision=precision, eig=eig, op_eval=op_eval, ppe_domain=ppe_domain,
-                   kernel=s.get("kernel", "wendland_c2"))
+                   kernel=s.get("kernel", "wendland_c2"), batched=batched)
 
 
 def rel_l2(got, ref) -> float:

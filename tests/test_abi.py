@@ -68,6 +68,10 @@ def test_workspace_query_and_validation():
     for oe in (api.OPS_FFT, api.OPS_DIRECT, api.OPS_FFT_WINDOW):
         assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(op_eval=oe)), ctypes.byref(nb)) == api.OK
     assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(op_eval=3)), ctypes.byref(nb)) == api.E_INVALID
+    # batched: 0 or 1
+    for v in (0, 1):
+        assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(batched=v)), ctypes.byref(nb)) == api.OK
+    assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(batched=2)), ctypes.byref(nb)) == api.E_INVALID
     # 3D: walls on y only; the direct evaluation is 2D only
     d3 = desc(ndim=3)
     d3.n[2] = 32

@@ -5,11 +5,17 @@ HIP graph replays the next step bitwise like a second plain call."""
 import numpy as np
 import pytest
 
-from gpu_helpers import lattice, problem, rel_l2, spec, to_dev, to_np
+from gpu_helpers import lattice, rel_l2, spec, to_dev, to_np
+from gpu_helpers import problem as _problem
 from oracle import step
 from paper_2606_06247_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+
+def problem(s, **kw):
+    """Every plan of these tests runs in batches (batched = 1)."""
+    return _problem(s, batched=True, **kw)
 
 
 @pytest.fixture(scope="module")
@@ -224,3 +230,20 @@ def test_tail_split_bitwise_1024(ctx, prec, oe):
     for a in range(2):
         assert torch.equal(plain[a], batched[a]), (a, float((plain[a] - batched[a]).abs().max()))
     assert torch.equal(pp, pb)
+
+
+def test_batch_refuses_plan_with_streamed_ppe(ctx):
+    """A plan built for single launches whose PPE uses the streamed radix
+    stages (1023 = 31 x 11 x 3 at 1024^2) is refused by the batch calls, with
+    no launch; built with batched = 1 it is accepted."""
+    import torch
+    from paper_2606_06247_amd import api
+    s = spec((1024, 1024), (True, True), vel=(("D", "D"), ("D", "D")), prs=(("N", "N"), ("N", "N")))
+    rhs = torch.zeros((1024, 1024), dtype=torch.float64, device="cuda")
+    b = api.Batch(ctx, 2)
+    single = api.Plan(ctx, _problem(s, op_eval="fft_window"))
+    with pytest.raises(api.FcsphError, match="streamed"):
+        b.add_ppe(single, rhs)
+    b.add_ppe(api.Plan(ctx, problem(s, op_eval="fft_window")), rhs)
+    b.launch()
+    torch.cuda.synchronize()

@@ -169,7 +169,7 @@ def test_rk3_batched_equals_plain_bitwise(ctx):
              (CASES_2D[2], "fp64", "direct"), (spec((24, 33, 16), (False, True, False)), "fp64", "fft_window")]
     plans, plain, batched = [], [], []
     for i, (s, prec, oe) in enumerate(items):
-        plans.append(api.Plan(ctx, problem(s, precision=prec, op_eval=oe)))
+        plans.append(api.Plan(ctx, problem(s, precision=prec, op_eval=oe, batched=True)))
         if s["nd"] == 2:
             u = [synth.poly_trig_2d(s["n"], 300 + 2 * i + k, dx=s["dx"]) for k in range(2)]
         else:
