@@ -191,7 +191,7 @@ def cpu_baseline(n: int, steps: int, budget_s: float) -> dict:
 
 
 # ------------------------------------------------------------------ timing
-def timed(ctx, step, steps: int, warmup: int, reset=None, profile_steps: int = 10):
+def timed(ctx, step, steps: int, warmup: int, reset=None, profile_steps: int = 10, known=None):
     """Runs warmup calls of step(k); then an untimed profiling pass of
     min(steps, profile_steps) calls with every kernel bracketed by HIP events
     (per-kernel breakdown, dominant kernel); then, after reset(), the timed
@@ -215,7 +215,9 @@ def timed(ctx, step, steps: int, warmup: int, reset=None, profile_steps: int = 1
     ctx.set_timing(False)
     prof = ctx.read_timing()
     prof_ms = q0.elapsed_time(q1)
-    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    # the dominant kernel among those with a byte model (known), if any
+    cand = {k: v for k, v in prof.items() if known is None or k in known} or prof
+    dom = max(cand.items(), key=lambda kv: kv[1][1])[0]
     if reset is not None:
         reset()
     ctx.set_timing(True, only=dom)
@@ -323,16 +325,76 @@ def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64
             for q in range(3):
                 plan.rk3_substep(q, u, F, dt, nu, p_out=p, force=forces[3 * c + q], wall=walls[3 * c + q])
 
+    ab = algorithmic_bytes_2d(n, precision == "fp32", n + (n // 4 if fc == "poly" else C_FC), rk3=scheme == "rk3")
     # the timed steps start at k = 0, which restarts the trajectory
-    wall_s, gpu_ms, live, profile = timed(ctx, step, steps, warmup)
+    wall_s, gpu_ms, live, profile = timed(ctx, step, steps, warmup, known=ab)
     ms_per_step = 1e3 * wall_s / steps
     finite = bool(all(torch.isfinite(c).all().item() for c in u))
-    ab = algorithmic_bytes_2d(n, precision == "fp32", n + (n // 4 if fc == "poly" else C_FC), rk3=scheme == "rk3")
+    # context: the state after the last timed step against the exact flow at
+    # its time (the trajectory restarts every `cycle` steps)
+    t_end = ((steps - 1) % cycle + 1) * dt
+    exact = flow.velocity(t_end)
+    err = [c.cpu().numpy() - e for c, e in zip(u, exact)]
+    vs_exact = {"t": t_end, "steps_into_cycle": (steps - 1) % cycle + 1,
+                "rms_error": float(f"{math.sqrt(sum(float((e * e).mean()) for e in err) / 2):.3e}"),
+                "rel_l2": float(f"{math.sqrt(sum(float((e * e).sum()) for e in err) / sum(float((x * x).sum()) for x in exact)):.3e}")}
     wl = f"2d_{n}_{precision}_{op_eval}" + ("" if scheme == "fop" else "_rk3") + ("" if fc == "gram" else "_fcpoly")
     roofline, per_kernel = summarise(live, profile, ab, steps, ms_per_step, wl)
+    if scheme == "fop":
+        # the method's compulsory I/O per FOP step, fully fused: 16 FP64 words
+        # per point (u, v, f_x, f_y in; u* out and read twice; b; phi; u, v out)
+        comp = 16 * n * n * 8
+        roofline["step_compulsory_GB"] = round(comp / 1e9, 4)
+        roofline["step_compulsory_frac"] = round(comp / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return {"value": round(n * n * steps / wall_s / 1e6, 2), "ms_per_step": round(ms_per_step, 4),
             "gpu_event_ms": round(gpu_ms, 3), "state_finite": finite, "roofline": roofline,
-            "kernels": per_kernel, "transform_lengths": plan.transform_lengths()}
+            "kernels": per_kernel, "transform_lengths": plan.transform_lengths(), "vs_exact": vs_exact}
+
+
+def run_calls(n: int = 64, reps: int = 200) -> dict:
+    """The small lattice of every boundary call: n x n on the unit square,
+    Dirichlet velocity and pressure on all four walls, manufactured fields
+    (seeds 0, 1, 2); microseconds per call (device time between events around
+    `reps` back-to-back calls, after warm-up) for each operator evaluation."""
+    import torch
+
+    from paper_2606_06247_amd import api, synth
+    ctx = api.Context(0)
+    dx = 1.0 / (n - 1)
+    u, v, pr = (torch.from_numpy(synth.poly_trig_2d(n, k, dx=dx)).cuda() for k in range(3))
+    out = {}
+    for oe in ("fft_window", "fft", "direct"):
+        prob = api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
+                           prs_bc=(("D", "D"), ("D", "D")), op_eval=oe)
+        plan = api.Plan(ctx, prob)
+        ext = plan.fc_extend(u)
+        g = plan.spectral_grad(pr, api.PRESSURE)
+        d = plan.spectral_div([u, v])
+        lp = plan.spectral_lap(u)
+        phi = plan.ppe_solve(d)
+        us = [u.clone(), v.clone()]
+        calls = {
+            "fc_extend": lambda: plan.fc_extend(u, api.VELOCITY, out=ext),
+            "spectral_grad": lambda: plan.spectral_grad(pr, api.PRESSURE, out=g),
+            "spectral_div": lambda: plan.spectral_div([u, v], out=d),
+            "spectral_lap": lambda: plan.spectral_lap(u, api.VELOCITY, out=lp),
+            "ppe_solve": lambda: plan.ppe_solve(d, out=phi),
+            "project_step": lambda: plan.project_step(us, 1e-4, 1e-3, p_out=phi),
+        }
+        rec = {}
+        for name, fn in calls.items():
+            for _ in range(20):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            rec[name] = round(1e3 * e0.elapsed_time(e1) / reps, 2)
+        out[oe] = rec
+    return out
 
 
 _INPUTS_2D = {}
@@ -435,10 +497,10 @@ def run_3d(n: int, steps: int, warmup: int, precision: str, ref_states=None, op_
         for c, c0 in zip(u, u0):
             c.copy_(c0)
 
-    wall_s, gpu_ms, live, profile = timed(ctx, timed_step, steps, 0, reset=reset)
+    ab = algorithmic_bytes_3d(n, precision == "fp32", n + C_FC)
+    wall_s, gpu_ms, live, profile = timed(ctx, timed_step, steps, 0, reset=reset, known=ab)
     ms_per_step = 1e3 * wall_s / steps
     finite = bool(all(torch.isfinite(c).all().item() for c in u))
-    ab = algorithmic_bytes_3d(n, precision == "fp32", n + C_FC)
     roofline, per_kernel = summarise(live, profile, ab, steps, ms_per_step, f"3d_{n}_{precision}_{op_eval}")
     out = {"value": round(n ** 3 * steps / wall_s / 1e6, 2), "ms_per_step": round(ms_per_step, 4),
            "gpu_event_ms": round(gpu_ms, 3), "state_finite": finite, "roofline": roofline,
@@ -653,18 +715,20 @@ def main() -> int:
                       "state_finite": head["state_finite"],
                       "schedule": sched64 if args.op_eval == "fft_window" else None},
            "roofline": head["roofline"]}
-    full = dict(out, kernels=head["kernels"], gpu_event_ms=head["gpu_event_ms"])
+    full = dict(out, kernels=head["kernels"], gpu_event_ms=head["gpu_event_ms"], vs_exact=head["vs_exact"])
     if not args.no_variants:
-        keep = ("value", "ms_per_step", "state_finite", "transform_lengths", "roofline", "kernels")
+        log("calls 2d 64 (us per call)")
+        full["calls_64_us"] = run_calls(64)
+        keep = ("value", "ms_per_step", "state_finite", "transform_lengths", "roofline", "kernels", "vs_exact")
         var = {}
         for oe in ("fft", "fft_window", "direct"):
             if oe != args.op_eval:
                 log(f"variant 2d {n} fp64 {oe}")
                 v = run_2d(oe, n, args.steps, args.warmup, schedule=sched64)
-                var[f"2d_{n}_fp64_{oe}"] = {k: v[k] for k in keep}
+                var[f"2d_{n}_fp64_{oe}"] = {k: v[k] for k in keep if k in v}
         log(f"variant 2d {n} fp64 {args.op_eval} RK3")
         v = run_2d(args.op_eval, n, max(1, args.steps // 3), args.warmup, schedule=sched64, scheme="rk3")
-        rec = {k: v[k] for k in keep}
+        rec = {k: v[k] for k in keep if k in v}
         rec["workload"] = ("the same 1024^2 workload advanced by whole low-storage RK3 steps (three sub-steps, "
                            "forcing at sub-step midpoints, wall data at sub-step ends), restart every "
                            f"{CYCLE_RK3} steps; value = points x RK3 steps / s")
@@ -672,7 +736,7 @@ def main() -> int:
         for oe in ("fft_window", "fft"):
             log(f"variant 2d {n} fp64 {oe} paper FC")
             v = run_2d(oe, n, args.steps, args.warmup, schedule=sched64, fc="poly")
-            rec = {k: v[k] for k in keep}
+            rec = {k: v[k] for k in keep if k in v}
             rec["workload"] = (f"the same 1024^2 FOP workload with the paper's own FC (least-squares degree-5 fit "
                                f"to 10 points per wall, quintic blend, extension {n // 4} points, extended period "
                                f"{n + n // 4}); every step restarts from the initial state (on-device copy in the "
@@ -681,7 +745,7 @@ def main() -> int:
         for oe in ("fft", "fft_window", "direct"):
             log(f"variant 2d {n} fp32 {oe}")
             v = run_2d(oe, n, args.steps, args.warmup, precision="fp32", schedule=sched32)
-            rec = {k: v[k] for k in keep}
+            rec = {k: v[k] for k in keep if k in v}
             rec["dtype"] = "f32 transforms, f64 FC/divide/state"
             rec["fp32_vs_fp64_rel_l2"] = fp32_error_2d(n, oe)
             var[f"2d_{n}_fp32_{oe}"] = rec
@@ -691,7 +755,7 @@ def main() -> int:
             for prec, ref in (("fp64", ref64), ("fp32", ref32)):
                 log(f"variant 3d {n3} {prec} {oe}")
                 v = run_3d(n3, args.steps3, 2, prec, ref, op_eval=oe)
-                rec = {k: v[k] for k in keep}
+                rec = {k: v[k] for k in keep if k in v}
                 rec["steps"] = args.steps3
                 rec["workload"] = (f"3D {n3}^3 channel, walls on y (Dirichlet velocity, Neumann pressure), "
                                    f"periodic x and z, extended {n3}x{n3 + 25}x{n3}, {args.steps3} steps "
