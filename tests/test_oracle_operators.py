@@ -173,3 +173,32 @@ def test_direct_and_fft_modes_agree_on_walled_lattice(fc_tables):
     o2 = operators.Operators(lat, fc_tables, mode="fft")
     for a, b in zip(o1.grad(f) + [o1.lap(f)], o2.grad(f) + [o2.lap(f)]):
         assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_wendland_laplacian_does_not_annihilate_constants():
+    """The sampled kernel Laplacian of Wendland C2 at h = 1.3 dx sums to
+    -0.745 / dx^2 over the lattice instead of 0, so the operator maps a
+    constant field to that multiple of it (a property of the kernel at this
+    smoothing length; the Gaussian G4 at h = 8 dx sums to nearly 0).  The
+    oracle's Laplacian of a constant (FC, corner-wrapped taps, circular
+    convolution) equals the brute-force lattice sum of the closed form
+    lap W = (alpha / h^2) (1 - q/2)^2 (12.5 q - 10), q = r / h < 2, derived by
+    hand from W = alpha (1 - q/2)^4 (2q + 1), alpha = 7 / (4 pi h^2)."""
+    import math
+    from oracle.lattice import Lattice
+    h = 1.3                                    # in units of dx
+    alpha = 7.0 / (4.0 * math.pi * h * h)
+    brute = 0.0
+    for i in range(-3, 4):
+        for j in range(-3, 4):
+            q = math.hypot(i, j) / h
+            if q < 2.0:
+                brute += alpha / (h * h) * (1.0 - q / 2.0) ** 2 * (12.5 * q - 10.0)
+    assert abs(brute - (-0.74503)) < 1e-4
+    n = 40
+    lat = Lattice(n=(n, n), walled=(False, False), dx=1.0 / n)
+    L = operators.Operators(lat, None, mode="direct").lap(np.ones((n, n)), "u")
+    assert np.allclose(L * lat.dx ** 2, brute, rtol=1e-12, atol=0)
+    g4 = Lattice(n=(48, 48), walled=(False, False), dx=1.0 / 48, h_over_dx=8.0, kernel="g4")
+    L4 = operators.Operators(g4, None, mode="fft").lap(np.ones((48, 48)), "u")
+    assert np.max(np.abs(L4)) * g4.dx ** 2 < 1e-3
