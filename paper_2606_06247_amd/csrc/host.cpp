@@ -1463,7 +1463,11 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
   return FCSPH_OK;
 }
 
-fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
+// spec non-null (2D): the right-hand side is not stored; the rows forward
+// pass forms it from the divergence's x half spectrum spec (FP64), times
+// spec_scale, rounded to FP32 when round32 (as the store of an FP32 plan).
+fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi, const void *spec = nullptr,
+                     double spec_scale = 0.0, bool round32 = false) {
   fcsph_status st = FCSPH_OK;
   for (int a = 0; a < p->nd; ++a)
     if (p->trig_kind[a] < 0)
@@ -1486,9 +1490,26 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi) {
   r.dcs = p->dcs[0];
   r.B = pick_B(r.plan, f32, p->want_B, 1, ppe_line_len(p, 0));
   r.ldsM = padded_len(ppe_line_len(p, 0), r.plan.pad);
+  PpeRowsArgs rf = r;
+  if (spec) {
+    // one line group runs both transforms: the larger thread count and line
+    rf.spec = spec;
+    rf.spec_pitch = p->H;
+    rf.xplan = p->fp32 ? p->op64[0] : p->op[0];
+    rf.xE = p->E[0];
+    rf.xH = p->H;
+    rf.in_scale = spec_scale;
+    rf.round32 = round32 ? 1 : 0;
+    rf.in_real = nullptr;
+    rf.in_float = nullptr;
+    rf.plan.TL = std::max(r.plan.TL, rf.xplan.TL);
+    const int len = std::max(ppe_line_len(p, 0), rf.xplan.M);
+    rf.B = pick_B(rf.plan, f32, p->want_B, 1, len);
+    rf.ldsM = padded_len(len, r.plan.pad);
+  }
   {
     LaunchTimer t(p->ctx, "ppe_rows_fwd");
-    if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows", st)) return st;
+    if (!chk(p, launch_ppe_rows(rf, f32, p->ctx->stream), "ppe rows", st)) return st;
   }
   // P2: columns forward, divide, inverse
   PpeColsArgs c{};
@@ -1900,8 +1921,10 @@ static fcsph_status div3_impl(fcsph_plan *p, const double *const *u, void *out, 
 
 // spectra_ready: the x forward pass of (u0, u1) into S[0], S[1] was done by
 // the pass that produced them (the fused u* epilogue of a step)
+// store = false: stop before the last pass (the x inverse into out), whose
+// input spectrum p->O[0] the caller hands to the PPE's fused row pass.
 static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, void *out, bool out_double,
-                             double scale, bool spectra_ready = false) {
+                             double scale, bool spectra_ready = false, bool store = true) {
   fcsph_status st = FCSPH_OK;
   if (p->direct) {
     DirectArgs a = direct_base(p, FCSPH_FIELD_VELOCITY);
@@ -1927,6 +1950,7 @@ static fcsph_status div_impl(fcsph_plan *p, const double *u0, const double *u1, 
   c.sym[0] = SYM_GX;
   c.sym[1] = SYM_GY;
   if (!chk(p, cols_launch(p, c, 1, "cols_div"), "div y", st)) return st;
+  if (!store) return FCSPH_OK;
   if (!chk(p, x_inv_store(p, p->O[0], nullptr, out, nullptr, out_double, scale), "div x inv", st)) return st;
   return FCSPH_OK;
 }
@@ -2233,14 +2257,17 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
   }
   if (p->d.ppe_domain == FCSPH_PPE_EXTENDED) return project_extended(p, u, p_out, wall_vel, dt_proj, fused);
   // B: b = (rho/dt) div u*, FP64 transforms in both forms
+  // (2D: the divergence stops at its x spectrum, which the PPE's row pass
+  // transforms back itself; b is never stored)
+  const bool fuse_rhs = p->nd == 2;
   {
     Fp64Passes g64(p);
-    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt_proj, fused);
+    st = div_impl(p, p->ustar[0], p->ustar[1], p->rhs, !f32, p->d.rho / dt_proj, fused, !fuse_rhs);
   }
   if (st != FCSPH_OK) return st;
   // C: PPE
   double *phi = p_out ? p_out : p->phi;
-  st = run_ppe(p, p->rhs, phi);
+  st = fuse_rhs ? run_ppe(p, nullptr, phi, p->O[0], p->d.rho / dt_proj, f32) : run_ppe(p, p->rhs, phi);
   if (st != FCSPH_OK) return st;
   // D: u = u* - dt/rho grad phi, walls reset; FP64 transforms in both forms
   // (the projection cancels the irrotational part of u*, so FP32 rounding

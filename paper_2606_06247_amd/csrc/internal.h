@@ -301,6 +301,16 @@ struct PpeRowsArgs {
   double *out;         // inverse output (physical rows)
   double scale;
   int B, ldsM;
+  // forward from an x half spectrum instead of real rows (spec non-null):
+  // rows 2l, 2l+1 of spec (pitch spec_pitch) through the packed C2R of
+  // xplan (extended length xE, xH coefficients), times in_scale, rounded to
+  // FP32 first when round32 (the values the separate C2R store would write)
+  const void *spec;
+  long spec_pitch;
+  LinePlan xplan;
+  int xE, xH;
+  double in_scale;
+  int round32;
 };
 
 struct PpeColsArgs {

@@ -838,7 +838,28 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
   // ---- line set-up: values (forward) or coefficients (inverse), extended
   const bool qw = a.kind == TRIG_QWS || a.kind == TRIG_QWC;
   const cpx<T> *qtw = static_cast<const cpx<T> *>(a.qtw);
-  if (!a.inverse) {
+  if (!a.inverse && a.spec) {
+    // the rows from their x half spectrum (the divergence's last pass fused
+    // in): packed C2R, then the values the C2R store would have written
+    // (conjugated output: row A = Re z, row B = -Im z), unknowns only
+    const cpx<T> *sp = static_cast<const cpx<T> *>(a.spec);
+    load_packed_c2r<T, true>(buf, okA ? sp + (size_t)rA * a.spec_pitch : nullptr,
+                             okB ? sp + (size_t)rB * a.spec_pitch : nullptr, a.xE, a.xH, lt, TL);
+    __syncthreads();
+    line_dft<T>(buf, a.xplan, lt, TL, false, false);
+    const int jl = a.kind == TRIG_DST1 || a.kind == TRIG_QWS ? 1 : 0;
+    const int jh = a.kind == TRIG_DST1 || a.kind == TRIG_QWC ? n - 2 : n - 1;
+    for (int j = lt; j < n; j += TL) {
+      const cpx<T> z = buf[j];
+      double va = a.in_scale * (double)z.r, vb = a.in_scale * (double)(-z.i);
+      if (a.round32) {
+        va = (double)(float)va;
+        vb = (double)(float)vb;
+      }
+      const bool in = j >= jl && j <= jh;
+      buf[j] = to_cpx<T>(okA && in ? va : 0.0, okB && in ? vb : 0.0);
+    }
+  } else if (!a.inverse) {
     if (a.kind == TRIG_DST1 || qw) {
       // unknowns only: DST1 1..n-2, QWS 1..n-1, QWC 0..n-2 (wall values are
       // zero); the extension is formed in LDS below
