@@ -1466,8 +1466,10 @@ fcsph_status run_ppe3(fcsph_plan *p, const void *rhs, double *phi) {
 // spec non-null (2D): the right-hand side is not stored; the rows forward
 // pass forms it from the divergence's x half spectrum spec (FP64), times
 // spec_scale, rounded to FP32 when round32 (as the store of an FP32 plan).
+// spec_out non-null (2D): the rows inverse pass also writes the x half spectra
+// of phi (pressure maps, FP64) to spec_out, the first pass of the projection.
 fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi, const void *spec = nullptr,
-                     double spec_scale = 0.0, bool round32 = false) {
+                     double spec_scale = 0.0, bool round32 = false, void *spec_out = nullptr) {
   fcsph_status st = FCSPH_OK;
   for (int a = 0; a < p->nd; ++a)
     if (p->trig_kind[a] < 0)
@@ -1553,6 +1555,18 @@ fcsph_status run_ppe(fcsph_plan *p, const void *rhs, double *phi, const void *sp
   r.in_float = nullptr;
   r.out = phi;
   r.scale = p->trig_kind[0] == TRIG_DFT ? 1.0 / p->n[0] : 1.0 / (2.0 * (p->n[0] - 1));
+  if (spec_out) {
+    r.spec_out = spec_out;
+    r.spec_pitch = p->H;
+    r.xplan = p->fp32 ? p->op64[0] : p->op[0];
+    r.xE = p->E[0];
+    r.xH = p->H;
+    r.xfc = walls_for(p, 0, FCSPH_FIELD_PRESSURE);
+    r.plan.TL = std::max(r.plan.TL, r.xplan.TL);
+    const int len = std::max(ppe_line_len(p, 0), r.xplan.M);
+    r.B = pick_B(r.plan, f32, p->want_B, 1, len);
+    r.ldsM = padded_len(len, r.plan.pad);
+  }
   {
     LaunchTimer t(p->ctx, "ppe_rows_inv");
     if (!chk(p, launch_ppe_rows(r, f32, p->ctx->stream), "ppe rows inverse", st)) return st;
@@ -2267,14 +2281,16 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
   if (st != FCSPH_OK) return st;
   // C: PPE
   double *phi = p_out ? p_out : p->phi;
-  st = fuse_rhs ? run_ppe(p, nullptr, phi, p->O[0], p->d.rho / dt_proj, f32) : run_ppe(p, p->rhs, phi);
+  // (2D, likewise: the rows inverse pass also writes phi's x spectra for D)
+  st = fuse_rhs ? run_ppe(p, nullptr, phi, p->O[0], p->d.rho / dt_proj, f32, p->S[0]) : run_ppe(p, p->rhs, phi);
   if (st != FCSPH_OK) return st;
   // D: u = u* - dt/rho grad phi, walls reset; FP64 transforms in both forms
   // (the projection cancels the irrotational part of u*, so FP32 rounding
   // relative to |grad phi| would dominate the result)
   Fp64Passes g64(p);
   const bool fd = p->fp32;
-  if (!chk(p, x_fwd_single(p, phi, FCSPH_FIELD_PRESSURE, p->S[0]), "step D x", st)) return st;
+  if (!fuse_rhs)
+    if (!chk(p, x_fwd_single(p, phi, FCSPH_FIELD_PRESSURE, p->S[0]), "step D x", st)) return st;
   ColsArgs cd = cols_base(p, COLS_OP, FCSPH_FIELD_PRESSURE);
   {
     const double *ph = phi;

@@ -311,6 +311,11 @@ struct PpeRowsArgs {
   int xE, xH;
   double in_scale;
   int round32;
+  // inverse, spec_out non-null: besides storing the rows, their x half
+  // spectra (FC_x with the maps xfc, packed R2C of xplan) at rows 2l, 2l+1
+  // of spec_out (pitch spec_pitch), the first pass of the projection gradient
+  void *spec_out;
+  FcWalls xfc;
 };
 
 struct PpeColsArgs {

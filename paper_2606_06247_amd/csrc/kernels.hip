@@ -980,8 +980,35 @@ __global__ void __launch_bounds__(kMaxThreads) k_ppe_rows(KArg<PpeRowsArgs, G> k
       va = (double)buf[x].r;
       vb = (double)buf[x].i;
     }
-    if (okA) a.out[(size_t)rA * n + x] = a.scale * va;
-    if (okB) a.out[(size_t)rB * n + x] = a.scale * vb;
+    const double pa = a.scale * va, pb = a.scale * vb;
+    if (okA) a.out[(size_t)rA * n + x] = pa;
+    if (okB) a.out[(size_t)rB * n + x] = pb;
+    // (each position is read and rewritten by its own thread only)
+    if (a.spec_out) buf[x] = to_cpx<T>(okA ? pa : 0.0, okB ? pb : 0.0);
+  }
+  if (!a.spec_out) return;
+  // the projection gradient's x pass fused in: FC_x of the two rows just
+  // stored (from LDS), packed R2C, half spectra of rows rA, rB
+  __syncthreads();
+  if (a.xfc.on)
+    for (int j = n + lt; j < a.xE; j += TL) {
+      const int i = fc_slot(a.xfc, n, a.xE, j);
+      const double ra = (okA && i >= 0) ? fc_cont(a.xfc, n, i, [&](int q) { return (double)buf[q].r; }) : 0.0;
+      const double rb = (okB && i >= 0) ? fc_cont(a.xfc, n, i, [&](int q) { return (double)buf[q].i; }) : 0.0;
+      buf[j] = to_cpx<T>(ra, rb);
+    }
+  __syncthreads();
+  line_dft<T>(buf, a.xplan, lt, TL, false, false);
+  if (!okA) return;
+  cpx<T> *so = static_cast<cpx<T> *>(a.spec_out);
+  cpx<T> *oa = so + (size_t)rA * a.spec_pitch;
+  cpx<T> *ob = okB ? so + (size_t)rB * a.spec_pitch : nullptr;
+  const T hf = T(0.5);
+  for (int k = lt; k < a.xH; k += TL) {
+    const cpx<T> z = buf[k];
+    const cpx<T> zc = cconj(buf[k == 0 ? 0 : a.xE - k]);
+    oa[k] = cscale(cadd(z, zc), hf);
+    if (ob) ob[k] = cscale(cmi(csub(z, zc)), hf);
   }
 }
 
