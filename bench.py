@@ -45,13 +45,17 @@ C_FC = 25
 
 
 # ------------------------------------------------------------------ bytes
-def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0, rk3: bool = False) -> dict:
+def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0, rk3: bool = False, fused_ppe: bool = True) -> dict:
     """Compulsory HBM bytes of one launch of each kernel kind of the 2D n x n
     step (every input read once, every output written once).  State arrays are
     FP64; spectra and derivative outputs are FP64 or FP32; L is the operator
     transform length of the walled axes (n + C, or the window length).  rk3:
     the u* epilogue also writes F (2 fields) and, in sub-steps 1 and 2, reads
     the previous F (2 fields): 10/3 fields more per launch on average.
+    fused_ppe (the FFT routes): the PPE's forward row pass reads the
+    divergence's x spectrum instead of the stored right-hand side, and its
+    inverse row pass also writes phi's x spectrum (the separate C2R store and
+    x forward pass are gone); the PPE passes are FP64 in both forms.
     Callers pass L = n + C, the extended period of the method: a longer
     transform that an evaluation route chooses (the smooth window length) is
     the route's own cost, not algorithmic work."""
@@ -70,9 +74,9 @@ def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0, rk3: bool = Fal
         "rows_inv_step_a": 6 * S + 4 * R + 2 * R + (0 if fp32 else 2 * S),
         "cols_div": 2 * S + S,
         "rows_inv_store": S + Rt,
-        "ppe_rows_fwd": Rt + P * ce // 2,
-        "ppe_cols_solve": P * ce,
-        "ppe_rows_inv": P * ce // 2 + R,
+        "ppe_rows_fwd": (n * H * 16 if fused_ppe else Rt) + P * 8,
+        "ppe_cols_solve": P * 16,
+        "ppe_rows_inv": P * 8 + R + (n * H * 16 if fused_ppe else 0),
         "rows_fwd": R + S,
         "cols_op_step_d": S + 2 * S,
         "rows_inv_step_d": 2 * S + 2 * R + 2 * R,
@@ -325,7 +329,8 @@ def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64
             for q in range(3):
                 plan.rk3_substep(q, u, F, dt, nu, p_out=p, force=forces[3 * c + q], wall=walls[3 * c + q])
 
-    ab = algorithmic_bytes_2d(n, precision == "fp32", n + (n // 4 if fc == "poly" else C_FC), rk3=scheme == "rk3")
+    ab = algorithmic_bytes_2d(n, precision == "fp32", n + (n // 4 if fc == "poly" else C_FC), rk3=scheme == "rk3",
+                              fused_ppe=op_eval != "direct")
     # the timed steps start at k = 0, which restarts the trajectory
     wall_s, gpu_ms, live, profile = timed(ctx, step, steps, warmup, known=ab)
     ms_per_step = 1e3 * wall_s / steps
@@ -600,8 +605,11 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
     for (n, _), pl in zip(inst, plans):
         ab = algorithmic_bytes_2d(n, precision == "fp32", n + C_FC)
         step_bytes += sum(ab[k] for k in ("rows_fwd_pair", "cols_op_step_a", "rows_inv_step_a", "cols_div",
-                                          "rows_inv_store", "ppe_rows_fwd", "ppe_cols_solve", "ppe_rows_inv",
-                                          "rows_fwd", "cols_op_step_d", "rows_inv_step_d"))
+                                          "ppe_rows_fwd", "ppe_cols_solve", "ppe_rows_inv",
+                                          "cols_op_step_d", "rows_inv_step_d"))
+        if precision == "fp32":
+            # the divergence's FP64 x pass (fused into the u* epilogue in FP64)
+            step_bytes += algorithmic_bytes_2d(n, False, n + C_FC)["rows_fwd_pair"]
         step_bytes -= 2 * n * n * 8        # no forcing arrays read
     out = {"instances": count, "points": pts, "groups": groups, "grouped_launches": launches,
            "batched_equals_plain_bitwise": bool(equal),
