@@ -945,7 +945,7 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
     p->trig_kind[a] = kind;
     const bool qw = kind == TRIG_QWS || kind == TRIG_QWC;
     p->ncoef[a] = kind == TRIG_DFT ? (a == 0 ? nn / 2 + 1 : nn) : (kind == TRIG_DCT1 ? nn : qw ? nn - 1 : nn - 2);
-    const int minTL = (a == 0) ? 64 : 64;
+    const int minTL = 64;
     // Streamed large radices (instead of Bluestein) only while every line pair
     // of the axis fits on the chip at once (1024 SIMDs at the PPE kernels' two
     // waves each): there the pass is bound by one line's serial chain, which

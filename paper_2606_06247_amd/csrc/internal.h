@@ -292,7 +292,6 @@ struct PpeRowsArgs {
   int nrows, nx;
   int ncoef;           // coefficients per row (DCT1: n, DST1: n-2, DFT: n/2+1)
   int cpitch;          // complex elements per coefficient row
-  int jlo;             // first unknown index (DST1: 1)
   const double *in_real;   // forward input (double), or null when in_float used
   const float *in_float;
   const void *qtw;     // QWS / QWC: cpx<T> exp(-i pi j / 2N), j < 2N
@@ -325,7 +324,6 @@ struct PpeColsArgs {
   long es, os;         // strides in complex elements
   int nline;           // physical points on the line axis
   int ncoef;           // modes on the line axis
-  int jlo;             // first unknown index on the line axis
   int solve;           // 1: forward, divide, inverse; 0: forward only; 2: inverse only
   const double *mu_line;   // eigenvalues along the line
   const double *mu_inner;  // eigenvalues along the inner axis
