@@ -2254,7 +2254,7 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
   r.nu = nu;
   r.dt_over_rho = dt_proj / p->d.rho;
   r.wi = wall_info(p);
-  if (3ull * r.ldsM * (f32 ? 8 : 16) > (size_t)kMaxLds)
+  if ((size_t)r.ldsM * (f32 ? 8 : 16) + 16ull * r.nx > (size_t)kMaxLds)
     return fail(p->ctx, FCSPH_E_UNSUPPORTED, "x line too long for the fused step kernel");
   // FP64 plans: the epilogue also runs the x forward pass of (u*, v*) that
   // the divergence (or the EXTENDED projection) starts with

@@ -145,9 +145,11 @@ __device__ __forceinline__ size_t spec_row(const RowsInvArgs &a, int r) {
   return ((size_t)(r / a.rpp) * a.prow + (r % a.rpp)) * (size_t)a.spec_pitch;
 }
 
-// At most 128 VGPRs (4 waves per SIMD): the fused step epilogues run 512-thread
-// workgroups, and at the compiler's own choice (137) only one of them fitted a
-// CU; capped, two do (no spills; the 1024^2 step 3 % faster).
+// At most 128 VGPRs (4 waves per SIMD): the 3D step epilogues run up to
+// 512-thread workgroups, and at the compiler's own choice (137) only one of
+// them fitted a CU; capped, two do (the 1024^2 step was 3 % faster when its
+// epilogue had that form too).  The 2D step-A epilogue runs one 256-thread
+// line group (four per CU; 52 B per lane of spill under the cap).
 template <typename T, int EPI, bool GR>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_rows_inv(KArg<RowsInvArgs, GR> ka) {
@@ -223,15 +225,92 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
       a.unew[0][ro + x] = un;
       a.unew[1][ro + x] = vn;
     }
+  } else if constexpr (EPI == EPI_STEP_A2) {
+    // One row per workgroup and one line group: the three packed lines run in
+    // turn through one LDS line, (L u, L v) first, then (Gx u, Gy u), then
+    // (Gx v, Gy v).  Two real arrays after the line carry each thread's own
+    // positions from one line to the next (L u then u*, and L v), so a
+    // workgroup holds 1.4 lines of LDS instead of three and the 1024 rows of
+    // a 1024^2 lattice are resident at once.  u* is stored only after the
+    // last line has read u and v, which keeps an in-place call correct.
+    const int row = blockIdx.x;
+    const size_t ro_s = spec_row(a, row);
+    const size_t ro = (size_t)row * a.nx;
+    double *keep_u = reinterpret_cast<double *>(smem + (size_t)a.ldsM);   // L u, then u*
+    double *keep_v = keep_u + a.nx;                                       // L v
+    constexpr int order[3] = {2, 0, 1};
+#pragma unroll 1
+    for (int s = 0; s < 3; ++s) {
+      const int q = order[s];
+      load_packed_c2r<T, true>(buf, static_cast<const cpx<T> *>(a.spec[2 * q]) + ro_s,
+                               static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + ro_s, a.E, a.H, lt, TL);
+      __syncthreads();
+      line_dft<T>(buf, a.plan, lt, TL, false, false);   // conjugated output: im = -.i
+      if (q == 2) {
+        for (int x = lt; x < a.nx; x += TL) {
+          keep_u[x] = (double)buf[x].r;
+          keep_v[x] = (double)(-buf[x].i);
+        }
+      } else if (q == 0) {
+        for (int x = lt; x < a.nx; x += TL) {
+          const double u = a.u[0][ro + x], v = a.u[1][ro + x];
+          const double gxu = buf[x].r, gyu = -buf[x].i;
+          const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
+          double us = rk_ustar(a.rk, u, u * gxu + v * gyu, a.nu, keep_u[x], fx, a.dt, ro + x, 0);
+          if (is_dirichlet_point(a.wi, x, row, 0)) us = a.wall[0] ? a.wall[0][ro + x] : 0.0;
+          keep_u[x] = us;
+        }
+      } else {
+        for (int x = lt; x < a.nx; x += TL) {
+          const double u = a.u[0][ro + x], v = a.u[1][ro + x];
+          const double gxv = buf[x].r, gyv = -buf[x].i;
+          const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
+          double vs = rk_ustar(a.rk, v, u * gxv + v * gyv, a.nu, keep_v[x], fy, a.dt, ro + x, 1);
+          if (is_dirichlet_point(a.wi, x, row, 0)) vs = a.wall[1] ? a.wall[1][ro + x] : 0.0;
+          const double us = keep_u[x];
+          a.ustar[0][ro + x] = us;
+          a.ustar[1][ro + x] = vs;
+          if constexpr (sizeof(T) == 8) {
+            // position x of the line was read above by this thread only
+            if (a.fwd_fused) buf[x] = to_cpx<T>(us, vs);
+          }
+        }
+      }
+      __syncthreads();   // the line is read before the next load overwrites it
+    }
+    if constexpr (sizeof(T) == 8) {
+      if (a.fwd_fused) {
+        // the x forward pass of (u*, v*): FC along x, packed DFT, half spectra
+        for (int j = a.nx + lt; j < a.E; j += TL) {
+          const int i = fc_slot(a.fwd_fc, a.nx, a.E, j);
+          double ra = 0.0, rb = 0.0;
+          if (a.fwd_fc.on && i >= 0) {
+            ra = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)buf[q].r; });
+            rb = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)buf[q].i; });
+          }
+          buf[j] = to_cpx<T>(ra, rb);
+        }
+        __syncthreads();
+        line_dft<T>(buf, a.plan, lt, TL, false, false);
+        cpx<T> *oa = static_cast<cpx<T> *>(a.fwd_out[0]) + (size_t)row * a.H;
+        cpx<T> *ob = static_cast<cpx<T> *>(a.fwd_out[1]) + (size_t)row * a.H;
+        const T half = T(0.5);
+        for (int k = lt; k < a.H; k += TL) {
+          const cpx<T> z = buf[k];
+          const cpx<T> zc = cconj(buf[k == 0 ? 0 : a.E - k]);
+          oa[k] = cscale(cadd(z, zc), half);
+          ob[k] = cscale(cmi(csub(z, zc)), half);
+        }
+      }
+    }
   } else {
     // One row per workgroup; NL packed lines, processed by the workgroup's
     // line groups in rounds (a group without a line in a round stays idle but
     // keeps the barriers).  Line buffers: NL consecutive slots of ldsM.
-    //  A2: 0 (Gx u, Gy u) 1 (Gx v, Gy v) 2 (L u, L v)            from spec[2q], spec[2q+1]
     //  A3: 0 (Gx u, Gy u) 1 (Gz u, Gx v) 2 (Gy v, Gz v) 3 (Gx w, Gy w) 4 (Gz w, L u) 5 (L v, L w)
     //      from spec[2q], spec[2q+1]
     //  D3: 0 (Gx p, Gy p) from spec[0], spec[1];  1 (Gz p, 0) from spec[2]
-    constexpr int NL = EPI == EPI_STEP_A2 ? 3 : EPI == EPI_STEP_A3 ? 6 : 2;
+    constexpr int NL = EPI == EPI_STEP_A3 ? 6 : 2;
     const int G = blockDim.x / TL;
     const int row = blockIdx.x;
     const size_t ro_s = spec_row(a, row);
@@ -241,7 +320,7 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
       Line<T> lb{smem + (size_t)(act ? q : 0) * a.ldsM};
       if (act) {
         const cpx<T> *sA, *sB;
-        if constexpr (EPI == EPI_STEP_A2 || EPI == EPI_STEP_A3) {
+        if constexpr (EPI == EPI_STEP_A3) {
           sA = static_cast<const cpx<T> *>(a.spec[2 * q]) + ro_s;
           sB = static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + ro_s;
         } else {
@@ -254,54 +333,7 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
       line_dft<T>(lb, a.plan, lt, TL, false, false, act);   // conjugated outputs: im = -.i
     }
     const size_t ro = (size_t)row * a.nx;
-    if constexpr (EPI == EPI_STEP_A2) {
-      const Line<T> b0{smem}, b1{smem + a.ldsM}, b2{smem + 2 * (size_t)a.ldsM};
-      for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
-        const double u = a.u[0][ro + x], v = a.u[1][ro + x];
-        const double gxu = b0[x].r, gyu = -b0[x].i, gxv = b1[x].r, gyv = -b1[x].i;
-        const double lu = b2[x].r, lv = -b2[x].i;
-        const double fx = a.f[0] ? a.f[0][ro + x] : 0.0;
-        const double fy = a.f[1] ? a.f[1][ro + x] : 0.0;
-        double us = rk_ustar(a.rk, u, u * gxu + v * gyu, a.nu, lu, fx, a.dt, ro + x, 0);
-        double vs = rk_ustar(a.rk, v, u * gxv + v * gyv, a.nu, lv, fy, a.dt, ro + x, 1);
-        if (is_dirichlet_point(a.wi, x, row, 0)) {
-          us = a.wall[0] ? a.wall[0][ro + x] : 0.0;
-          vs = a.wall[1] ? a.wall[1][ro + x] : 0.0;
-        }
-        a.ustar[0][ro + x] = us;
-        a.ustar[1][ro + x] = vs;
-        if constexpr (sizeof(T) == 8) {
-          // position x of line 0 was read above by this thread only
-          if (a.fwd_fused) b0[x] = to_cpx<T>(us, vs);
-        }
-      }
-      if constexpr (sizeof(T) == 8) {
-        if (a.fwd_fused) {
-          // the x forward pass of (u*, v*): FC along x, packed DFT, half spectra
-          __syncthreads();
-          for (int j = a.nx + threadIdx.x; j < a.E; j += blockDim.x) {
-            const int i = fc_slot(a.fwd_fc, a.nx, a.E, j);
-            double ra = 0.0, rb = 0.0;
-            if (a.fwd_fc.on && i >= 0) {
-              ra = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)b0[q].r; });
-              rb = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)b0[q].i; });
-            }
-            b0[j] = to_cpx<T>(ra, rb);
-          }
-          __syncthreads();
-          line_dft<T>(b0, a.plan, lt, TL, false, false, g == 0);
-          cpx<T> *oa = static_cast<cpx<T> *>(a.fwd_out[0]) + (size_t)row * a.H;
-          cpx<T> *ob = static_cast<cpx<T> *>(a.fwd_out[1]) + (size_t)row * a.H;
-          const T half = T(0.5);
-          for (int k = threadIdx.x; k < a.H; k += blockDim.x) {
-            const cpx<T> z = b0[k];
-            const cpx<T> zc = cconj(b0[k == 0 ? 0 : a.E - k]);
-            oa[k] = cscale(cadd(z, zc), half);
-            ob[k] = cscale(cmi(csub(z, zc)), half);
-          }
-        }
-      }
-    } else if constexpr (EPI == EPI_STEP_A3) {
+    if constexpr (EPI == EPI_STEP_A3) {
       Line<T> b[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) b[k] = Line<T>{smem + (size_t)k * a.ldsM};
@@ -1273,15 +1305,20 @@ static hipError_t rows_inv_dispatch(const RowsInvArgs &a, int epi, hipStream_t s
       lds = lds_bytes(a.B, a.ldsM, sizeof(T) == 4);
       return rows_inv_t<T, EPI_ADVECT2>(a, grid, block, lds, s);
     case EPI_STEP_A2:
+      // one line group, one line and two real arrays of the row
+      grid = dim3(a.nrows);
+      block = dim3(TL);
+      lds = lds_bytes(1, a.ldsM, sizeof(T) == 4) + 2 * (size_t)a.nx * sizeof(double);
+      if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+      return rows_inv_t<T, EPI_STEP_A2>(a, grid, block, lds, s);
     case EPI_STEP_A3:
     case EPI_STEP_D3: {
-      const int NL = epi == EPI_STEP_A2 ? 3 : epi == EPI_STEP_A3 ? 6 : 2;
+      const int NL = epi == EPI_STEP_A3 ? 6 : 2;
       const int G = std::max(1, std::min(NL, kMaxThreads / TL));
       grid = dim3(a.nrows);
       block = dim3(G * TL);
       lds = lds_bytes(NL, a.ldsM, sizeof(T) == 4);
       if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
-      if (epi == EPI_STEP_A2) return rows_inv_t<T, EPI_STEP_A2>(a, grid, block, lds, s);
       if (epi == EPI_STEP_A3) return rows_inv_t<T, EPI_STEP_A3>(a, grid, block, lds, s);
       return rows_inv_t<T, EPI_STEP_D3>(a, grid, block, lds, s);
     }
