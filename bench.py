@@ -313,6 +313,7 @@ def run_2d(op_eval: str, n: int, steps: int, warmup: int, precision: str = "fp64
     if schedule and op_eval == "fft_window":
         prob.window_len = (schedule["window_len"],) * 2
         prob.lines_per_group = schedule["lines_per_group"]
+        prob.radix_order = schedule.get("radix_order", 0)
     if fc == "poly":
         # the paper's own FC: 10 fit points, degree 5, extension n / 4
         prob.fc_kind, prob.fc_d, prob.fc_p, prob.fc_C = "poly", 10, 5, n // 4
@@ -552,7 +553,7 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
         prob = api.Problem(n=(n, n), walled=(True, True), dx=1.0 / (n - 1), vel_bc=vel,
                            prs_bc=_complement(vel), precision=precision, op_eval="fft_window",
                            window_len=(wl, wl) if wl else (), lines_per_group=sch.get("lines_per_group", 0),
-                           batched=True)
+                           radix_order=sch.get("radix_order", 0), batched=True)
         plans.append(api.Plan(ctx, prob))
         u = [synth.poly_trig_2d(n, 1000 + 2 * i), synth.poly_trig_2d(n, 1001 + 2 * i)]
         states.append([torch.from_numpy(c).cuda() for c in u])

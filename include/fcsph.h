@@ -141,6 +141,13 @@ typedef enum { FCSPH_OPS_FFT = 0, FCSPH_OPS_DIRECT = 1, FCSPH_OPS_FFT_WINDOW = 2
  *              them, and the batch calls refuse such a plan
  *              (FCSPH_E_UNSUPPORTED).  Plain calls of a batched plan give
  *              bitwise the results of its batch items.
+ *  radix_order schedule hint for the operator line transforms: 0 (default)
+ *              keeps the library's stage order (radices 8, 4, 2, then odd
+ *              ascending); k >= 1 runs each operator line plan's stages in
+ *              the ((k - 1) mod m)-th of its m distinct radix orderings,
+ *              counted in lexicographic order from the ascending one.  The
+ *              PPE transforms keep their order.  Changes speed and rounding
+ *              only; negative values are FCSPH_E_INVALID.
  */
 typedef struct {
   int ndim;
@@ -162,6 +169,7 @@ typedef struct {
   int window_len[3];
   int lines_per_group;
   int batched;
+  int radix_order;
 } fcsph_desc;
 
 typedef struct fcsph_ctx fcsph_ctx;

@@ -53,7 +53,7 @@ class Desc(ctypes.Structure):
         ("kernel", ctypes.c_int), ("h_over_dx", ctypes.c_double), ("prec", ctypes.c_int),
         ("ppe_domain", ctypes.c_int), ("eig", ctypes.c_int), ("rho", ctypes.c_double),
         ("op_eval", ctypes.c_int), ("window_len", ctypes.c_int * 3), ("lines_per_group", ctypes.c_int),
-        ("batched", ctypes.c_int),
+        ("batched", ctypes.c_int), ("radix_order", ctypes.c_int),
     ]
 
 
@@ -151,6 +151,7 @@ class Problem:
     window_len: tuple = ()        # schedule hint per axis (0 = library choice)
     lines_per_group: int = 0      # schedule hint (0 = library choice)
     batched: bool = False         # plan also runs in batches (no streamed PPE radices)
+    radix_order: int = 0          # schedule hint: operator stage order (0 = library order)
 
     @property
     def ndim(self):
@@ -250,6 +251,7 @@ def make_desc(prob: "Problem"):
         d.window_len[a] = int(L)
     d.lines_per_group = int(prob.lines_per_group)
     d.batched = 1 if prob.batched else 0
+    d.radix_order = int(prob.radix_order)
     return d, mdir, mneu
 
 

@@ -41,8 +41,11 @@ hipEvent_t pool_event(fcsph_ctx *c) {
     c->event_pool.pop_back();
     return e;
   }
+  // timing only (read after the caller's synchronisation): no system-scope
+  // fence at record time, so an event between two kernels neither writes
+  // back nor invalidates the caches the next kernel reads
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -228,7 +231,7 @@ struct LineSpec {
 // Build a line plan for length n.  min_TL forces a minimum thread count per
 // line (used where the kernel keeps E / TL spectrum values in registers).
 bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> &up, LinePlan &p,
-                    bool big = false, bool wide = false) {
+                    bool big = false, bool wide = false, int order = 0) {
   std::memset(&p, 0, sizeof(p));
   p.n = n;
   std::vector<int> rad;
@@ -246,6 +249,15 @@ bool make_line_plan(int n, bool fp32, int min_TL, Bump &ws, std::vector<Upload> 
     for (M = 2 * n - 1; M <= 8 * n; ++M)
       if (smooth7(M) && factor_direct(M, rad) && (tl = line_threads(M, rad, min_TL, wide)) > 0) break;
     if (tl <= 0 || tl > kMaxThreads) return false;
+  }
+  // schedule hint: the ((order - 1) mod m)-th distinct ordering of the radices
+  // (lexicographic from the ascending one); the twiddle table serves any order
+  if (order > 0 && !big && rad.size() > 1) {
+    std::sort(rad.begin(), rad.end());
+    int m = 0;
+    std::vector<int> r = rad;
+    do ++m; while (std::next_permutation(r.begin(), r.end()));
+    for (int k = (order - 1) % m; k > 0; --k) std::next_permutation(rad.begin(), rad.end());
   }
   p.M = M;
   p.wide = wide ? 1 : 0;
@@ -709,6 +721,7 @@ fcsph_status validate(const fcsph_desc *d, std::string &msg) {
   }
   if (!(d->rho > 0.0)) { msg = "rho must be positive"; return FCSPH_E_INVALID; }
   if (d->lines_per_group < 0 || d->lines_per_group > 16) { msg = "lines_per_group must be in 0..16"; return FCSPH_E_INVALID; }
+  if (d->radix_order < 0) { msg = "radix_order must be >= 0"; return FCSPH_E_INVALID; }
   if (d->batched != 0 && d->batched != 1) { msg = "batched must be 0 or 1"; return FCSPH_E_INVALID; }
   bool any_wall = false;
   for (int a = 0; a < d->ndim; ++a) {
@@ -798,8 +811,8 @@ fcsph_status layout(fcsph_plan *p, const fcsph_desc *d, Bump &ws, std::vector<Up
   // operator line plans
   for (int a = 0; a < p->nd; ++a) {
     const int minTL = 64;
-    if (!make_line_plan(p->E[a], f32, minTL, ws, up, p->op[a]) ||
-        (f32 && !make_line_plan(p->E[a], false, minTL, ws, up, p->op64[a]))) {
+    if (!make_line_plan(p->E[a], f32, minTL, ws, up, p->op[a], false, false, d->radix_order) ||
+        (f32 && !make_line_plan(p->E[a], false, minTL, ws, up, p->op64[a], false, false, d->radix_order))) {
       msg = "cannot plan a DFT of length " + std::to_string(p->E[a]);
       return FCSPH_E_UNSUPPORTED;
     }

@@ -1,15 +1,18 @@
 """Schedule autotuner: picks the transform length of the windowed operator
-evaluation and the number of lines per workgroup of the line kernels for one
-lattice shape by timing whole projection steps on the device.
+evaluation, the number of lines per workgroup of the line kernels and the
+stage order of the operator transforms' radices for one lattice shape by
+timing whole projection steps on the device.
 
-The candidates only change speed: every schedule computes the same
-convolutions and PPE (the window length is any smooth L >= n + 2R, the lines
-per workgroup only regroup independent lines), so the tuner is free to pick
+The candidates only change speed and rounding: every schedule computes the
+same convolutions and PPE (the window length is any smooth L >= n + 2R, the
+lines per workgroup only regroup independent lines, a radix order only
+reorders the Stockham stages of the same DFT), so the tuner is free to pick
 the fastest.  Results are cached per (shape, precision) in memory and, when a
 path is given, in a JSON file.
 """
 from __future__ import annotations
 
+import itertools
 import json
 import math
 import os
@@ -61,12 +64,33 @@ def window_candidates(n: int, reach: int = 2, count: int = 5, span: float = 1.35
     return [L for _, L in scored[:count]]
 
 
-def _problem_2d(n, precision, window_len=0, lines=0):
+def radix_order_candidates(L: int) -> list:
+    """radix_order values worth timing for window length L: the library's own
+    order (0), ascending, descending, the library order reversed and rotated
+    by one stage either way, each distinct ordering once.  radix_order k >= 1
+    names the (k - 1)-th distinct ordering in lexicographic order from the
+    ascending one (the library counts the same way)."""
+    rad = _factor(L)
+    if rad is None or len(rad) < 2:
+        return [0]
+    distinct = sorted(set(itertools.permutations(sorted(rad))))
+    want = [tuple(rad), distinct[0], distinct[-1], tuple(reversed(rad)),
+            tuple(rad[1:] + rad[:1]), tuple(rad[-1:] + rad[:-1])]
+    out, seen = [], set()
+    for i, t in enumerate(want):
+        if t in seen:
+            continue
+        seen.add(t)
+        out.append(0 if i == 0 else distinct.index(t) + 1)
+    return out
+
+
+def _problem_2d(n, precision, window_len=0, lines=0, radix_order=0):
     dx = 1.0 / (n - 1)
     wl = (window_len, window_len) if window_len else ()
     return api.Problem(n=(n, n), walled=(True, True), dx=dx, vel_bc=(("D", "D"), ("D", "D")),
                        prs_bc=(("N", "N"), ("N", "N")), precision=precision, op_eval="fft_window",
-                       window_len=wl, lines_per_group=lines)
+                       window_len=wl, lines_per_group=lines, radix_order=radix_order)
 
 
 def time_step(ctx, prob, steps: int = 8, warmup: int = 2) -> float:
@@ -97,7 +121,9 @@ _CACHE: dict = {}
 
 def tune_2d(ctx, n: int, precision: str = "fp64", lines=(1, 2, 4, 8), cache_path: str | None = None,
             log=None) -> dict:
-    """Best (window_len, lines_per_group) for the 2D n x n walled lattice."""
+    """Best (window_len, lines_per_group, radix_order) for the 2D n x n walled
+    lattice: window lengths x lines per workgroup first, then the radix
+    orders of the best window length."""
     key = f"2d:{n}:{precision}"
     if key in _CACHE:
         return _CACHE[key]
@@ -118,11 +144,22 @@ def tune_2d(ctx, n: int, precision: str = "fp64", lines=(1, 2, 4, 8), cache_path
             trials.append((L, b, ms))
             if best is None or ms < best[2]:
                 best = (L, b, ms)
+    order = 0
+    if best is not None:
+        for k in radix_order_candidates(best[0])[1:]:
+            try:
+                ms = time_step(ctx, _problem_2d(n, precision, best[0], best[1], k))
+            except api.FcsphError:
+                continue
+            trials.append((best[0], best[1], ms))
+            if ms < best[2]:
+                best = (best[0], best[1], ms)
+                order = k
     default_ms = time_step(ctx, _problem_2d(n, precision))
     if best is None:
         # no candidate could be planned: the library's own choice (0 = default)
         best = (0, 0, default_ms)
-    rec = {"window_len": best[0], "lines_per_group": best[1], "ms": round(best[2], 4),
+    rec = {"window_len": best[0], "lines_per_group": best[1], "radix_order": order, "ms": round(best[2], 4),
            "default_ms": round(default_ms, 4), "trials": len(trials)}
     if log:
         log(f"tuned {key}: {rec}")

@@ -72,6 +72,10 @@ def test_workspace_query_and_validation():
     for v in (0, 1):
         assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(batched=v)), ctypes.byref(nb)) == api.OK
     assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(batched=2)), ctypes.byref(nb)) == api.E_INVALID
+    # radix_order: any k >= 0 plans (taken modulo the number of orderings)
+    for v in (0, 1, 7, 1000):
+        assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(radix_order=v)), ctypes.byref(nb)) == api.OK
+    assert L.fcsph_plan_workspace_bytes(ctypes.byref(desc(radix_order=-1)), ctypes.byref(nb)) == api.E_INVALID
     # 3D: walls on y only; the direct evaluation is 2D only
     d3 = desc(ndim=3)
     d3.n[2] = 32

@@ -176,17 +176,21 @@ def test_batch_rejects_repeated_plan(ctx):
 
 
 def test_batch_tuned_schedules_bitwise(ctx):
-    """Larger lattices, random walls, explicit window lengths and one line per
-    workgroup (the schedules the tuner picks): batched == plain bitwise."""
+    """Larger lattices, random walls, explicit window lengths, lines per
+    workgroup and radix orders (the schedules the tuner picks; two items of
+    one shape with different radix orders share a grouped launch):
+    batched == plain bitwise."""
     import torch
     from paper_2606_06247_amd import api
     rng = np.random.default_rng(31)
     plans, plain, batched, walls = [], [], [], []
-    for i, (n, L, lines) in enumerate([(192, 200, 1), (192, 200, 1), (256, 270, 2), (384, 392, 1), (256, 0, 0)]):
+    for i, (n, L, lines, order) in enumerate([(192, 200, 1, 0), (192, 200, 1, 2), (256, 270, 2, 0),
+                                              (384, 392, 1, 3), (256, 0, 0, 0)]):
         s = spec((n, n), (True, True), vel=random_walls(rng))
         prob = problem(s, op_eval="fft_window")
         prob.window_len = (L, L) if L else ()
         prob.lines_per_group = lines
+        prob.radix_order = order
         plans.append(api.Plan(ctx, prob))
         u = make_inputs(s, 500 + 2 * i)
         plain.append([to_dev(c) for c in u])

@@ -191,6 +191,48 @@ def test_project_step_random_inputs(ctx, fc_tables, s, op_eval):
     check(f"random step p {op_eval}", to_np(pd), ref_p, TOL)
 
 
+@pytest.mark.parametrize("op_eval", ["fft_window", "fft"])
+def test_project_step_radix_orders(ctx, fc_tables, op_eval):
+    """The radix_order schedule hint reorders the operator transforms' Stockham
+    stages (the tuner's third knob): every ordering, including indices past
+    the number of orderings (taken modulo), keeps parity with the oracle on
+    random inputs, and the orders differ from each other only by rounding.
+    The whole-period route's transforms are Bluestein, whose work length is
+    reordered the same way."""
+    import torch
+    from paper_2606_06247_amd import api
+    s = RANDOM_STEP_CASES[1]
+    lat = lattice(s)
+    shape = tuple(reversed(s["n"]))
+    u = [synth.random_field(shape, 70), synth.random_field(shape, 71)]
+    f = [synth.random_field(shape, 72), synth.random_field(shape, 73)]
+    w = [synth.random_field(shape, 74), synth.random_field(shape, 75)]
+    dt, nu = 1e-4, 1e-3
+    ref_u, ref_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
+    fft_u, fft_p = (step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+                    if op_eval == "fft" else ([None] * 2, None))
+    gates = [gate(op_eval, ref_u[0], fft_u[0]), gate(op_eval, ref_u[1], fft_u[1]), gate(op_eval, ref_p, fft_p)]
+    outs = {}
+    for k in (0, 1, 2, 3, 5, 1000):
+        prob = problem(s, op_eval=op_eval)
+        prob.radix_order = k
+        plan = api.Plan(ctx, prob)
+        ud = [to_dev(c) for c in u]
+        pd = torch.empty_like(ud[0])
+        plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
+        got = [to_np(ud[0]), to_np(ud[1]), to_np(pd)]
+        for a in range(2):
+            check(f"radix order {k} u{a} {op_eval}", got[a], ref_u[a], gates[a])
+        check(f"radix order {k} p {op_eval}", got[2], ref_p, gates[2])
+        outs[k] = got
+    # two roundings of one result: within the parity gate of each other (the
+    # whole period rounds relative to its continuation, the window does not)
+    for k in outs:
+        for a in range(3):
+            d = rel_l2(outs[k][a], outs[0][a])
+            assert d < (1e-12 if op_eval == "fft_window" else gates[a]), (k, a, d)
+
+
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window", "direct"])
 def test_decaying_flow_1024_one_step(ctx, fc_tables, op_eval):
     """The 1024^2 workload in the launch configuration the bench times: one
