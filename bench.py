@@ -518,6 +518,7 @@ def run_3d(n: int, steps: int, warmup: int, precision: str, ref_states=None, op_
 
 # ------------------------------------------------------------------ batched workload
 BATCH_SIZES = (64, 96, 128, 192, 256, 384, 512)
+TUNE_BATCH = 8        # lattices per timed batch when tuning a size class for the batched form
 
 
 def batch_instances(count: int, seed: int = 30) -> list:
@@ -774,18 +775,23 @@ def main() -> int:
                 f"step{k}": {name: float(f"{rel_l2(a, b):.3e}") for name, a, b in
                              zip(("u", "v", "w", "p"), ref32[k], ref64[k])} for k in sorted(ref64)}
             del ref64, ref32
-        # batched solves (512 independent 2D lattices), schedules from the autotuner
+        # batched solves (512 independent 2D lattices), schedules from the
+        # autotuner timing graph-replayed batches of each size class
         tctx = _api.Context(0)
         for prec in ("fp64", "fp32"):
             sched = {}
             for nb in BATCH_SIZES:
                 if not args.no_tune:
-                    log(f"tuning {nb} {prec}")
-                    sched[nb] = tune.tune_2d(tctx, nb, prec, lines=(1, 2, 4))
+                    log(f"tuning {nb} {prec} (batches of {TUNE_BATCH})")
+                    sched[nb] = tune.tune_2d(tctx, nb, prec, lines=(1, 2), batch=TUNE_BATCH)
             log(f"batch {args.batch} {prec}")
             rec, first = run_batch(args.batch, prec, 5, sched, ref_u=ref_batch if prec == "fp32" else None)
             if prec == "fp64":
                 ref_batch = first
+            if sched:
+                # the same batch on the library's default schedules
+                dflt, _ = run_batch(args.batch, prec, 5, {})
+                rec["solves_per_s_default_schedules"] = dflt["solves_per_s"]
             rec["schedules"] = {str(k): v for k, v in sched.items()}
             rec["workload"] = (f"{args.batch} independent 2D lattices, n ~ U{{64..512}} (seed 30), each wall "
                                "Dirichlet or Neumann velocity (complementary pressure), manufactured fields, "

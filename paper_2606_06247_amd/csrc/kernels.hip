@@ -149,7 +149,7 @@ __device__ __forceinline__ size_t spec_row(const RowsInvArgs &a, int r) {
 // 512-thread workgroups, and at the compiler's own choice (137) only one of
 // them fitted a CU; capped, two do (the 1024^2 step was 3 % faster when its
 // epilogue had that form too).  The 2D step-A epilogue runs one 256-thread
-// line group (four per CU; 52 B per lane of spill under the cap).
+// line group (four per CU, 113 VGPRs).
 template <typename T, int EPI, bool GR>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_rows_inv(KArg<RowsInvArgs, GR> ka) {
@@ -239,9 +239,16 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
     double *keep_u = reinterpret_cast<double *>(smem + (size_t)a.ldsM);   // L u, then u*
     double *keep_v = keep_u + a.nx;                                       // L v
     constexpr int order[3] = {2, 0, 1};
+    const int lt0 = lt;
 #pragma unroll 1
     for (int s = 0; s < 3; ++s) {
       const int q = order[s];
+      // a fresh copy of the lane index per line keeps the compiler from
+      // hoisting the transform's lane-dependent LDS offsets out of this loop,
+      // whose live ranges across the transforms spilled 52 B per lane to
+      // scratch (13.6 MB of scratch writes per 1024^2 launch)
+      int lt = lt0;
+      asm volatile("" : "+v"(lt));
       load_packed_c2r<T, true>(buf, static_cast<const cpx<T> *>(a.spec[2 * q]) + ro_s,
                                static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + ro_s, a.E, a.H, lt, TL);
       __syncthreads();

@@ -116,15 +116,54 @@ def time_step(ctx, prob, steps: int = 8, warmup: int = 2) -> float:
     return times[len(times) // 2]
 
 
+def time_batch(ctx, probs, reps: int = 6) -> float:
+    """Milliseconds of one graph-replayed batch step of the problems `probs`
+    (one FOP step each, synthetic state): the batched form's throughput
+    objective."""
+    import torch
+    plans = [api.Plan(ctx, pr) for pr in probs]
+    g = torch.Generator(device="cpu").manual_seed(0)
+    b = api.Batch(ctx, len(plans))
+    keep = []
+    for pl, pr in zip(plans, probs):
+        u = [torch.randn(pr.shape, generator=g, dtype=torch.float64).cuda() * 1e-3 for _ in range(pr.ndim)]
+        p = torch.empty_like(u[0])
+        b.add_step(pl, u, 1e-6, 1e-3, p_out=p)
+        keep.append((u, p))
+    b.launch()
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.replay()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del b
+    return ms
+
+
 _CACHE: dict = {}
 
 
 def tune_2d(ctx, n: int, precision: str = "fp64", lines=(1, 2, 4, 8), cache_path: str | None = None,
-            log=None) -> dict:
+            log=None, batch: int = 0) -> dict:
     """Best (window_len, lines_per_group, radix_order) for the 2D n x n walled
     lattice: window lengths x lines per workgroup first, then the radix
-    orders of the best window length."""
-    key = f"2d:{n}:{precision}"
+    orders of the best window length.  batch = 0 times single steps (the
+    latency of one problem); batch = m > 0 times graph-replayed batches of m
+    such lattices (batched plans), the objective of the batched form."""
+    key = f"2d:{n}:{precision}" + (f":batch{batch}" if batch else "")
+
+    def measure(L=0, b=0, k=0):
+        if batch:
+            pr = _problem_2d(n, precision, L, b, k)
+            pr.batched = True
+            return time_batch(ctx, [pr] * batch)
+        return time_step(ctx, _problem_2d(n, precision, L, b, k))
+
     if key in _CACHE:
         return _CACHE[key]
     if cache_path and os.path.exists(cache_path):
@@ -138,27 +177,33 @@ def tune_2d(ctx, n: int, precision: str = "fp64", lines=(1, 2, 4, 8), cache_path
     for L in window_candidates(n):
         for b in lines:
             try:
-                ms = time_step(ctx, _problem_2d(n, precision, L, b))
+                ms = measure(L, b)
             except api.FcsphError:
                 continue               # a schedule the library cannot plan
             trials.append((L, b, ms))
             if best is None or ms < best[2]:
                 best = (L, b, ms)
+    # radix orders move a step by about 1 % (the run-to-run spread of these
+    # timings), so an order replaces the library's only when it is faster by
+    # more than that
     order = 0
     if best is not None:
+        base = best[2]
         for k in radix_order_candidates(best[0])[1:]:
             try:
-                ms = time_step(ctx, _problem_2d(n, precision, best[0], best[1], k))
+                ms = measure(best[0], best[1], k)
             except api.FcsphError:
                 continue
             trials.append((best[0], best[1], ms))
-            if ms < best[2]:
+            if ms < 0.99 * base and ms < best[2]:
                 best = (best[0], best[1], ms)
                 order = k
-    default_ms = time_step(ctx, _problem_2d(n, precision))
-    if best is None:
-        # no candidate could be planned: the library's own choice (0 = default)
+    default_ms = measure()
+    if best is None or default_ms < best[2]:
+        # no candidate could be planned, or none beat the library's own
+        # choice in its own timing: keep the library's (0 = default)
         best = (0, 0, default_ms)
+        order = 0
     rec = {"window_len": best[0], "lines_per_group": best[1], "radix_order": order, "ms": round(best[2], 4),
            "default_ms": round(default_ms, 4), "trials": len(trials)}
     if log:
