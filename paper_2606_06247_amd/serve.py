@@ -8,8 +8,12 @@ new one fits in the budget) and its buffers fit.  Admitted requests are packed
 into a batch (grouped launches, `api.Batch`) on one of several lanes (each
 lane: its own context stream and batch object), so requests that arrive while
 other batches run are issued as soon as a lane is free and their work
-overlaps on the device with the batches already in flight.  Completion is
-observed by polling an event per batch; latency = completion - arrival.
+overlaps on the device with the batches already in flight.  Each plan
+instance is bound to one lane's context: a request that is alone on its
+plan's own lane runs as the plain call on that lane's stream (no grouping,
+argument upload or stream fork / join), any other work as a batch.
+Completion is observed by polling an event per launch (every poll_s seconds
+while idle); latency = completion - arrival.
 
 Every result equals the plain call on the same plan bitwise (the batch
 launches the same kernels on the same data), so a request gives the same
@@ -92,10 +96,13 @@ def problem_for(dims: int, n: int, precision: str, op_eval: str = "fft_window") 
 class Server:
     def __init__(self, precision: str = "fp64", hbm_budget: float = 200e9, max_batch: int = 16,
                  lanes: int = 4, op_eval: str = "fft_window", dt: float = 1e-4, nu: float = 1e-3,
-                 max_batch_3d: int = 2, check_finite: bool = False):
+                 max_batch_3d: int = 2, check_finite: bool = False, poll_s: float = 2e-5):
         import torch
         self.precision, self.op_eval = precision, op_eval
         self.check_finite = check_finite
+        # idle wait of the loop between polls (arrivals, completions): it adds
+        # about half of itself (plus the OS wake-up) to a lone request's latency
+        self.poll_s = poll_s
         self.cancelled: set = set()
         self.budget = hbm_budget
         self.max_batch = max_batch
@@ -110,7 +117,6 @@ class Server:
         self.used = 0.0                         # bytes: plan workspaces + request buffers in flight
         self.resident = 0.0                     # bytes: plan workspaces (resident until the server ends)
         self.templates: dict = {}
-        self.plan_ctx = api.Context(0)
         self.stats = {"plans_created": 0, "admitted": 0, "max_queue": 0, "batches": 0}
 
     # ---- resident state
@@ -128,9 +134,13 @@ class Server:
             self.templates[k] = [torch.from_numpy(c).cuda() for c in f]
         return self.templates[k]
 
-    def _new_plan(self, dims, n):
-        plan = api.Plan(self.plan_ctx, problem_for(dims, n, self.precision, self.op_eval))
-        self.plan_ctx.sync()           # tables resident before any lane stream uses the plan
+    def _new_plan(self, dims, n, lane: int = 0):
+        # bound to a lane's context: a lone request on that lane runs as the
+        # plain call on the lane's stream; in batches any lane can run it
+        ctx = self.ctxs[lane % len(self.ctxs)]
+        plan = api.Plan(ctx, problem_for(dims, n, self.precision, self.op_eval))
+        plan.lane = lane % len(self.ctxs)
+        ctx.sync()                     # tables resident before any lane stream uses the plan
         self.used += plan.workspace.numel()
         self.resident += plan.workspace.numel()
         self.stats["plans_created"] += 1
@@ -140,8 +150,8 @@ class Server:
         """Create the resident plans (one per lane) and the input template per shape."""
         for dims, n in shapes:
             self._template(dims, n)
-            for _ in range(len(self.streams)):
-                self.pool.setdefault((dims, n), []).append(self._new_plan(dims, n))
+            for lane in range(len(self.streams)):
+                self.pool.setdefault((dims, n), []).append(self._new_plan(dims, n, lane))
             self.count[(dims, n)] = len(self.streams)
 
     def _request_bytes(self, r: Request) -> int:
@@ -162,12 +172,16 @@ class Server:
         ws = api.workspace_bytes(problem_for(r.dims, r.n, self.precision, self.op_eval))
         return ws + need > room
 
-    def _acquire(self, r: Request):
+    def _acquire(self, r: Request, lane: int = 0):
         idle = self.pool.setdefault(self._key(r), [])
         need = self._request_bytes(r)
         if idle:
             if self.used + need > self.budget:
                 return None
+            # an instance bound to this lane when one is idle
+            for i in range(len(idle) - 1, -1, -1):
+                if getattr(idle[i], "lane", -1) == lane:
+                    return idle.pop(i)
             return idle.pop()
         # a new instance only while a shape has fewer than one per lane
         # (otherwise the request waits for an instance to return)
@@ -177,7 +191,7 @@ class Server:
         if self.used + ws + need > self.budget:
             return None
         self.count[self._key(r)] = self.count.get(self._key(r), 0) + 1
-        return self._new_plan(r.dims, r.n)
+        return self._new_plan(r.dims, r.n, lane)
 
     def _inputs(self, r: Request):
         import torch
@@ -220,14 +234,25 @@ class Server:
         return done
 
     def _launch(self, lane: int, work):
-        b = self.batches[lane]
-        b.clear()
-        for r, plan, bufs in work:
+        if len(work) == 1 and getattr(work[0][1], "lane", -1) == lane:
+            # a lone request on its plan's own lane: the plain call (the same
+            # kernels and bitwise the same result as a batch of one, without
+            # the grouping, argument upload and stream fork / join)
+            r, plan, bufs = work[0]
             if r.kind == "step":
-                b.add_step(plan, bufs["u"], self.dt, self.nu, p_out=bufs["p"], wall=bufs["wall"])
+                plan.project_step(bufs["u"], self.dt, self.nu, p_out=bufs["p"], wall=bufs["wall"])
             else:
-                b.add_ppe(plan, bufs["rhs"], bufs["phi"])
-        b.launch()
+                plan.ppe_solve(bufs["rhs"], bufs["phi"])
+            self.stats["plain_launches"] = self.stats.get("plain_launches", 0) + 1
+        else:
+            b = self.batches[lane]
+            b.clear()
+            for r, plan, bufs in work:
+                if r.kind == "step":
+                    b.add_step(plan, bufs["u"], self.dt, self.nu, p_out=bufs["p"], wall=bufs["wall"])
+                else:
+                    b.add_ppe(plan, bufs["rhs"], bufs["phi"])
+            b.launch()
         ev = self.streams[lane].record_event()
         self.inflight[lane] = (ev, work)
         self.stats["batches"] += 1
@@ -287,7 +312,7 @@ class Server:
                         if r.dims != cls:
                             skipped.append(r)
                             continue
-                        plan = self._acquire(r)
+                        plan = self._acquire(r, lane)
                         if plan is None:
                             skipped.append(r)
                             continue
@@ -299,7 +324,7 @@ class Server:
                     self._launch(lane, work)
                     continue
             if not free or not queue:
-                time.sleep(0.0002)
+                time.sleep(self.poll_s)
         wall = now()
         ok = [r for r in requests if r.status == "ok"]
         lat = np.array([r.t_done - r.t_arrival for r in ok]) if ok else np.array([math.nan])
@@ -330,7 +355,7 @@ def run_plain(requests: list, srv: Server, realtime: bool = True) -> dict:
     for r in pending:
         if realtime:
             while time.perf_counter() - t0 < r.t_arrival:
-                time.sleep(0.0002)
+                time.sleep(srv.poll_s)
         plan = srv._acquire(r)
         bufs = srv._inputs(r)
         if r.kind == "step":
