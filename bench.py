@@ -63,23 +63,25 @@ def algorithmic_bytes_2d(n: int, fp32: bool = False, L: int = 0, rk3: bool = Fal
     H = (L or n + C_FC) // 2 + 1
     ce = 8 if fp32 else 16
     te = 4 if fp32 else 8
-    S = n * H * ce                 # one x half-spectrum array
+    S = n * H * ce                 # one x half-spectrum array (the form's precision)
+    S64 = n * H * 16               # one FP64 x half-spectrum array
     R = P * 8                      # one real FP64 field
     Rt = P * te                    # one derivative / rhs field
     out = {
         "rows_fwd_pair": 2 * R + 2 * S,
         "cols_op_step_a": 2 * S + 6 * S,
-        # FP64: the epilogue also writes the x spectra of (u*, v*) (the fused
+        # the epilogue also writes the FP64 x spectra of (u*, v*) (the fused
         # first pass of the divergence; the separate rows forward goes away)
-        "rows_inv_step_a": 6 * S + 4 * R + 2 * R + (0 if fp32 else 2 * S),
-        "cols_div": 2 * S + S,
+        "rows_inv_step_a": 6 * S + 4 * R + 2 * R + 2 * S64,
+        # the divergence, the PPE and stage D run FP64 transforms in both forms
+        "cols_div": 2 * S64 + S64,
         "rows_inv_store": S + Rt,
         "ppe_rows_fwd": (n * H * 16 if fused_ppe else Rt) + P * 8,
         "ppe_cols_solve": P * 16,
         "ppe_rows_inv": P * 8 + R + (n * H * 16 if fused_ppe else 0),
         "rows_fwd": R + S,
-        "cols_op_step_d": S + 2 * S,
-        "rows_inv_step_d": 2 * S + 2 * R + 2 * R,
+        "cols_op_step_d": S64 + 2 * S64,
+        "rows_inv_step_d": 2 * S64 + 2 * R + 2 * R,
         "direct_step_a": 6 * R,
         "direct_div": 2 * R + Rt,
         "direct_step_d": 5 * R,
@@ -609,9 +611,6 @@ def run_batch(count: int, precision: str, reps: int, schedules: dict, ref_u=None
         step_bytes += sum(ab[k] for k in ("rows_fwd_pair", "cols_op_step_a", "rows_inv_step_a", "cols_div",
                                           "ppe_rows_fwd", "ppe_cols_solve", "ppe_rows_inv",
                                           "cols_op_step_d", "rows_inv_step_d"))
-        if precision == "fp32":
-            # the divergence's FP64 x pass (fused into the u* epilogue in FP64)
-            step_bytes += algorithmic_bytes_2d(n, False, n + C_FC)["rows_fwd_pair"]
         step_bytes -= 2 * n * n * 8        # no forcing arrays read
     out = {"instances": count, "points": pts, "groups": groups, "grouped_launches": launches,
            "batched_equals_plain_bitwise": bool(equal),

@@ -2267,17 +2267,17 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
   r.nu = nu;
   r.dt_over_rho = dt_proj / p->d.rho;
   r.wi = wall_info(p);
-  if ((size_t)r.ldsM * (f32 ? 8 : 16) + 16ull * r.nx > (size_t)kMaxLds)
+  if ((size_t)r.ldsM * 16 + 16ull * r.nx > (size_t)kMaxLds)
     return fail(p->ctx, FCSPH_E_UNSUPPORTED, "x line too long for the fused step kernel");
-  // FP64 plans: the epilogue also runs the x forward pass of (u*, v*) that
-  // the divergence (or the EXTENDED projection) starts with
-  const bool fused = !f32;
-  if (fused) {
-    r.fwd_fused = 1;
-    r.fwd_fc = walls_for(p, 0, FCSPH_FIELD_VELOCITY);
-    r.fwd_out[0] = p->S[0];
-    r.fwd_out[1] = p->S[1];
-  }
+  // the epilogue also runs the FP64 x forward pass of (u*, v*) that the
+  // divergence (or the EXTENDED projection) starts with (FP32 plans: with
+  // the FP64 plan of the same length)
+  const bool fused = true;
+  r.fwd_fused = 1;
+  r.fwd_fc = walls_for(p, 0, FCSPH_FIELD_VELOCITY);
+  r.fwd_out[0] = p->S[0];
+  r.fwd_out[1] = p->S[1];
+  r.plan64 = f32 ? p->op64[0] : p->op[0];
   {
     LaunchTimer t(p->ctx, "rows_inv_step_a");
     if (!chk(p, launch_rows_inv(r, EPI_STEP_A2, f32, s), "step A x inv", st)) return st;

@@ -202,14 +202,16 @@ struct RowsInvArgs {
   // EPI_STEP_D2 / D3: 1 = the transformed values are the new velocity
   // (EXTENDED projection, no u* read), 0 = u* - (dt/rho) times them
   int assign;
-  // EPI_STEP_A2 (T = double): 1 = the row's u* and v* also go through the x
-  // forward pass of the divergence that follows (FC along x with fwd_fc, the
-  // packed real-to-complex DFT of the same plan) into the half-spectrum rows
-  // fwd_out[0], fwd_out[1] (row pitch H), as a separate rows-forward launch
-  // would write them
+  // EPI_STEP_A2: 1 = the row's u* and v* also go through the FP64 x forward
+  // pass of the divergence that follows (FC along x with fwd_fc, the packed
+  // real-to-complex DFT with plan64, the FP64 plan of the same length: plan
+  // itself in FP64 kernels) into the FP64 half-spectrum rows fwd_out[0],
+  // fwd_out[1] (row pitch H), as a separate FP64 rows-forward launch would
+  // write them
   int fwd_fused;
   FcWalls fwd_fc;
   void *fwd_out[2];
+  LinePlan plan64;
   // EPI_ADVECT2: F = adv_c[0] Gx u + adv_c[1] Gy u, u <- u - dt (g F + z F_prev)
   // (rk.g, rk.z, rk.F[0]: F_prev in, F out), u[0] read and unew[0] written;
   // wall points flagged in wi.dir take wall[0]

@@ -236,8 +236,10 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
     const int row = blockIdx.x;
     const size_t ro_s = spec_row(a, row);
     const size_t ro = (size_t)row * a.nx;
-    double *keep_u = reinterpret_cast<double *>(smem + (size_t)a.ldsM);   // L u, then u*
-    double *keep_v = keep_u + a.nx;                                       // L v
+    // the arrays start after one FP64 line, which the fused FP64 forward pass
+    // of an FP32 kernel lays over its own (then finished) line
+    double *keep_u = reinterpret_cast<double *>(smem_raw + (size_t)a.ldsM * sizeof(cpx<double>));   // L u, then u*
+    double *keep_v = keep_u + a.nx;   // L v, then v* (FP32 kernels)
     constexpr int order[3] = {2, 0, 1};
     const int lt0 = lt;
 #pragma unroll 1
@@ -280,34 +282,42 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
           if constexpr (sizeof(T) == 8) {
             // position x of the line was read above by this thread only
             if (a.fwd_fused) buf[x] = to_cpx<T>(us, vs);
+          } else {
+            keep_v[x] = vs;   // position x of keep_v was read above by this thread only
           }
         }
       }
       __syncthreads();   // the line is read before the next load overwrites it
     }
-    if constexpr (sizeof(T) == 8) {
-      if (a.fwd_fused) {
-        // the x forward pass of (u*, v*): FC along x, packed DFT, half spectra
-        for (int j = a.nx + lt; j < a.E; j += TL) {
-          const int i = fc_slot(a.fwd_fc, a.nx, a.E, j);
-          double ra = 0.0, rb = 0.0;
-          if (a.fwd_fc.on && i >= 0) {
-            ra = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)buf[q].r; });
-            rb = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return (double)buf[q].i; });
-          }
-          buf[j] = to_cpx<T>(ra, rb);
-        }
+    if (a.fwd_fused) {
+      // the FP64 x forward pass of (u*, v*): FC along x, packed DFT, half
+      // spectra (FP64 kernels: on buf itself, which holds (u*, v*) already;
+      // FP32 kernels: on an FP64 line over the finished FP32 one, filled from
+      // the arrays)
+      Line<double> b64{reinterpret_cast<cpx<double> *>(smem_raw)};
+      const LinePlan &plan64 = sizeof(T) == 8 ? a.plan : a.plan64;
+      if constexpr (sizeof(T) == 4) {
+        for (int x = lt; x < a.nx; x += TL) b64[x] = cpx<double>{keep_u[x], keep_v[x]};
         __syncthreads();
-        line_dft<T>(buf, a.plan, lt, TL, false, false);
-        cpx<T> *oa = static_cast<cpx<T> *>(a.fwd_out[0]) + (size_t)row * a.H;
-        cpx<T> *ob = static_cast<cpx<T> *>(a.fwd_out[1]) + (size_t)row * a.H;
-        const T half = T(0.5);
-        for (int k = lt; k < a.H; k += TL) {
-          const cpx<T> z = buf[k];
-          const cpx<T> zc = cconj(buf[k == 0 ? 0 : a.E - k]);
-          oa[k] = cscale(cadd(z, zc), half);
-          ob[k] = cscale(cmi(csub(z, zc)), half);
+      }
+      for (int j = a.nx + lt; j < a.E; j += TL) {
+        const int i = fc_slot(a.fwd_fc, a.nx, a.E, j);
+        double ra = 0.0, rb = 0.0;
+        if (a.fwd_fc.on && i >= 0) {
+          ra = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return b64[q].r; });
+          rb = fc_cont(a.fwd_fc, a.nx, i, [&](int q) { return b64[q].i; });
         }
+        b64[j] = cpx<double>{ra, rb};
+      }
+      __syncthreads();
+      line_dft<double>(b64, plan64, lt, TL, false, false);
+      cpx<double> *oa = static_cast<cpx<double> *>(a.fwd_out[0]) + (size_t)row * a.H;
+      cpx<double> *ob = static_cast<cpx<double> *>(a.fwd_out[1]) + (size_t)row * a.H;
+      for (int k = lt; k < a.H; k += TL) {
+        const cpx<double> z = b64[k];
+        const cpx<double> zc = cconj(b64[k == 0 ? 0 : a.E - k]);
+        oa[k] = cscale(cadd(z, zc), 0.5);
+        ob[k] = cscale(cmi(csub(z, zc)), 0.5);
       }
     }
   } else {
@@ -1312,10 +1322,12 @@ static hipError_t rows_inv_dispatch(const RowsInvArgs &a, int epi, hipStream_t s
       lds = lds_bytes(a.B, a.ldsM, sizeof(T) == 4);
       return rows_inv_t<T, EPI_ADVECT2>(a, grid, block, lds, s);
     case EPI_STEP_A2:
-      // one line group, one line and two real arrays of the row
+      // one line group, one FP64 line (the FP32 line and, in FP32 kernels,
+      // the fused FP64 forward pass's line) and two real arrays of the row
+      if (a.fwd_fused && sizeof(T) == 4 && (a.plan64.TL != TL || a.plan64.M != a.plan.M)) return hipErrorInvalidValue;
       grid = dim3(a.nrows);
       block = dim3(TL);
-      lds = lds_bytes(1, a.ldsM, sizeof(T) == 4) + 2 * (size_t)a.nx * sizeof(double);
+      lds = lds_bytes(1, a.ldsM, false) + 2 * (size_t)a.nx * sizeof(double);
       if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
       return rows_inv_t<T, EPI_STEP_A2>(a, grid, block, lds, s);
     case EPI_STEP_A3:
