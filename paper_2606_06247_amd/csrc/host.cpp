@@ -1113,7 +1113,10 @@ hipError_t x_fwd_single(fcsph_plan *p, const double *f, int fc, void *S) {
 }
 
 // x-pass forward of two fields with the same wall maps, packed row by row.
-hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc, void *S0, void *S1) {
+// edge0 / edge1 (FP32 2D plans): the FP64 boundary-row spectra of f0 / f1
+// (the column pass's FC_y inputs) come out of the same launch.
+hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc, void *S0, void *S1,
+                      void *edge0 = nullptr, void *edge1 = nullptr) {
   RowsFwdArgs a{};
   a.plan = p->op[0];
   const int rows = p->n[1] * p->n[2];
@@ -1131,6 +1134,13 @@ hipError_t x_fwd_pair(fcsph_plan *p, const double *f0, const double *f1, int fc,
   a.ostrideA = a.ostrideB = p->H;
   a.B = pick_B(a.plan, p->fp32, p->want_B);
   a.ldsM = padded_len(a.plan.M, a.plan.pad);
+  if (edge0) {
+    a.edge_rows = p->d.fc_d;
+    a.ny = p->n[1];
+    a.plan64 = p->op64[0];
+    a.edgeA = edge0;
+    a.edgeB = edge1;
+  }
   LaunchTimer t(p->ctx, "rows_fwd_pair");
   return launch_rows_fwd(a, p->fp32, p->ctx->stream);
 }
@@ -2221,9 +2231,21 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
     return FCSPH_OK;
   }
   // A: u* = u - dt [(u.grad)u - nu lap u - f], Dirichlet walls <- wall data
-  if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1]), "step A x", st)) return st;
   ColsArgs c = cols_base(p, COLS_OP, FCSPH_FIELD_VELOCITY);
-  if (!chk(p, set_edges(p, c, 2, u, FCSPH_FIELD_VELOCITY), "step A edges", st)) return st;
+  // FP32 plans: the FP64 boundary-row spectra (FC_y inputs) come out of the
+  // x pass itself
+  const bool edges_fused = p->fp32 && p->edge[0] && c.fc.on && c.line_axis == 1 && p->n[2] == 1;
+  if (!chk(p, x_fwd_pair(p, u[0], u[1], FCSPH_FIELD_VELOCITY, p->S[0], p->S[1],
+                         edges_fused ? p->edge[0] : nullptr, edges_fused ? p->edge[1] : nullptr),
+           "step A x", st))
+    return st;
+  if (edges_fused) {
+    c.edge[0] = (const double2 *)p->edge[0];
+    c.edge[1] = (const double2 *)p->edge[1];
+    c.edge[2] = nullptr;
+  } else if (!chk(p, set_edges(p, c, 2, u, FCSPH_FIELD_VELOCITY), "step A edges", st)) {
+    return st;
+  }
   c.in[0] = p->S[0];
   c.in[1] = p->S[1];
   c.out[0][0] = p->O[0];

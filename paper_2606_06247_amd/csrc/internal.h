@@ -134,6 +134,15 @@ struct RowsFwdArgs {
   // field + (r / map_per) * map_plane + (r % map_per) * nx (boundary-row blocks)
   int map_per;
   long map_plane;
+  // edge_rows = d > 0 (FP32 kernels, 2D, line l = row l of inA and of inB):
+  // the lines of rows y < d and y >= ny - d also run an FP64 pass with
+  // plan64 (the FP64 plan of the same length) into the FP64 boundary-row
+  // spectra edgeA, edgeB (row e = y, or d + y - (ny - d); pitch H), the
+  // inputs of FC_y in the column pass, as a separate FP64 edge launch would
+  int edge_rows;
+  int ny;
+  LinePlan plan64;
+  void *edgeA, *edgeB;
 };
 
 enum RowsEpi {

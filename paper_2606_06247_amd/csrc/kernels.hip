@@ -87,15 +87,54 @@ __global__ void __launch_bounds__(kMaxThreads) k_rows_fwd(KArg<RowsFwdArgs, G> k
   }
   __syncthreads();
   line_dft<T>(buf, a.plan, lt, TL, false, false);
-  if (!active) return;
-  cpx<T> *oa = static_cast<cpx<T> *>(a.outA) + (size_t)line * a.ostrideA;
-  cpx<T> *ob = pb ? static_cast<cpx<T> *>(a.outB) + (size_t)line * a.ostrideB : nullptr;
-  const T half = T(0.5);
-  for (int k = lt; k < a.H; k += TL) {
-    const cpx<T> z = buf[k];
-    const cpx<T> zc = cconj(buf[k == 0 ? 0 : a.E - k]);
-    oa[k] = cscale(cadd(z, zc), half);
-    if (ob) ob[k] = cscale(cmi(csub(z, zc)), half);
+  if (active) {
+    cpx<T> *oa = static_cast<cpx<T> *>(a.outA) + (size_t)line * a.ostrideA;
+    cpx<T> *ob = pb ? static_cast<cpx<T> *>(a.outB) + (size_t)line * a.ostrideB : nullptr;
+    const T half = T(0.5);
+    for (int k = lt; k < a.H; k += TL) {
+      const cpx<T> z = buf[k];
+      const cpx<T> zc = cconj(buf[k == 0 ? 0 : a.E - k]);
+      oa[k] = cscale(cadd(z, zc), half);
+      if (ob) ob[k] = cscale(cmi(csub(z, zc)), half);
+    }
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (a.edge_rows > 0) {
+      // FP64 spectra of the boundary rows: every line group of a workgroup
+      // that holds one runs the FP64 transform (the others inactive, through
+      // the same barriers), on FP64 lines laid over the finished FP32 ones
+      const int d = a.edge_rows;
+      const int l0 = blockIdx.x * a.B, l1 = min(l0 + a.B, a.nlines);
+      const bool wg_edge = l0 < d || l1 > a.ny - d;
+      if (wg_edge) {
+        const bool mine = active && (line < d || line >= a.ny - d);
+        Line<double> b64{reinterpret_cast<cpx<double> *>(smem_raw) + (size_t)g * a.ldsM};
+        __syncthreads();   // every group has read its FP32 line
+        if (mine) {
+          for (int j = lt; j < a.nx; j += TL) b64[j] = cpx<double>{pa[j], pb ? pb[j] : 0.0};
+          if (a.fc.on)
+            for (int j = a.nx + lt; j < a.E; j += TL) {
+              const int i = fc_slot(a.fc, a.nx, a.E, j);
+              const double ra = i >= 0 ? fc_cont(a.fc, a.nx, i, [&](int q) { return pa[q]; }) : 0.0;
+              const double rb = (pb && i >= 0) ? fc_cont(a.fc, a.nx, i, [&](int q) { return pb[q]; }) : 0.0;
+              b64[j] = cpx<double>{ra, rb};
+            }
+        }
+        __syncthreads();
+        line_dft<double>(b64, a.plan64, lt, TL, false, false, mine);
+        if (mine) {
+          const int e = line < d ? line : d + line - (a.ny - d);
+          cpx<double> *oa = static_cast<cpx<double> *>(a.edgeA) + (size_t)e * a.H;
+          cpx<double> *ob = pb ? static_cast<cpx<double> *>(a.edgeB) + (size_t)e * a.H : nullptr;
+          for (int k = lt; k < a.H; k += TL) {
+            const cpx<double> z = b64[k];
+            const cpx<double> zc = cconj(b64[k == 0 ? 0 : a.E - k]);
+            oa[k] = cscale(cadd(z, zc), 0.5);
+            if (ob) ob[k] = cscale(cmi(csub(z, zc)), 0.5);
+          }
+        }
+      }
+    }
   }
 }
 
@@ -1287,7 +1326,12 @@ static size_t lds_bytes(int B, int ldsM, bool fp32) {
 
 hipError_t launch_rows_fwd(const RowsFwdArgs &a, bool fp32, hipStream_t s) {
   const dim3 grid((a.nlines + a.B - 1) / a.B), block(a.B * a.plan.TL);
-  const size_t lds = lds_bytes(a.B, a.ldsM, fp32);
+  // the fused FP64 boundary-row pass of FP32 kernels lays FP64 lines over the FP32 ones
+  const bool edge = fp32 && a.edge_rows > 0;
+  if (edge && (a.plan64.TL != a.plan.TL || a.plan64.M != a.plan.M || a.map_per != 0 || !a.edgeA ||
+               (a.inB && !a.edgeB)))
+    return hipErrorInvalidValue;
+  const size_t lds = lds_bytes(a.B, a.ldsM, fp32 && !edge);
   if (fp32) return issue(k_rows_fwd<float, false>, k_rows_fwd<float, true>, a, grid, block, lds, s);
   return issue(k_rows_fwd<double, false>, k_rows_fwd<double, true>, a, grid, block, lds, s);
 }
