@@ -478,6 +478,40 @@ def test_fp32_project_step_2d(ctx, fc_tables, s, op_eval):
     assert max(errs) < tol32(op_eval), errs
 
 
+def test_fp32_step_lines_per_group_bitwise(ctx, fc_tables):
+    """The FP32 step's x pass computes the FP64 boundary-row spectra in the
+    workgroups that hold boundary rows, and its step-A epilogue runs the FP64
+    x pass of (u*, v*) on FP64 lines over its FP32 ones.  With several line
+    groups per workgroup (1, 2, 4; 72 x 65 rows: workgroups that mix wall and
+    interior rows, a ragged last workgroup) every line computes the same
+    values: the results are bitwise equal across the groupings and within the
+    FP32 gate of the FP64 oracle."""
+    import torch
+    from paper_2606_06247_amd import api
+    s = FP32_CASES[2]
+    u = [smooth2(s, 20), smooth2(s, 21)]
+    f = [smooth2(s, 22), smooth2(s, 23)]
+    w = [c.copy() for c in u]
+    dt, nu = 1e-4, 1e-3
+    ref_u, ref_p = step.project_step(lattice(s), fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
+    outs = []
+    for lines in (1, 2, 4):
+        prob = problem(s, precision="fp32", op_eval="fft_window")
+        prob.lines_per_group = lines
+        plan = api.Plan(ctx, prob)
+        ud = [to_dev(c) for c in u]
+        pd = torch.empty_like(ud[0])
+        plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
+        got = [to_np(ud[0]), to_np(ud[1]), to_np(pd)]
+        errs = [rel_l2(got[a], ref_u[a]) for a in range(2)] + [rel_l2(got[2], ref_p)]
+        print("fp32 step, lines per group", lines, [f"{e:.2e}" for e in errs])
+        assert max(errs) < TOL32, errs
+        outs.append(got)
+    for o in outs[1:]:
+        for a in range(3):
+            assert np.array_equal(o[a], outs[0][a])
+
+
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window"])
 def test_fp32_project_step_3d(ctx, fc_tables, op_eval):
     import torch
