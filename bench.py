@@ -686,6 +686,9 @@ def main() -> int:
                          "compact JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--only", choices=["fp32", "batch"], default=None,
+                    help="only run one secondary workload (the FP32-mixed 2D step, or the FP64 batch of "
+                         "--batch lattices) and print its record: a profiling entry point, not the bench line")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -698,6 +701,23 @@ def main() -> int:
     if args.gpus != 1:
         print("bench.py: the library runs one lattice per GPU in one process; --gpus must be 1 (there is no multi-GPU path)", file=sys.stderr)
         return 2
+    if args.only:
+        from paper_2606_06247_amd import api as _api, tune
+        tctx = _api.Context(0)
+        if args.only == "fp32":
+            sched = None if args.no_tune else tune.tune_2d(tctx, args.n, "fp32", lines=(1, 2, 4))
+            v = run_2d(args.op_eval, args.n, args.steps, args.warmup, precision="fp32", schedule=sched)
+            print(json.dumps({"workload": f"2d_{args.n}_fp32_{args.op_eval}", "value": v["value"], "unit": "Mpts/s",
+                              "ms_per_step": v["ms_per_step"], "schedule": sched, "roofline": v["roofline"]}))
+        else:
+            sched = {} if args.no_tune else {nb: tune.tune_2d(tctx, nb, "fp64", lines=(1, 2), batch=TUNE_BATCH)
+                                             for nb in BATCH_SIZES}
+            rec, _ = run_batch(args.batch, "fp64", max(1, min(args.steps, 20)), sched)
+            print(json.dumps({"workload": f"batch_{args.batch}_fp64", "solves_per_s": rec["solves_per_s"],
+                              "ms_per_batch_step": rec["ms_per_batch_step"], "groups": rec["groups"],
+                              "grouped_launches": rec["grouped_launches"],
+                              "batched_equals_plain_bitwise": rec["batched_equals_plain_bitwise"]}))
+        return 0
     n = args.n
     from paper_2606_06247_amd import api as _api, tune
     sched64 = sched32 = None
