@@ -2143,8 +2143,13 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
     r.H = p->H;
     r.B = 1;
     r.ldsM = padded_len(r.plan.M, r.plan.pad);
-    const int order[12] = {0, 1, 2, 4, 5, 6, 8, 9, 10, 3, 7, 11};
-    for (int k = 0; k < 12; ++k) r.spec[k] = p->O[order[k]];
+    // rows of at most 4 line-group widths: one line group takes the six lines
+    // in turn, paired (Gx, Gy), (Gz, L) per component; otherwise the lines
+    // are spread over the workgroup's line groups
+    const bool seq = r.nx <= 4 * r.plan.TL;
+    const int order_seq[12] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
+    const int order_par[12] = {0, 1, 2, 4, 5, 6, 8, 9, 10, 3, 7, 11};
+    for (int k = 0; k < 12; ++k) r.spec[k] = p->O[seq ? order_seq[k] : order_par[k]];
     r.spec_pitch = p->H;
     r.rpp = p->n[1];
     r.prow = p->E[1];
@@ -2162,7 +2167,7 @@ static fcsph_status step_impl(fcsph_plan *p, double *const *u, double *p_out, co
     r.wi = wall_info(p);
     {
       LaunchTimer t(p->ctx, "rows_inv_step_a3");
-      if (!chk(p, launch_rows_inv(r, EPI_STEP_A3, f32, s), "step3 A x inv", st)) return st;
+      if (!chk(p, launch_rows_inv(r, seq ? EPI_STEP_A3S : EPI_STEP_A3, f32, s), "step3 A x inv", st)) return st;
     }
     if (p->d.ppe_domain == FCSPH_PPE_EXTENDED) return project_extended(p, u, p_out, wall_vel, dt_proj);
     // B (FP64 transforms in both forms), C

@@ -151,7 +151,9 @@ enum RowsEpi {
   EPI_STEP_D2 = 2,     // 2D: projection from (Gx phi, Gy phi)
   EPI_STEP_A3 = 3,     // 3D: u* from 12 derivatives in 6 packed lines
   EPI_STEP_D3 = 4,     // 3D: projection from 3 gradients in 2 packed lines
-  EPI_ADVECT2 = 5      // 2D: RK3 sub-step of linear advection from (Gx u, Gy u)
+  EPI_ADVECT2 = 5,     // 2D: RK3 sub-step of linear advection from (Gx u, Gy u)
+  EPI_STEP_A3S = 6     // 3D: u* from 12 derivatives, one line group taking the
+                       // 6 packed lines in turn (rows of at most 4 TL points)
 };
 
 struct WallInfo {

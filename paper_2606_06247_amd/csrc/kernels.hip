@@ -359,6 +359,67 @@ k_rows_inv(KArg<RowsInvArgs, GR> ka) {
         ob[k] = cscale(cmi(csub(z, zc)), 0.5);
       }
     }
+  } else if constexpr (EPI == EPI_STEP_A3S) {
+    // One row per workgroup and one line group: the six packed lines (Gx u,
+    // Gy u), (Gz u, L u), (Gx v, Gy v), (Gz v, L v), (Gx w, Gy w), (Gz w, L w)
+    // (spec[2q], spec[2q + 1]) run in turn through one LDS line.  Each thread
+    // keeps its positions' u, v, w in registers (at most K positions:
+    // nx <= K TL) and the partial advection sum and the finished u*, v* in
+    // three real arrays after the line (its own positions only), so the
+    // workgroup is one wave; u* is stored after the last line.
+    constexpr int K = 4;
+    const int row = blockIdx.x;
+    const size_t ro_s = spec_row(a, row);
+    const size_t ro = (size_t)row * a.nx;
+    const int y = row % a.wi.n[1], z = row / a.wi.n[1];
+    double *acc = reinterpret_cast<double *>(smem + (size_t)a.ldsM);   // u d/dx + v d/dy
+    double *us = acc + a.nx, *vs = us + a.nx;                          // u*, v*
+    double uu[K], vv[K], ww[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int x = lt + k * TL;
+      const bool in = x < a.nx;
+      uu[k] = in ? a.u[0][ro + x] : 0.0;
+      vv[k] = in ? a.u[1][ro + x] : 0.0;
+      ww[k] = in ? a.u[2][ro + x] : 0.0;
+    }
+    const int lt0 = lt;
+#pragma unroll 1
+    for (int q = 0; q < 6; ++q) {
+      // a fresh copy of the lane index per line (no transform offsets hoisted
+      // out of this loop, as in the 2D epilogue)
+      int lt = lt0;
+      asm volatile("" : "+v"(lt));
+      load_packed_c2r<T, true>(buf, static_cast<const cpx<T> *>(a.spec[2 * q]) + ro_s,
+                               static_cast<const cpx<T> *>(a.spec[2 * q + 1]) + ro_s, a.E, a.H, lt, TL);
+      __syncthreads();
+      line_dft<T>(buf, a.plan, lt, TL, false, false);   // conjugated output: im = -.i
+      const int c = q >> 1;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int x = lt + k * TL;
+        if (x >= a.nx) continue;
+        const double re = (double)buf[x].r, im = (double)(-buf[x].i);
+        if ((q & 1) == 0) {
+          acc[x] = uu[k] * re + vv[k] * im;   // u d/dx + v d/dy of component c
+          continue;
+        }
+        const double self = c == 0 ? uu[k] : (c == 1 ? vv[k] : ww[k]);
+        const double f = a.f[c] ? a.f[c][ro + x] : 0.0;
+        double st = rk_ustar(a.rk, self, acc[x] + ww[k] * re, a.nu, im, f, a.dt, ro + x, c);
+        if (is_dirichlet_point(a.wi, x, y, z)) st = a.wall[c] ? a.wall[c][ro + x] : 0.0;
+        if (c == 0) {
+          us[x] = st;
+        } else if (c == 1) {
+          vs[x] = st;
+        } else {
+          a.ustar[0][ro + x] = us[x];
+          a.ustar[1][ro + x] = vs[x];
+          a.ustar[2][ro + x] = st;
+        }
+      }
+      __syncthreads();   // the line is read before the next load overwrites it
+    }
   } else {
     // One row per workgroup; NL packed lines, processed by the workgroup's
     // line groups in rounds (a group without a line in a round stays idle but
@@ -1374,6 +1435,15 @@ static hipError_t rows_inv_dispatch(const RowsInvArgs &a, int epi, hipStream_t s
       lds = lds_bytes(1, a.ldsM, false) + 2 * (size_t)a.nx * sizeof(double);
       if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
       return rows_inv_t<T, EPI_STEP_A2>(a, grid, block, lds, s);
+    case EPI_STEP_A3S:
+      // one line group, one line and three real arrays of the row; rows of at
+      // most 4 TL points
+      if (a.nx > 4 * TL) return hipErrorInvalidValue;
+      grid = dim3(a.nrows);
+      block = dim3(TL);
+      lds = lds_bytes(1, a.ldsM, sizeof(T) == 4) + 3 * (size_t)a.nx * sizeof(double);
+      if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+      return rows_inv_t<T, EPI_STEP_A3S>(a, grid, block, lds, s);
     case EPI_STEP_A3:
     case EPI_STEP_D3: {
       const int NL = epi == EPI_STEP_A3 ? 6 : 2;
