@@ -363,6 +363,32 @@ def test_ppe_solve_3d(ctx, s, eig):
 
 
 @pytest.mark.parametrize("op_eval", ["fft", "fft_window"])
+def test_project_step_3d_wide_rows(ctx, fc_tables, op_eval):
+    """Rows wider than four line-group widths (512 x-points, 64-thread line
+    groups) take the 3D step-A epilogue that spreads a row's six packed
+    lines over the workgroup's line groups; narrower rows take the one-group
+    form that the other 3D cases cover."""
+    import torch
+    from paper_2606_06247_amd import api
+    s = spec((512, 12, 6), (False, True, False))
+    plan = api.Plan(ctx, problem(s, op_eval=op_eval))
+    lat = lattice(s)
+    u = channel_fields(s, 44)
+    f = channel_fields(s, 46)
+    w = [c.copy() for c in u]
+    dt, nu = 1e-4, 1e-3
+    ud = [to_dev(c) for c in u]
+    pd = torch.empty_like(ud[0])
+    plan.project_step(ud, dt, nu, p_out=pd, force=[to_dev(c) for c in f], wall=[to_dev(c) for c in w])
+    ref_u, ref_p = step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu)
+    fft_u, fft_p = (step.project_step(lat, fc_tables, u, force=f, wall=w, dt=dt, nu=nu, opmode="fft")
+                    if op_eval == "fft" else ([None] * 3, None))
+    for a in range(3):
+        check(f"3D wide-row step u{a} {op_eval}", to_np(ud[a]), ref_u[a], gate(op_eval, ref_u[a], fft_u[a]))
+    check(f"3D wide-row step p {op_eval}", to_np(pd), ref_p, gate(op_eval, ref_p, fft_p))
+
+
+@pytest.mark.parametrize("op_eval", ["fft", "fft_window"])
 @pytest.mark.parametrize("s", CASES_3D, ids=lambda s: f"{s['n']}-{s['vel'][1]}-{s['prs'][1]}")
 def test_project_step_3d(ctx, fc_tables, s, op_eval):
     import torch
