@@ -1447,7 +1447,9 @@ static hipError_t rows_inv_dispatch(const RowsInvArgs &a, int epi, hipStream_t s
     case EPI_STEP_A3:
     case EPI_STEP_D3: {
       const int NL = epi == EPI_STEP_A3 ? 6 : 2;
-      const int G = std::max(1, std::min(NL, kMaxThreads / TL));
+      // step D (two lines): one line group taking them in turn (one-wave
+      // workgroups, twice as many rows resident as with a group per line)
+      const int G = epi == EPI_STEP_D3 ? 1 : std::max(1, std::min(NL, kMaxThreads / TL));
       grid = dim3(a.nrows);
       block = dim3(G * TL);
       lds = lds_bytes(NL, a.ldsM, sizeof(T) == 4);
