@@ -7,18 +7,11 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_served_results_equal_alone(precision):
+def assert_equal_alone(srv, reqs, precision):
+    """Every served output equals bitwise the plain call on a fresh plan with
+    the same inputs."""
     import torch
     from paper_2606_06247_amd import api, serve
-    reqs = serve.make_requests(lam=5000.0, count=40, seed=41, n2=(64, 160), n3=(32, 48))
-    srv = serve.Server(precision, max_batch=8, lanes=2)
-    srv.warm(sorted({(r.dims, r.n) for r in reqs}))
-    stats = srv.run(reqs, realtime=True, keep_outputs=True)
-    assert stats["requests"] == len(reqs)
-    assert stats["batches"] >= 2
-    assert all(np.isfinite(r.t_done) and r.t_done >= r.t_arrival for r in reqs)
-    # alone: a fresh plan, the same inputs, the plain call
     ctx = api.Context(0)
     for r in reqs:
         plan = api.Plan(ctx, serve.problem_for(r.dims, r.n, precision))
@@ -33,6 +26,32 @@ def test_served_results_equal_alone(precision):
         assert len(got) == len(ref)
         for g, f in zip(got, ref):
             assert torch.equal(g, f), (r.rid, r.kind, r.dims, r.n)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_served_results_equal_alone(precision):
+    from paper_2606_06247_amd import serve
+    reqs = serve.make_requests(lam=5000.0, count=40, seed=41, n2=(64, 160), n3=(32, 48))
+    srv = serve.Server(precision, max_batch=8, lanes=2)
+    srv.warm(sorted({(r.dims, r.n) for r in reqs}))
+    stats = srv.run(reqs, realtime=True, keep_outputs=True)
+    assert stats["requests"] == len(reqs)
+    assert stats["batches"] >= 2
+    assert all(np.isfinite(r.t_done) and r.t_done >= r.t_arrival for r in reqs)
+    assert_equal_alone(srv, reqs, precision)
+
+
+def test_lone_requests_take_the_plain_call():
+    """Requests that arrive one at a time run alone on their plan's lane as
+    the plain call (no grouped batch), with the same results."""
+    from paper_2606_06247_amd import serve
+    reqs = serve.make_requests(lam=100.0, count=6, seed=43, n2=(64, 96), n3=(32, 40))
+    srv = serve.Server("fp64", max_batch=8, lanes=2)
+    srv.warm(sorted({(r.dims, r.n) for r in reqs}))
+    stats = srv.run(reqs, realtime=True, keep_outputs=True)
+    assert stats["status"].get("ok", 0) == len(reqs)
+    assert srv.stats.get("plain_launches", 0) >= 1
+    assert_equal_alone(srv, reqs, "fp64")
 
 
 def test_admission_respects_budget():
